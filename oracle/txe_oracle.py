@@ -1,0 +1,264 @@
+"""CPU FP64 oracle for the Tucker-tensor Fock-exchange hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  The GPU library
+never calls it, shares no code with it, and must fail loudly rather than fall
+back to it.
+
+What it computes (Subramanian, Das & Gavini, arXiv 2401.04189, section
+"Algorithmic implementation"), plainly, in float64, one orbital pair at a
+time, in the order the paper gives the steps:
+
+  * O1  1-D convolution matrices of each Gaussian term on the 1-D FE mesh:
+        C_k[a,b] = int exp(-alpha_k (x_a - x')^2) N_b(x') dx'  with linear
+        hat functions N_b, i.e. the precomputed node sums of eqs. `quadVal` /
+        `discInteg` (interpolate to quadrature points, integrate against the
+        Gaussian with Jacobian x weight, swap the sums), here evaluated by
+        composite Gauss-Legendre quadrature.
+  * O2  Projection bases V_d = diag(q_d) U_d and core matrices
+        Chat_k^d = V_d^T C_k^d U_d.
+  * O3  Per pair (i, j): pair density rho = psi_i psi_j (section "Convolution
+        operation"), Tucker core G = rho x0 V0^T x1 V1^T x2 V2^T (eq.
+        `TuckerDecompField`, with bases shared by all pairs), core-space kernel
+        sum Phi = sum_k w_k G x0 Chat_k^0 x1 Chat_k^1 x2 Chat_k^2 (eqs. `gauss`
+        and `final`), reconstruction phi = Phi x0 U0 x1 U1 x2 U2, and the pair
+        energy e_ij = <G, Phi>_F = <rho, phi>_W.
+  * O4  Exchange action Vx psi_i = - sum_j psi_j phi_ij (eqs.
+        `ExchangeOperator`, `hadam`).
+  * O5  Exchange energy E_x = -1/2 sum_{i,j} e_ij (the exact-exchange term of
+        the functional S with the mixing fraction set to 1).
+  * O6  Gradient dE_x/dpsi_i = 2 w (Vx psi_i) with w the 3-D grid weights.
+
+Readings where the paper is silent (grid, boundary, element order, bases,
+where the convolution is evaluated) are listed in the design doc; they are the
+same for the oracle and the GPU path.  Parity of the Tucker-truncated
+(r < n) result against anything but this oracle is unpinned (no closed form
+exists for it); the full-rank case is pinned to a dense 3-D kernel apply.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# ---------------------------------------------------------------------------------------
+# O1: 1-D convolution matrices by composite Gauss-Legendre quadrature
+# ---------------------------------------------------------------------------------------
+_GL_ORDER = 12
+
+
+def _ghosted(x):
+    """Nodes with one ghost node added at each end, so that every real node
+    carries a full hat function (the end nodes of the extended mesh are held at
+    zero)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.concatenate([[2 * x[0] - x[1]], x, [2 * x[-1] - x[-2]]])
+
+
+def conv_matrix_1d(x, alpha, order=_GL_ORDER):
+    """C[a,b] = int exp(-alpha (x_a - t)^2) N_b(t) dt for linear hats N_b.
+
+    Each hat is split into its rising and falling linear pieces; each piece is
+    cut into m equal sub-intervals of width at most 1/(4 sqrt(alpha)) and
+    integrated with an `order`-point Gauss-Legendre rule."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    xg = _ghosted(x)
+    t_ref, w_ref = np.polynomial.legendre.leggauss(order)
+    C = np.zeros((n, n))
+    for b in range(n):
+        left, mid, right = xg[b], xg[b + 1], xg[b + 2]
+        for lo, hi, rising in ((left, mid, True), (mid, right, False)):
+            width = hi - lo
+            m = 1 if alpha <= 0 else max(1, int(math.ceil(width * 4.0 * math.sqrt(alpha))))
+            edges = lo + width * np.arange(m + 1) / m
+            a_ = edges[:-1, None]
+            b_ = edges[1:, None]
+            t = 0.5 * (b_ - a_) * t_ref[None, :] + 0.5 * (a_ + b_)          # (m, order)
+            wt = 0.5 * (b_ - a_) * w_ref[None, :]
+            hat = (t - lo) / width if rising else (hi - t) / width
+            t = t.reshape(-1)
+            wh = (wt * hat).reshape(-1)
+            C[:, b] += np.exp(-alpha * (x[:, None] - t[None, :]) ** 2) @ wh
+    return C
+
+
+def conv_matrices(x, alphas):
+    return np.stack([conv_matrix_1d(x, float(a)) for a in alphas])
+
+
+# ---------------------------------------------------------------------------------------
+# O2: projection bases and core matrices
+# ---------------------------------------------------------------------------------------
+class Setup:
+    """Per-system precomputation: V_d, C_k^d and Chat_k^d for d = 0, 1, 2."""
+
+    def __init__(self, x, q, U, w, alpha, C=None):
+        self.x = [np.asarray(v, dtype=np.float64) for v in x]
+        self.q = [np.asarray(v, dtype=np.float64) for v in q]
+        self.U = [np.asarray(u, dtype=np.float64) for u in U]
+        self.w = np.asarray(w, dtype=np.float64)
+        self.alpha = np.asarray(alpha, dtype=np.float64)
+        self.V = [self.q[d][:, None] * self.U[d] for d in range(3)]
+        if C is None:
+            cache = {}
+            C = []
+            for d in range(3):
+                key = self.x[d].tobytes()
+                if key not in cache:
+                    cache[key] = conv_matrices(self.x[d], self.alpha)
+                C.append(cache[key])
+        self.C = [np.asarray(c, dtype=np.float64) for c in C]
+        self.Chat = [np.einsum("ap,kab,bs->kps", self.V[d], self.C[d], self.U[d]) for d in range(3)]
+
+    @classmethod
+    def from_system(cls, sysm):
+        return cls(sysm.grid.x, sysm.grid.q, sysm.U, sysm.w, sysm.alpha)
+
+
+# ---------------------------------------------------------------------------------------
+# O3: one pair
+# ---------------------------------------------------------------------------------------
+def mode_product(T, M, d):
+    """(T x_d M)[.., i', ..] = sum_i M[i', i] T[.., i, ..]."""
+    return np.moveaxis(np.tensordot(M, T, axes=(1, d)), 0, d)
+
+
+def project(rho, V):
+    G = rho
+    for d in range(3):
+        G = mode_product(G, V[d].T, d)
+    return G
+
+
+def core_sum(G, w, Chat):
+    Phi = np.zeros_like(G)
+    for k in range(len(w)):
+        T = G
+        for d in range(3):
+            T = mode_product(T, Chat[d][k], d)
+        Phi += w[k] * T
+    return Phi
+
+
+def reconstruct(Phi, U):
+    phi = Phi
+    for d in range(3):
+        phi = mode_product(phi, U[d], d)
+    return phi
+
+
+def pair(psi_i, psi_j, st: Setup):
+    """(phi_ij, e_ij, G, Phi) for one pair."""
+    rho = psi_i * psi_j
+    G = project(rho, st.V)
+    Phi = core_sum(G, st.w, st.Chat)
+    phi = reconstruct(Phi, st.U)
+    e = float(np.sum(G * Phi))
+    return phi, e, G, Phi
+
+
+# ---------------------------------------------------------------------------------------
+# O4 / O5: exchange action and energy
+# ---------------------------------------------------------------------------------------
+def apply(psi, st: Setup, mode="symmetric", i0=0, Ni=None, want_vx=True, pairs_out=None):
+    """Vx psi and E_x.
+
+    mode="symmetric": all unique pairs i <= j of the N orbitals; each unique pair
+    feeds target i (times psi_j) and target j (times psi_i).  Returns Vx psi for
+    all N orbitals and E_x = -1/2 sum over all ordered pairs.
+
+    mode="block": targets i in [i0, i0+Ni) against all N sources; returns
+    Vx psi for the Ni targets and E_x = -1/2 sum_{i in block} sum_j e_ij.
+
+    When `pairs_out` is a dict it receives e_ij keyed by (i, j)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    N = psi.shape[0]
+    if mode == "symmetric":
+        targets = list(range(N))
+        vx = np.zeros_like(psi) if want_vx else None
+        ex = 0.0
+        for i in range(N):
+            for j in range(i, N):
+                phi, e, _, _ = pair(psi[i], psi[j], st)
+                if pairs_out is not None:
+                    pairs_out[(i, j)] = e
+                if want_vx:
+                    vx[i] -= psi[j] * phi
+                    if j != i:
+                        vx[j] -= psi[i] * phi
+                ex += -0.5 * e if i == j else -e
+        return vx, ex
+    Ni = N - i0 if Ni is None else Ni
+    targets = list(range(i0, i0 + Ni))
+    vx = np.zeros((Ni,) + psi.shape[1:]) if want_vx else None
+    ex = 0.0
+    for t, i in enumerate(targets):
+        for j in range(N):
+            phi, e, _, _ = pair(psi[i], psi[j], st)
+            if pairs_out is not None:
+                pairs_out[(i, j)] = e
+            if want_vx:
+                vx[t] -= psi[j] * phi
+            ex += -0.5 * e
+    return vx, ex
+
+
+def apply_target(psi, st: Setup, i, sources=None):
+    """Vx psi_i for one target against the given sources (all by default)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    sources = range(psi.shape[0]) if sources is None else sources
+    out = np.zeros(psi.shape[1:])
+    for j in sources:
+        phi, _, _, _ = pair(psi[i], psi[j], st)
+        out -= psi[j] * phi
+    return out
+
+
+def pair_energy(psi, st: Setup, i, j):
+    return pair(np.asarray(psi[i], dtype=np.float64), np.asarray(psi[j], dtype=np.float64), st)[1]
+
+
+# ---------------------------------------------------------------------------------------
+# O6: gradient
+# ---------------------------------------------------------------------------------------
+def weights3d(q):
+    return q[0][:, None, None] * q[1][None, :, None] * q[2][None, None, :]
+
+
+def gradient(psi, st: Setup):
+    """dE_x/dpsi (raw grid values) = 2 w (Vx psi), symmetric mode over all orbitals."""
+    vx, _ = apply(psi, st, mode="symmetric")
+    return 2.0 * weights3d(st.q)[None] * vx
+
+
+def energy_change_one_orbital(psi, st: Setup, m, delta):
+    """E_x(psi with psi_m += delta) - E_x(psi), from the 2N-1 pairs that involve
+    orbital m only (all other pair energies are unchanged)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    N = psi.shape[0]
+    new = psi[m] + delta
+
+    def contrib(pm):
+        tot = 0.0
+        for j in range(N):
+            pj = pm if j == m else psi[j]
+            _, e, _, _ = pair(pm, pj, st)
+            tot += -0.5 * e if j == m else -e
+        return tot
+
+    return contrib(new) - contrib(psi[m])
+
+
+# ---------------------------------------------------------------------------------------
+# references used to pin the oracle (dense, brute force)
+# ---------------------------------------------------------------------------------------
+def dense_kernel_apply(rho, w, C):
+    """sum_k w_k (C_k^0 (x) C_k^1 (x) C_k^2) rho with the dense 3-D kernel matrix
+    formed explicitly (tiny grids only)."""
+    n = rho.shape
+    out = np.zeros(rho.size)
+    for k in range(len(w)):
+        A = np.kron(np.kron(C[0][k], C[1][k]), C[2][k])
+        out += w[k] * (A @ rho.reshape(-1))
+    return out.reshape(n)

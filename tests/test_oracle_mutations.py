@@ -1,0 +1,88 @@
+"""The pins in test_oracle_pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake in the oracle (on the CPU, by monkeypatching one
+of its steps) and checks that at least one of the pins then fails.
+"""
+import numpy as np
+import pytest
+
+import tests.test_oracle_pins as P
+from oracle import txe_oracle as O
+from paper_2401_04189_amd import workloads as W
+
+
+def _pins_fail():
+    """Run a cheap subset of the pins; True when any of them fails."""
+    checks = [
+        P.test_full_rank_equals_dense_kernel,
+        P.test_non_cubic_full_rank_equals_dense_kernel,
+        P.test_constant_kernel_limit,
+        P.test_single_gaussian_energy_converges_second_order,
+        lambda: P.test_conv_matrix_closed_form(30.0),
+    ]
+    s = W.small_system(n=10, L=5.0, N=3, r=6, K=6, seed=21)
+    st = O.Setup.from_system(s)
+    fixture = (s, st)
+    checks += [
+        lambda: P.test_exchange_matrix_symmetric_nsd_trace(fixture),
+        lambda: P.test_gradient_central_differences(fixture),
+    ]
+    for c in checks:
+        try:
+            c()
+        except (AssertionError, ValueError):
+            return True
+    return False
+
+
+def test_unmutated_oracle_passes():
+    assert not _pins_fail()
+
+
+def _mut_project_with_U(rho, V):          # forgets the quadrature weights
+    G = rho
+    for d in range(3):
+        G = O.mode_product(G, (V[d] / V[d].max() * 1.0).T, d)
+    return G
+
+
+def _mut_core_drop_last_term(G, w, Chat):
+    return _orig["core_sum"](G, w[:-1], [c[:-1] for c in Chat])
+
+
+def _mut_core_mode0_everywhere(G, w, Chat):
+    return _orig["core_sum"](G, w, [Chat[0], Chat[0][:, :Chat[1].shape[1], :Chat[1].shape[2]]
+                                    if Chat[0].shape[1] >= Chat[1].shape[1] else Chat[1], Chat[2]])
+
+
+def _swap(Phi, U):
+    phi = O.mode_product(Phi, U[1][:U[0].shape[0]] if U[1].shape[0] == U[0].shape[0] else U[0], 0)
+    phi = O.mode_product(phi, U[0][:U[1].shape[0]] if U[0].shape[0] == U[1].shape[0] else U[1], 1)
+    return O.mode_product(phi, U[2], 2)
+
+
+def _mut_conv_half_hat(x, alpha, order=12):
+    C = _orig["conv_matrix_1d"](x, alpha, order)
+    C[:, 0] *= 0.5                        # half hat at the first node
+    return C
+
+
+def _mut_pair_sign(psi_i, psi_j, st):
+    phi, e, G, Phi = _orig["pair"](psi_i, psi_j, st)
+    return -phi, e, G, Phi
+
+
+_orig = {"core_sum": O.core_sum, "conv_matrix_1d": O.conv_matrix_1d, "pair": O.pair}
+
+
+@pytest.mark.parametrize("name,fn", [
+    ("project", _mut_project_with_U),
+    ("core_sum", _mut_core_drop_last_term),
+    ("core_sum", _mut_core_mode0_everywhere),
+    ("reconstruct", _swap),
+    ("conv_matrix_1d", _mut_conv_half_hat),
+    ("pair", _mut_pair_sign),
+])
+def test_planted_mistake_is_caught(monkeypatch, name, fn):
+    monkeypatch.setattr(O, name, fn)
+    assert _pins_fail(), f"a planted mistake in oracle step {name} ({fn.__name__}) went unnoticed"
