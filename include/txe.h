@@ -1,0 +1,165 @@
+/*
+ * txe.h -- Tucker-tensor Fock exchange on MI355X (gfx950): C ABI.
+ *
+ * Computes, for real orbitals psi_i sampled on a tensor-product grid, the
+ * action of the Fock exchange operator and the exchange energy
+ *
+ *     (Vx psi_i)(r) = - sum_j psi_j(r) phi_ij(r),
+ *     phi_ij       ~= int psi_i(r') psi_j(r') / |r - r'| dr',
+ *     E_x          = -1/2 sum_{i,j} <psi_i psi_j, phi_ij>_W
+ *
+ * (Subramanian, Das & Gavini, arXiv 2401.04189: eq. `ExchangeOperator` and the
+ * exact-exchange term of the functional S in section "Preliminaries"; the
+ * convolution of eq. `conv` and the Hadamard sum of eq. `hadam` in section
+ * "Overview of the algorithm").  The convolution is evaluated the paper's way
+ * (section "Convolution operation"): each pair density psi_i psi_j is
+ * projected onto rank-r per-mode Tucker bases (eq. `TuckerDecompField`, here
+ * with bases U_d shared by every pair), 1/r is a sum of K separable Gaussians
+ * (eq. `gauss`), so the 3-D convolution is a weighted sum of tensor products
+ * of 1-D convolution matrices (eq. `final`), built once from the 1-D
+ * finite-element mesh (eqs. `quadVal`, `discInteg`).  The library evaluates
+ * the kernel sum in the Tucker core space and back-projects:
+ *
+ *     G_ij   = (psi_i psi_j) x0 V0^T x1 V1^T x2 V2^T,     V_d = diag(q_d) U_d
+ *     Phi_ij = sum_k w_k G_ij x0 Chat_k^0 x1 Chat_k^1 x2 Chat_k^2,
+ *              Chat_k^d = V_d^T C_k^d U_d
+ *     phi_ij = Phi_ij x0 U0 x1 U1 x2 U2,    e_ij = <G_ij, Phi_ij>_F
+ *
+ * with C_k^d[a,b] = int exp(-alpha_k (x_a - x')^2) N_b(x') dx' for the
+ * linear hat functions N_b of the 1-D mesh (every node has a full hat).
+ *
+ * Conventions
+ *   - Grid arrays are C-contiguous (n0, n1, n2): mode 0 is the slowest axis.
+ *     Orbital arrays are (N, n0, n1, n2), orbital-major ("band" layout: every
+ *     orbital is contiguous), as the paper's structured-mesh storage.
+ *   - All pointers marked "device" must be device memory (hipMalloc or a torch
+ *     CUDA tensor) on the context's device; "host" pointers are ordinary host
+ *     memory.  The caller owns every buffer it passes.
+ *   - Every function validates all of its arguments on the host before it
+ *     enqueues anything.  On any error nothing is enqueued, no output is
+ *     touched, and a status other than TXE_OK is returned; txe_last_error()
+ *     then describes the failure (thread-local text, valid until the next
+ *     call on the same thread).
+ *   - Device work is asynchronous on the context's stream; the host never
+ *     waits inside txe_apply.  Same inputs, same plan => bitwise-identical
+ *     outputs (no atomics; every reduction has a fixed order).
+ */
+#ifndef TXE_H
+#define TXE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TXE_ABI_VERSION 1
+
+typedef enum {
+  TXE_OK = 0,
+  TXE_ERR_ARG = 1,          /* bad pointer, value or flag                                   */
+  TXE_ERR_SHAPE = 2,        /* inconsistent sizes                                           */
+  TXE_ERR_NOMEM = 3,        /* device allocation failed or the workspace limit is exceeded  */
+  TXE_ERR_DEVICE = 4,       /* a HIP call failed (sticky on the context)                    */
+  TXE_ERR_UNSUPPORTED = 5,  /* valid request that this build does not implement             */
+  TXE_ERR_STATE = 6         /* call not allowed in the current state (e.g. would allocate   */
+                            /* while the stream is being captured)                          */
+} txe_status;
+
+/* Arithmetic of the mode products and kernel sums.  The 1-D convolution
+ * matrices and Chat_k^d are always built in FP64 and then rounded; the E_x
+ * reduction is always FP64. */
+typedef enum {
+  TXE_COMPUTE_F64 = 0,      /* FP64 MFMA                                                    */
+  TXE_COMPUTE_F32 = 1,      /* FP32 MFMA, FP32 accumulation                                 */
+  TXE_COMPUTE_BF16X3 = 2    /* bf16 hi+lo split operands, 3 products, FP32 accumulation     */
+} txe_compute;
+
+typedef enum { TXE_DTYPE_F64 = 0, TXE_DTYPE_F32 = 1 } txe_dtype;
+
+typedef struct txe_context txe_context;
+typedef struct txe_system txe_system;
+
+/* One exchange problem's fixed data (grid, bases, kernel).  All host arrays. */
+typedef struct {
+  int32_t n[3];             /* grid points per mode, each a multiple of 4, 4 <= n <= 512    */
+  const double *x[3];       /* host: n[d] 1-D nodes, uniformly spaced, strictly increasing  */
+  const double *q[3];       /* host: n[d] 1-D quadrature weights (> 0)                      */
+  int32_t r[3];             /* Tucker rank per mode, 1 <= r[d] <= min(n[d], 80)             */
+  const double *U[3];       /* host: n[d] x r[d], row-major; must satisfy                   */
+                            /*       U^T diag(q) U = I to 1e-10 (checked)                   */
+  int32_t K;                /* number of Gaussian terms, 1 <= K <= 256                      */
+  const double *w;          /* host: K weights w_k (finite)                                 */
+  const double *alpha;      /* host: K exponents alpha_k >= 0 (finite)                      */
+} txe_system_desc;
+
+/* Arguments of one apply. */
+typedef struct {
+  int32_t compute;          /* txe_compute                                                  */
+  int32_t dtype;            /* txe_dtype of psi and vxpsi (F64 compute requires F64)        */
+  int32_t N;                /* number of orbitals in psi                                    */
+  const void *psi;          /* device: N x n0 x n1 x n2                                     */
+  int32_t symmetric;        /* 1: all N(N+1)/2 unique pairs; targets = all N orbitals       */
+                            /*    (requires i0 = 0 and Ni = N)                              */
+                            /* 0: block mode, targets [i0, i0+Ni) against all N sources     */
+  int32_t i0, Ni;           /* target block                                                 */
+  void *vxpsi;              /* device: Ni x n0 x n1 x n2, overwritten; NULL = energy only   */
+  const double *out_scale;  /* device scalar s or NULL (s = 1): vxpsi = s * Vx psi          */
+  int32_t out_weighted;     /* 1: vxpsi additionally multiplied by w(r) = q0 q1 q2          */
+  double *ex;               /* device: one FP64, overwritten with E_x; NULL = skip          */
+  double *e_pairs;          /* device: per-pair energies e_ij (FP64) or NULL.  Symmetric:   */
+                            /* N(N+1)/2 entries, pair (i<=j) at i*N - i(i-1)/2 + (j-i);     */
+                            /* block: Ni*N entries, pair (i0+t, j) at t*N + j               */
+} txe_apply_args;
+
+/* ABI version (TXE_ABI_VERSION). */
+int32_t txe_abi_version(void);
+
+/* Static text for a status code. */
+const char *txe_status_string(int32_t status);
+
+/* Detail of the last failure on this thread ("" when none). */
+const char *txe_last_error(void);
+
+/* 1-D convolution matrix of one Gaussian term on a uniform linear-FE mesh,
+ * C[a*n + b] = int exp(-alpha (x_a - x')^2) N_b(x') dx' (paper eqs. `quadVal`,
+ * `discInteg`, with the node sum evaluated in closed form through erf /
+ * erfc / expm1).  Host only: needs no GPU.  x: host, n nodes; C_out: host,
+ * n*n doubles. */
+txe_status txe_conv_matrix_1d(int32_t n, const double *x, double alpha, double *C_out);
+
+/* Context: one device and one HIP stream (hipStream_t, may be NULL for the
+ * default stream).  The context owns a reusable device workspace. */
+txe_status txe_context_create(int32_t device, void *hip_stream, txe_context **out);
+txe_status txe_context_destroy(txe_context *ctx);
+/* Change the stream later work is enqueued on. */
+txe_status txe_context_set_stream(txe_context *ctx, void *hip_stream);
+/* Grow the workspace to at least `bytes` now (so that later applies allocate
+ * nothing).  A limit for tests: env TXE_TEST_MAX_WORKSPACE (bytes). */
+txe_status txe_workspace_reserve(txe_context *ctx, size_t bytes);
+
+/* System: validates the description (U orthonormality included), builds the
+ * FP64 tables C_k^d, V_d, Chat_k^d on the host, rounds them to every compute
+ * precision and uploads them.  Copies all host arrays; keeps no caller
+ * pointer.  Synchronises the context stream once (upload). */
+txe_status txe_system_create(txe_context *ctx, const txe_system_desc *desc, txe_system **out);
+txe_status txe_system_destroy(txe_system *sys);
+
+/* FP64 copies of the setup tables of one mode (tests): C_out (host, K*n*n,
+ * may be NULL) and Chat_out (host, K*r*r, row-major Chat_k[p][s], may be
+ * NULL). */
+txe_status txe_system_conv(const txe_system *sys, int32_t mode, double *C_out, double *Chat_out);
+
+/* Workspace bytes one apply with these arguments needs. */
+txe_status txe_workspace_query(txe_context *ctx, const txe_system *sys, const txe_apply_args *args,
+                               size_t *bytes);
+
+/* One exchange apply (Vx psi for the targets and/or E_x). */
+txe_status txe_apply(txe_context *ctx, const txe_system *sys, const txe_apply_args *args);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TXE_H */

@@ -1,0 +1,582 @@
+// C ABI of the Tucker-tensor exchange library: argument validation, FP64
+// setup tables, per-precision device tables, workspace and chunk planning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/txe.h"
+#include "txe_internal.h"
+
+using namespace txe;
+
+// ------------------------------------------------------------------------------------
+// error text
+// ------------------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static txe_status fail(txe_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+static txe_status ok() {
+  g_last_error.clear();
+  return TXE_OK;
+}
+
+struct txe_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  bool sticky = false;
+  std::string sticky_msg;
+};
+
+template <typename T>
+struct DevTables {
+  Tables<T> t{};
+  std::vector<void *> owned;
+};
+
+struct txe_system {
+  txe_context *ctx = nullptr;
+  int device = 0;
+  Dims D{};
+  int n[3], r[3], K;
+  std::vector<double> x[3], q[3], U[3], w, alpha;
+  std::vector<double> C[3];      // K x n x n
+  std::vector<double> Chat[3];   // K x r x r
+  DevTables<double> t64;
+  DevTables<float> t32;
+  double *qdev[3] = {nullptr, nullptr, nullptr};
+};
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(TXE_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------------------
+extern "C" int32_t txe_abi_version(void) { return TXE_ABI_VERSION; }
+
+extern "C" const char *txe_status_string(int32_t st) {
+  switch (st) {
+    case TXE_OK: return "ok";
+    case TXE_ERR_ARG: return "invalid argument";
+    case TXE_ERR_SHAPE: return "inconsistent shape";
+    case TXE_ERR_NOMEM: return "out of device memory or workspace limit";
+    case TXE_ERR_DEVICE: return "device error";
+    case TXE_ERR_UNSUPPORTED: return "unsupported";
+    case TXE_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+extern "C" const char *txe_last_error(void) { return g_last_error.c_str(); }
+
+static bool finite_all(const double *p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+static txe_status check_grid_1d(int n, const double *x, const char *what) {
+  if (!x) return fail(TXE_ERR_ARG, "%s: null node array", what);
+  if (!finite_all(x, n)) return fail(TXE_ERR_ARG, "%s: non-finite node", what);
+  const double h = x[1] - x[0];
+  if (!(h > 0)) return fail(TXE_ERR_ARG, "%s: nodes must be strictly increasing", what);
+  for (int i = 1; i < n; ++i) {
+    const double hi = x[i] - x[i - 1];
+    if (!(hi > 0)) return fail(TXE_ERR_ARG, "%s: nodes must be strictly increasing", what);
+    if (std::fabs(hi - h) > 1e-9 * std::fabs(h)) return fail(TXE_ERR_UNSUPPORTED, "%s: nodes must be uniformly spaced", what);
+  }
+  return TXE_OK;
+}
+
+extern "C" txe_status txe_conv_matrix_1d(int32_t n, const double *x, double alpha, double *C_out) {
+  if (n < 2 || n > 4096) return fail(TXE_ERR_SHAPE, "n = %d out of range [2, 4096]", n);
+  if (!C_out) return fail(TXE_ERR_ARG, "C_out is null");
+  txe_status st = check_grid_1d(n, x, "x");
+  if (st != TXE_OK) return st;
+  if (!std::isfinite(alpha) || alpha < 0) return fail(TXE_ERR_ARG, "alpha must be finite and >= 0");
+  conv_matrix_1d(n, x, alpha, C_out);
+  return ok();
+}
+
+// ------------------------------------------------------------------------------------
+// context
+// ------------------------------------------------------------------------------------
+extern "C" txe_status txe_context_create(int32_t device, void *hip_stream, txe_context **out) {
+  if (!out) return fail(TXE_ERR_ARG, "out is null");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(TXE_ERR_ARG, "device %d not in [0, %d)", device, ndev);
+  auto *c = new txe_context();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return ok();
+}
+
+extern "C" txe_status txe_context_destroy(txe_context *ctx) {
+  if (!ctx) return fail(TXE_ERR_ARG, "ctx is null");
+  if (ctx->ws) {
+    hipSetDevice(ctx->device);
+    hipFree(ctx->ws);
+  }
+  delete ctx;
+  return ok();
+}
+
+extern "C" txe_status txe_context_set_stream(txe_context *ctx, void *hip_stream) {
+  if (!ctx) return fail(TXE_ERR_ARG, "ctx is null");
+  ctx->stream = (hipStream_t)hip_stream;
+  return ok();
+}
+
+static size_t workspace_limit() {
+  const char *e = getenv("TXE_TEST_MAX_WORKSPACE");
+  if (e && *e) return (size_t)strtoull(e, nullptr, 10);
+  return (size_t)96 << 30;  // 96 GiB of the 288 GiB HBM
+}
+
+static txe_status ensure_workspace(txe_context *ctx, size_t bytes) {
+  if (bytes <= ctx->ws_bytes) return TXE_OK;
+  if (bytes > workspace_limit())
+    return fail(TXE_ERR_NOMEM, "workspace of %zu bytes exceeds the limit of %zu bytes", bytes, workspace_limit());
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(ctx->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(TXE_ERR_STATE, "workspace must grow to %zu bytes while the stream is captured; call "
+                               "txe_workspace_reserve first", bytes);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (ctx->ws) {
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TXE_ERR_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+  }
+  ctx->ws = p;
+  ctx->ws_bytes = bytes;
+  return TXE_OK;
+}
+
+extern "C" txe_status txe_workspace_reserve(txe_context *ctx, size_t bytes) {
+  if (!ctx) return fail(TXE_ERR_ARG, "ctx is null");
+  txe_status st = ensure_workspace(ctx, bytes);
+  return st == TXE_OK ? ok() : st;
+}
+
+// ------------------------------------------------------------------------------------
+// system
+// ------------------------------------------------------------------------------------
+template <typename T>
+static txe_status upload(DevTables<T> &dt, const std::vector<double> &src, T **dst, hipStream_t s) {
+  std::vector<T> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = (T)src[i];
+  void *p = nullptr;
+  HIP_TRY(hipMalloc(&p, std::max<size_t>(tmp.size(), 1) * sizeof(T)));
+  dt.owned.push_back(p);
+  HIP_TRY(hipMemcpyAsync(p, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *dst = (T *)p;
+  return TXE_OK;
+}
+
+// Build every table in FP64 with the layouts Tables<T> documents.
+struct HostTables {
+  std::vector<double> V2B, V1chain, V0K, C1B, C2chain, Ahat, U0chain, U2T, U1chain;
+};
+
+static void build_tables(const txe_system &S, HostTables &H) {
+  const Dims &D = S.D;
+  auto U = [&](int d, int i, int s) -> double { return S.U[d][(size_t)i * S.r[d] + s]; };
+  auto V = [&](int d, int i, int s) -> double { return S.q[d][i] * U(d, i, s); };
+  auto Ch = [&](int d, int k, int p, int s) -> double { return S.Chat[d][((size_t)k * S.r[d] + p) * S.r[d] + s]; };
+  // V2B[c][gamma]
+  H.V2B.assign((size_t)D.nc2 * D.rp2, 0.0);
+  for (int c = 0; c < D.n2; ++c)
+    for (int g = 0; g < D.r2; ++g) H.V2B[(size_t)c * D.rp2 + g] = V(2, c, g);
+  // V1chain[mt][mb][v][lane] = V1[b = 16mb+4lg+v][beta = 16mt+lr]
+  const int nbt = D.nb1 / 16;
+  H.V1chain.assign((size_t)D.MT1 * nbt * 256, 0.0);
+  for (int mt = 0; mt < D.MT1; ++mt)
+    for (int mb = 0; mb < nbt; ++mb)
+      for (int v = 0; v < 4; ++v)
+        for (int l = 0; l < 64; ++l) {
+          const int beta = 16 * mt + (l & 15), b = 16 * mb + 4 * (l >> 4) + v;
+          if (beta < D.r1 && b < D.n1) H.V1chain[(((size_t)mt * nbt + mb) * 4 + v) * 64 + l] = V(1, b, beta);
+        }
+  // V0K[a][alpha]
+  H.V0K.assign((size_t)D.n0 * D.rp0, 0.0);
+  for (int a = 0; a < D.n0; ++a)
+    for (int al = 0; al < D.r0; ++al) H.V0K[(size_t)a * D.rp0 + al] = V(0, a, al);
+  // C1B[k][beta][beta'] = Chat1_k[beta'][beta]
+  H.C1B.assign((size_t)D.Kp * D.rp1 * D.rp1, 0.0);
+  for (int k = 0; k < D.K; ++k)
+    for (int be = 0; be < D.r1; ++be)
+      for (int bp = 0; bp < D.r1; ++bp) H.C1B[((size_t)k * D.rp1 + be) * D.rp1 + bp] = Ch(1, k, bp, be);
+  // C2chain[k][mt'][mg][v][lane] = Chat2_k[gamma' = 16mt'+lr][gamma = 16mg+4lg+v]
+  H.C2chain.assign((size_t)D.Kp * D.MT2 * D.MT2 * 256, 0.0);
+  for (int k = 0; k < D.K; ++k)
+    for (int mtp = 0; mtp < D.MT2; ++mtp)
+      for (int mg = 0; mg < D.MT2; ++mg)
+        for (int v = 0; v < 4; ++v)
+          for (int l = 0; l < 64; ++l) {
+            const int gp = 16 * mtp + (l & 15), g = 16 * mg + 4 * (l >> 4) + v;
+            if (gp < D.r2 && g < D.r2)
+              H.C2chain[((((size_t)k * D.MT2 + mtp) * D.MT2 + mg) * 4 + v) * 64 + l] = Ch(2, k, gp, g);
+          }
+  // Ahat[alpha][k][alpha'] = w_k Chat0_k[alpha'][alpha]
+  H.Ahat.assign((size_t)D.r0 * D.Kp * D.rp0, 0.0);
+  for (int al = 0; al < D.r0; ++al)
+    for (int k = 0; k < D.K; ++k)
+      for (int ap = 0; ap < D.r0; ++ap) H.Ahat[((size_t)al * D.Kp + k) * D.rp0 + ap] = S.w[k] * Ch(0, k, ap, al);
+  // U0chain[ma][mt][v][lane] = U0[a = 16ma+lr][alpha' = 16mt+4lg+v]
+  const int nat = D.na0 / 16;
+  H.U0chain.assign((size_t)nat * D.MT0 * 256, 0.0);
+  for (int ma = 0; ma < nat; ++ma)
+    for (int mt = 0; mt < D.MT0; ++mt)
+      for (int v = 0; v < 4; ++v)
+        for (int l = 0; l < 64; ++l) {
+          const int a = 16 * ma + (l & 15), ap = 16 * mt + 4 * (l >> 4) + v;
+          if (a < D.n0 && ap < D.r0) H.U0chain[(((size_t)ma * D.MT0 + mt) * 4 + v) * 64 + l] = U(0, a, ap);
+        }
+  // U2T[gamma][c] = U2[c][gamma]
+  H.U2T.assign((size_t)D.rp2 * D.nc2, 0.0);
+  for (int g = 0; g < D.r2; ++g)
+    for (int c = 0; c < D.n2; ++c) H.U2T[(size_t)g * D.nc2 + c] = U(2, c, g);
+  // U1chain[mb][mbeta][v][lane] = U1[b = 16mb+lr][beta = 16mbeta+4lg+v]
+  H.U1chain.assign((size_t)nbt * D.MT1 * 256, 0.0);
+  for (int mb = 0; mb < nbt; ++mb)
+    for (int me = 0; me < D.MT1; ++me)
+      for (int v = 0; v < 4; ++v)
+        for (int l = 0; l < 64; ++l) {
+          const int b = 16 * mb + (l & 15), be = 16 * me + 4 * (l >> 4) + v;
+          if (b < D.n1 && be < D.r1) H.U1chain[(((size_t)mb * D.MT1 + me) * 4 + v) * 64 + l] = U(1, b, be);
+        }
+}
+
+template <typename T>
+static txe_status upload_tables(DevTables<T> &dt, const HostTables &H, hipStream_t s) {
+  txe_status st;
+  if ((st = upload(dt, H.V2B, &dt.t.V2B, s)) != TXE_OK) return st;
+  if ((st = upload(dt, H.V1chain, &dt.t.V1chain, s)) != TXE_OK) return st;
+  if ((st = upload(dt, H.V0K, &dt.t.V0K, s)) != TXE_OK) return st;
+  if ((st = upload(dt, H.C1B, &dt.t.C1B, s)) != TXE_OK) return st;
+  if ((st = upload(dt, H.C2chain, &dt.t.C2chain, s)) != TXE_OK) return st;
+  if ((st = upload(dt, H.Ahat, &dt.t.Ahat, s)) != TXE_OK) return st;
+  if ((st = upload(dt, H.U0chain, &dt.t.U0chain, s)) != TXE_OK) return st;
+  if ((st = upload(dt, H.U2T, &dt.t.U2T, s)) != TXE_OK) return st;
+  if ((st = upload(dt, H.U1chain, &dt.t.U1chain, s)) != TXE_OK) return st;
+  return TXE_OK;
+}
+
+template <typename T>
+static void free_tables(DevTables<T> &dt) {
+  for (void *p : dt.owned) hipFree(p);
+  dt.owned.clear();
+}
+
+extern "C" txe_status txe_system_destroy(txe_system *sys) {
+  if (!sys) return fail(TXE_ERR_ARG, "sys is null");
+  hipSetDevice(sys->device);
+  free_tables(sys->t64);
+  free_tables(sys->t32);
+  for (int d = 0; d < 3; ++d)
+    if (sys->qdev[d]) hipFree(sys->qdev[d]);
+  delete sys;
+  return ok();
+}
+
+extern "C" txe_status txe_system_create(txe_context *ctx, const txe_system_desc *desc, txe_system **out) {
+  if (!ctx || !desc || !out) return fail(TXE_ERR_ARG, "null argument");
+  for (int d = 0; d < 3; ++d) {
+    const int n = desc->n[d], r = desc->r[d];
+    if (n < 4 || n > 512 || n % 4 != 0) return fail(TXE_ERR_SHAPE, "n[%d] = %d must be a multiple of 4 in [4, 512]", d, n);
+    if (r < 1 || r > n || r > 16 * MAX_MT) return fail(TXE_ERR_SHAPE, "r[%d] = %d must be in [1, min(n, %d)]", d, r, 16 * MAX_MT);
+    char what[16];
+    snprintf(what, sizeof what, "x[%d]", d);
+    txe_status st = check_grid_1d(n, desc->x[d], what);
+    if (st != TXE_OK) return st;
+    if (!desc->q[d] || !desc->U[d]) return fail(TXE_ERR_ARG, "q[%d] or U[%d] is null", d, d);
+    if (!finite_all(desc->q[d], n)) return fail(TXE_ERR_ARG, "q[%d] has a non-finite entry", d);
+    for (int i = 0; i < n; ++i)
+      if (!(desc->q[d][i] > 0)) return fail(TXE_ERR_ARG, "q[%d][%d] must be > 0", d, i);
+    if (!finite_all(desc->U[d], (size_t)n * r)) return fail(TXE_ERR_ARG, "U[%d] has a non-finite entry", d);
+    // U^T diag(q) U = I
+    double worst = 0.0;
+    for (int s1 = 0; s1 < r; ++s1)
+      for (int s2 = 0; s2 < r; ++s2) {
+        long double acc = 0;
+        for (int i = 0; i < n; ++i)
+          acc += (long double)desc->q[d][i] * desc->U[d][(size_t)i * r + s1] * desc->U[d][(size_t)i * r + s2];
+        worst = std::max(worst, std::fabs((double)acc - (s1 == s2 ? 1.0 : 0.0)));
+      }
+    if (worst > 1e-10)
+      return fail(TXE_ERR_ARG, "U[%d] is not q-orthonormal (max |U^T diag(q) U - I| = %.3g)", d, worst);
+  }
+  if (desc->K < 1 || desc->K > 256) return fail(TXE_ERR_SHAPE, "K = %d must be in [1, 256]", desc->K);
+  if (!desc->w || !desc->alpha) return fail(TXE_ERR_ARG, "w or alpha is null");
+  if (!finite_all(desc->w, desc->K) || !finite_all(desc->alpha, desc->K))
+    return fail(TXE_ERR_ARG, "w and alpha must be finite");
+  for (int k = 0; k < desc->K; ++k)
+    if (desc->alpha[k] < 0) return fail(TXE_ERR_ARG, "alpha[%d] < 0", k);
+
+  auto *S = new txe_system();
+  S->ctx = ctx;
+  S->device = ctx->device;
+  S->K = desc->K;
+  for (int d = 0; d < 3; ++d) {
+    S->n[d] = desc->n[d];
+    S->r[d] = desc->r[d];
+    S->x[d].assign(desc->x[d], desc->x[d] + S->n[d]);
+    S->q[d].assign(desc->q[d], desc->q[d] + S->n[d]);
+    S->U[d].assign(desc->U[d], desc->U[d] + (size_t)S->n[d] * S->r[d]);
+  }
+  S->w.assign(desc->w, desc->w + S->K);
+  S->alpha.assign(desc->alpha, desc->alpha + S->K);
+  // FP64 setup: C_k^d and Chat_k^d
+  for (int d = 0; d < 3; ++d) {
+    const int n = S->n[d], r = S->r[d];
+    S->C[d].assign((size_t)S->K * n * n, 0.0);
+    S->Chat[d].assign((size_t)S->K * r * r, 0.0);
+    bool reused = false;
+    for (int e = 0; e < d && !reused; ++e)
+      if (S->x[e] == S->x[d]) {
+        S->C[d] = S->C[e];
+        reused = true;
+      }
+    for (int k = 0; k < S->K; ++k) {
+      if (!reused) conv_matrix_1d(n, S->x[d].data(), S->alpha[k], &S->C[d][(size_t)k * n * n]);
+      core_matrix(n, r, S->q[d].data(), S->U[d].data(), &S->C[d][(size_t)k * n * n], &S->Chat[d][(size_t)k * r * r]);
+    }
+  }
+  Dims &D = S->D;
+  D.n0 = S->n[0]; D.n1 = S->n[1]; D.n2 = S->n[2];
+  D.na0 = rup(D.n0, 16); D.nb1 = rup(D.n1, 16); D.nc2 = rup(D.n2, 16);
+  D.r0 = S->r[0]; D.r1 = S->r[1]; D.r2 = S->r[2];
+  D.rp0 = rup(D.r0, 16); D.rp1 = rup(D.r1, 16); D.rp2 = rup(D.r2, 16);
+  D.MT0 = D.rp0 / 16; D.MT1 = D.rp1 / 16; D.MT2 = D.rp2 / 16;
+  D.r1k = rup(D.r1, 4); D.r2k = rup(D.r2, 4);
+  D.K = S->K; D.Kp = rup(S->K, KCHUNK);
+
+  HostTables H;
+  build_tables(*S, H);
+  txe_status st;
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    delete S;
+    return fail(TXE_ERR_DEVICE, "hipSetDevice failed");
+  }
+  if ((st = upload_tables(S->t64, H, ctx->stream)) != TXE_OK || (st = upload_tables(S->t32, H, ctx->stream)) != TXE_OK) {
+    txe_system_destroy(S);
+    return st;
+  }
+  for (int d = 0; d < 3; ++d) {
+    void *p = nullptr;
+    if (hipMalloc(&p, S->n[d] * sizeof(double)) != hipSuccess ||
+        hipMemcpy(p, S->q[d].data(), S->n[d] * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      if (p) hipFree(p);
+      txe_system_destroy(S);
+      return fail(TXE_ERR_DEVICE, "upload of q failed");
+    }
+    S->qdev[d] = (double *)p;
+  }
+  *out = S;
+  return ok();
+}
+
+extern "C" txe_status txe_system_conv(const txe_system *sys, int32_t mode, double *C_out, double *Chat_out) {
+  if (!sys) return fail(TXE_ERR_ARG, "sys is null");
+  if (mode < 0 || mode > 2) return fail(TXE_ERR_ARG, "mode must be 0, 1 or 2");
+  if (C_out) memcpy(C_out, sys->C[mode].data(), sys->C[mode].size() * sizeof(double));
+  if (Chat_out) memcpy(Chat_out, sys->Chat[mode].data(), sys->Chat[mode].size() * sizeof(double));
+  return ok();
+}
+
+// ------------------------------------------------------------------------------------
+// apply
+// ------------------------------------------------------------------------------------
+struct Plan {
+  bool f64;
+  bool symmetric;
+  bool want_vx;
+  long long npairs;
+  int NGS;
+  int tchunk;          // targets per chunk (block mode)
+  long long Pmax;      // pairs per chunk
+  size_t elt;
+  size_t off_T2, off_G, off_S1, off_epart, off_epair, total;
+};
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+static void plan_sizes(const Dims &D, Plan &pl) {
+  const size_t P = (size_t)pl.Pmax;
+  const size_t perT2 = (size_t)D.n0 * D.rp1 * D.rp2;
+  const size_t perG = (size_t)D.rp0 * D.rp1 * D.rp2;
+  const size_t perS1 = pl.want_vx ? (size_t)D.n0 * D.rp2 * D.rp1 : 0;
+  size_t off = 0;
+  pl.off_T2 = off; off = align256(off + P * perT2 * pl.elt);
+  pl.off_G = off; off = align256(off + P * perG * pl.elt);
+  pl.off_S1 = off; off = align256(off + P * perS1 * pl.elt);
+  pl.off_epart = off; off = align256(off + P * D.MT1 * pl.NGS * sizeof(double));
+  pl.off_epair = off; off = align256(off + (size_t)pl.npairs * sizeof(double));
+  pl.total = off;
+}
+
+static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, Plan &pl) {
+  const Dims &D = sys->D;
+  pl.f64 = a->compute == TXE_COMPUTE_F64;
+  pl.symmetric = a->symmetric != 0;
+  pl.want_vx = a->vxpsi != nullptr;
+  pl.elt = pl.f64 ? sizeof(double) : sizeof(float);
+  pl.npairs = pl.symmetric ? (long long)a->N * (a->N + 1) / 2 : (long long)a->Ni * a->N;
+  const int mt = std::max(D.MT0, std::max(D.MT1, D.MT2));
+  const int ngw = core_ngw(pl.f64, mt);
+  pl.NGS = (D.r2 + 4 * ngw - 1) / (4 * ngw);
+  const size_t limit = workspace_limit();
+  if (pl.symmetric) {
+    pl.tchunk = a->N;
+    pl.Pmax = pl.npairs;
+    plan_sizes(D, pl);
+    if (pl.total > limit)
+      return fail(TXE_ERR_NOMEM, "symmetric apply needs %zu workspace bytes (limit %zu); use block mode", pl.total, limit);
+    return TXE_OK;
+  }
+  // block mode: largest target chunk that fits the limit
+  int tc = a->Ni;
+  while (true) {
+    pl.tchunk = tc;
+    pl.Pmax = (long long)tc * a->N;
+    plan_sizes(D, pl);
+    if (pl.total <= limit) break;
+    if (tc == 1) return fail(TXE_ERR_NOMEM, "one target needs %zu workspace bytes (limit %zu)", pl.total, limit);
+    tc = (tc + 1) / 2;
+  }
+  return TXE_OK;
+}
+
+static txe_status validate_args(const txe_context *ctx, const txe_system *sys, const txe_apply_args *a) {
+  if (!ctx || !sys || !a) return fail(TXE_ERR_ARG, "null argument");
+  if (sys->device != ctx->device) return fail(TXE_ERR_ARG, "system and context are on different devices");
+  if (a->compute != TXE_COMPUTE_F64 && a->compute != TXE_COMPUTE_F32 && a->compute != TXE_COMPUTE_BF16X3)
+    return fail(TXE_ERR_ARG, "unknown compute %d", a->compute);
+  if (a->compute == TXE_COMPUTE_BF16X3) return fail(TXE_ERR_UNSUPPORTED, "BF16X3 compute is not built yet");
+  if (a->dtype != TXE_DTYPE_F64 && a->dtype != TXE_DTYPE_F32) return fail(TXE_ERR_ARG, "unknown dtype %d", a->dtype);
+  if (a->compute == TXE_COMPUTE_F64 && a->dtype != TXE_DTYPE_F64)
+    return fail(TXE_ERR_ARG, "FP64 compute requires FP64 orbitals");
+  if (a->N < 1) return fail(TXE_ERR_SHAPE, "N = %d must be >= 1", a->N);
+  if (!a->psi) return fail(TXE_ERR_ARG, "psi is null");
+  if (a->symmetric != 0 && a->symmetric != 1) return fail(TXE_ERR_ARG, "symmetric must be 0 or 1");
+  if (a->symmetric) {
+    if (a->i0 != 0 || a->Ni != a->N) return fail(TXE_ERR_SHAPE, "symmetric mode requires i0 = 0 and Ni = N");
+  } else {
+    if (a->i0 < 0 || a->Ni < 1 || (long long)a->i0 + a->Ni > a->N)
+      return fail(TXE_ERR_SHAPE, "target block [%d, %d) not inside [0, %d)", a->i0, a->i0 + a->Ni, a->N);
+  }
+  if (a->out_weighted != 0 && a->out_weighted != 1) return fail(TXE_ERR_ARG, "out_weighted must be 0 or 1");
+  if (!a->vxpsi && !a->ex && !a->e_pairs) return fail(TXE_ERR_ARG, "nothing to compute (vxpsi, ex and e_pairs are null)");
+  const size_t elt = a->dtype == TXE_DTYPE_F64 ? 8 : 4;
+  const size_t grid = (size_t)sys->n[0] * sys->n[1] * sys->n[2];
+  if (a->vxpsi) {
+    const char *p0 = (const char *)a->psi, *p1 = p0 + (size_t)a->N * grid * elt;
+    const char *v0 = (const char *)a->vxpsi, *v1 = v0 + (size_t)a->Ni * grid * elt;
+    if (v0 < p1 && p0 < v1) return fail(TXE_ERR_ARG, "vxpsi overlaps psi");
+  }
+  if (((uintptr_t)a->psi % (4 * elt)) != 0) return fail(TXE_ERR_ARG, "psi must be %zu-byte aligned", 4 * elt);
+  if (a->vxpsi && ((uintptr_t)a->vxpsi % elt) != 0) return fail(TXE_ERR_ARG, "vxpsi is misaligned");
+  return TXE_OK;
+}
+
+extern "C" txe_status txe_workspace_query(txe_context *ctx, const txe_system *sys, const txe_apply_args *args,
+                                          size_t *bytes) {
+  if (!bytes) return fail(TXE_ERR_ARG, "bytes is null");
+  txe_status st = validate_args(ctx, sys, args);
+  if (st != TXE_OK) return st;
+  Plan pl;
+  if ((st = make_plan(sys, args, pl)) != TXE_OK) return st;
+  *bytes = pl.total;
+  return ok();
+}
+
+template <typename T>
+static ChunkArgs<T> chunk_args(const txe_system *sys, const txe_apply_args *a, const Plan &pl, char *ws) {
+  ChunkArgs<T> c{};
+  c.D = sys->D;
+  c.pm.symmetric = pl.symmetric ? 1 : 0;
+  c.pm.N = a->N;
+  c.pm.i0 = a->i0;
+  c.N = a->N;
+  c.NGS = pl.NGS;
+  c.psi = a->psi;
+  c.vx = a->vxpsi;
+  c.out_scale = a->out_scale;
+  c.weighted = a->out_weighted;
+  for (int d = 0; d < 3; ++d) c.qdev[d] = sys->qdev[d];
+  c.T2 = (T *)(ws + pl.off_T2);
+  c.G = (T *)(ws + pl.off_G);
+  c.S1 = (T *)(ws + pl.off_S1);
+  c.epart = (double *)(ws + pl.off_epart);
+  c.epair = (double *)(ws + pl.off_epair);
+  return c;
+}
+
+extern "C" txe_status txe_apply(txe_context *ctx, const txe_system *sys, const txe_apply_args *args) {
+  txe_status st = validate_args(ctx, sys, args);
+  if (st != TXE_OK) return st;
+  if (ctx->sticky) return fail(TXE_ERR_DEVICE, "context has a previous device error: %s", ctx->sticky_msg.c_str());
+  Plan pl;
+  if ((st = make_plan(sys, args, pl)) != TXE_OK) return st;
+  if ((st = ensure_workspace(ctx, pl.total)) != TXE_OK) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  char *ws = (char *)ctx->ws;
+  hipError_t e = hipSuccess;
+  const bool psi64 = args->dtype == TXE_DTYPE_F64;
+  const int nchunks = pl.symmetric ? 1 : (args->Ni + pl.tchunk - 1) / pl.tchunk;
+  for (int ci = 0; ci < nchunks && e == hipSuccess; ++ci) {
+    const int tb = pl.symmetric ? 0 : ci * pl.tchunk;
+    const int tcnt = pl.symmetric ? args->N : std::min(pl.tchunk, args->Ni - tb);
+    const long long p0 = pl.symmetric ? 0 : (long long)tb * args->N;
+    const int P = (int)(pl.symmetric ? pl.npairs : (long long)tcnt * args->N);
+    if (pl.f64) {
+      ChunkArgs<double> c = chunk_args<double>(sys, args, pl, ws);
+      c.pm.p0 = p0; c.P = P; c.t_begin = tb; c.t_count = tcnt;
+      e = run_chunk_f64(sys->t64.t, c, pl.want_vx, ctx->stream);
+    } else {
+      ChunkArgs<float> c = chunk_args<float>(sys, args, pl, ws);
+      c.pm.p0 = p0; c.P = P; c.t_begin = tb; c.t_count = tcnt;
+      e = run_chunk_f32(sys->t32.t, c, psi64, pl.want_vx, ctx->stream);
+    }
+  }
+  if (e == hipSuccess)
+    e = run_energy((const double *)(ws + pl.off_epair), pl.npairs, pl.symmetric ? 1 : 0, args->N, args->ex,
+                   args->e_pairs, ctx->stream);
+  if (e != hipSuccess) {
+    ctx->sticky = true;
+    ctx->sticky_msg = hipGetErrorString(e);
+    return fail(TXE_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  }
+  return ok();
+}

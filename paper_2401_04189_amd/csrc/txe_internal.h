@@ -1,0 +1,90 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace txe {
+
+// ---- FP64 host setup (txe_setup.cpp) ------------------------------------------------
+void conv_matrix_1d(int n, const double *x, double alpha, double *C);
+void core_matrix(int n, int r, const double *q, const double *U, const double *C, double *Chat);
+
+inline int rup(int v, int m) { return (v + m - 1) / m * m; }
+
+constexpr int KCHUNK = 8;     // Gaussian terms staged per LDS round in the core kernel
+constexpr int MAX_MT = 5;     // rank tiles of 16: r <= 80
+
+// Sizes of one system, with the paddings the kernels use.
+struct Dims {
+  int n0, n1, n2;             // grid points per mode (multiples of 4)
+  int na0, nb1, nc2;          // n rounded up to 16
+  int r0, r1, r2;             // Tucker ranks
+  int rp0, rp1, rp2;          // ranks rounded up to 16
+  int MT0, MT1, MT2;          // rp / 16
+  int r1k, r2k;               // ranks rounded up to 4
+  int K, Kp;                  // Gaussian terms, and K rounded up to KCHUNK
+};
+
+// Pair enumeration: symmetric mode numbers the unique pairs i <= j row by
+// row (pair (i,j) at i*N - i(i-1)/2 + (j-i)); block mode numbers target
+// t (orbital i0+t) against source j at t*N + j.
+struct PairMap {
+  int symmetric;
+  int N;
+  int i0;
+  long long p0;               // global index of the chunk's first pair
+};
+
+// Device copies of the setup tables in one compute precision.  Every table
+// is zero beyond the true sizes, so padded rows and columns contribute zero.
+// "chain" tables hold the A operand of an MFMA whose B operand is the
+// accumulator of the previous MFMA, permuted to the accumulator's row order:
+// entry [..][v][lane] is M[16*m + lane%16][16*kt + 4*(lane/16) + v].
+template <typename T>
+struct Tables {
+  T *V2B;       // [nc2][rp2]            V2[c][gamma]                    (q2 U2)
+  T *V1chain;   // [MT1][nb1/16][4][64]  V1[b][beta] as A[beta][b]
+  T *V0K;       // [n0][rp0]             V0[a][alpha]
+  T *C1B;       // [Kp][rp1][rp1]        Chat1_k[beta'][beta] at [k][beta][beta']
+  T *C2chain;   // [Kp][MT2][MT2][4][64] Chat2_k[gamma'][gamma]
+  T *Ahat;      // [r0][Kp][rp0]         w_k Chat0_k[alpha'][alpha] at [alpha][k][alpha']
+  T *U0chain;   // [na0/16][MT0][4][64]  U0[a][alpha']
+  T *U2T;       // [rp2][nc2]            U2[c][gamma] at [gamma][c]
+  T *U1chain;   // [nb1/16][MT1][4][64]  U1[b][beta]
+};
+
+// Everything one chunk of pairs needs.
+template <typename T>
+struct ChunkArgs {
+  Dims D;
+  PairMap pm;
+  int P;                      // pairs in the chunk
+  int N;                      // sources (all orbitals)
+  int t_begin, t_count;       // targets of the back-projection (local target indices)
+  int NGS;                    // gamma' splits in the core kernel
+  const void *psi;
+  void *vx;
+  const double *out_scale;
+  int weighted;
+  const double *qdev[3];
+  T *T2, *G, *S1;
+  double *epart;              // [P][MT1][NGS]
+  double *epair;              // all pairs of the apply, global index
+};
+
+// Runs one chunk (projection, core sum, back-projection, pair energies).
+// Returns hipSuccess or the first launch error.
+hipError_t run_chunk_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s);
+hipError_t run_chunk_f32(const Tables<float> &tb, const ChunkArgs<float> &a, bool psi_f64, bool want_vx,
+                         hipStream_t s);
+// E_x = sum_p c_p e_pair[p] (fixed order), and an optional copy of e_pair.
+hipError_t run_energy(const double *epair, long long npairs, int symmetric, int N, double *ex, double *e_out,
+                      hipStream_t s);
+
+// Core-kernel variant choice (register budget per precision).
+int core_ngw(bool f64, int mt);
+
+}  // namespace txe

@@ -1,0 +1,677 @@
+// HIP kernels for gfx950 (MI355X): the per-pair Tucker-tensor exchange path.
+//
+// One chunk of orbital pairs runs through four kernels:
+//   proj12  pair density rho = psi_i psi_j formed on load; T1 = rho x2 V2^T
+//           (mode-2 product) chained on the MFMA accumulators into
+//           T2 = T1 x1 V1^T (mode-1 product), one a-slab per wavefront
+//   proj3   G = T2 x0 V0^T (mode-0 product), batched GEMM
+//   core    Phi = sum_k w_k G x0 Chat0_k x1 Chat1_k x2 Chat2_k (the kernel
+//           sum in the Tucker core space, eqs. `gauss`, `final`), with
+//           e_ij = <G, Phi> and the first back-projection S1 = Phi x0 U0 in
+//           its epilogue
+//   back    phi = S1 x2 U2 x1 U1 (chained), Vx psi_t -= psi_s phi_ts summed
+//           over all sources s in registers (eq. `hadam`), no atomics
+// followed by a fixed-order FP64 reduction of the pair energies into E_x.
+//
+// All products use 16x16x4 MFMA tiles (f64 or f32) with 64-lane wavefronts.
+// Fragment layouts of a 16x16x4 MFMA for lane l (lr = l%16, lg = l/16):
+//   A[m][k]: m = lr, k = lg        B[k][n]: k = lg, n = lr
+//   D[m][n]: m = 4*lg + v, n = lr  (v = 0..3, the four accumulator entries)
+// so an accumulator whose rows are the next contraction index feeds the next
+// MFMA as its B operand directly, one entry v at a time ("chained").
+#include "txe_internal.h"
+
+namespace txe {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MF;
+template <>
+struct MF<double> {
+  typedef d4 acc;
+  static __device__ __forceinline__ acc mma(double a, double b, const acc &c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MF<float> {
+  typedef f4 acc;
+  static __device__ __forceinline__ acc mma(float a, float b, const acc &c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename A>
+__device__ __forceinline__ A zero4() {
+  A z;
+  z[0] = 0; z[1] = 0; z[2] = 0; z[3] = 0;
+  return z;
+}
+
+// four consecutive elements (16- or 32-byte aligned)
+__device__ __forceinline__ void load4(const double *p, double (&o)[4]) {
+  const d4 v = *reinterpret_cast<const d4 *>(p);
+  o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+}
+__device__ __forceinline__ void load4(const float *p, double (&o)[4]) {
+  const f4 v = *reinterpret_cast<const f4 *>(p);
+  o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+}
+
+__device__ __forceinline__ long long sym_start(long long i, long long N) { return i * N - i * (i - 1) / 2; }
+
+__device__ __forceinline__ void pair_ij(const PairMap &pm, long long pg, int &i, int &j) {
+  if (!pm.symmetric) {
+    i = pm.i0 + (int)(pg / pm.N);
+    j = (int)(pg % pm.N);
+    return;
+  }
+  const double Nd = (double)pm.N;
+  const double b = 2.0 * Nd + 1.0;
+  long long ii = (long long)floor((b - sqrt(b * b - 8.0 * (double)pg)) * 0.5);
+  if (ii < 0) ii = 0;
+  if (ii > pm.N - 1) ii = pm.N - 1;
+  while (ii > 0 && sym_start(ii, pm.N) > pg) --ii;
+  while (ii + 1 < pm.N && sym_start(ii + 1, pm.N) <= pg) ++ii;
+  i = (int)ii;
+  j = (int)(ii + (pg - sym_start(ii, pm.N)));
+}
+
+// -------------------------------------------------------------------------------------
+// proj12: T2[p][a][beta][gamma] = sum_b V1[b][beta] sum_c psi_i[a,b,c] psi_j[a,b,c] V2[c][gamma]
+// one wavefront per (pair, a-slab, group of GT gamma tiles)
+// -------------------------------------------------------------------------------------
+template <typename T, typename Tin, int GT>
+__global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dims D, PairMap pm, int P,
+                                                Tables<T> tb, T *__restrict__ T2) {
+  using M = MF<T>;
+  using acc = typename M::acc;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
+  const int ngg = (D.MT2 + GT - 1) / GT;
+  const long long item = (long long)blockIdx.x * 4 + wave;
+  if (item >= (long long)P * D.n0 * ngg) return;
+  const int gg = (int)(item % ngg);
+  const long long rest = item / ngg;
+  const int a = (int)(rest % D.n0);
+  const int p = (int)(rest / D.n0);
+  int i, j;
+  pair_ij(pm, pm.p0 + p, i, j);
+  const size_t plane = (size_t)D.n1 * D.n2;
+  const Tin *pi = psi + ((size_t)i * D.n0 + a) * plane;
+  const Tin *pj = psi + ((size_t)j * D.n0 + a) * plane;
+  const int g0 = gg * GT;
+
+  acc T2a[MAX_MT][GT];
+#pragma unroll
+  for (int mt = 0; mt < MAX_MT; ++mt)
+#pragma unroll
+    for (int gt = 0; gt < GT; ++gt) T2a[mt][gt] = zero4<acc>();
+
+  const int nbt = D.nb1 >> 4, nct = D.nc2 >> 4;
+  for (int mb = 0; mb < nbt; ++mb) {
+    acc T1[GT];
+#pragma unroll
+    for (int gt = 0; gt < GT; ++gt) T1[gt] = zero4<acc>();
+    const int b = 16 * mb + lr;
+    for (int J = 0; J < nct; ++J) {
+      const int c = 16 * J + 4 * lg;
+      double x[4] = {0.0, 0.0, 0.0, 0.0};
+      if (b < D.n1 && c < D.n2) {
+        double y[4];
+        load4(pi + (size_t)b * D.n2 + c, x);
+        load4(pj + (size_t)b * D.n2 + c, y);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] *= y[q];
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const T *vrow = tb.V2B + (size_t)(c + jj) * D.rp2 + 16 * g0 + lr;
+        const T rho = (T)x[jj];
+#pragma unroll
+        for (int gt = 0; gt < GT; ++gt)
+          if (g0 + gt < D.MT2) T1[gt] = M::mma(rho, vrow[16 * gt], T1[gt]);
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MAX_MT; ++mt) {
+      if (mt < D.MT1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const T af = tb.V1chain[(((size_t)mt * nbt + mb) * 4 + v) * 64 + lane];
+#pragma unroll
+          for (int gt = 0; gt < GT; ++gt)
+            if (g0 + gt < D.MT2) T2a[mt][gt] = M::mma(af, T1[gt][v], T2a[mt][gt]);
+        }
+      }
+    }
+  }
+  T *out = T2 + ((size_t)p * D.n0 + a) * D.rp1 * D.rp2;
+#pragma unroll
+  for (int mt = 0; mt < MAX_MT; ++mt) {
+    if (mt < D.MT1) {
+#pragma unroll
+      for (int gt = 0; gt < GT; ++gt) {
+        if (g0 + gt < D.MT2) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int beta = 16 * mt + 4 * lg + v;
+            const int gamma = 16 * (g0 + gt) + lr;
+            out[(size_t)beta * D.rp2 + gamma] = T2a[mt][gt][v];
+          }
+        }
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------------------------------
+// proj3: G[p][alpha][f] = sum_a V0[a][alpha] T2[p][a][f], f = (beta, gamma)
+// one wavefront per (pair, group of FT f-tiles)
+// -------------------------------------------------------------------------------------
+template <typename T, int FT>
+__global__ __launch_bounds__(256) void k_proj3(const T *__restrict__ T2, Dims D, int P, Tables<T> tb,
+                                               T *__restrict__ G) {
+  using M = MF<T>;
+  using acc = typename M::acc;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
+  const int NF = (D.rp1 * D.rp2) >> 4;
+  const int nfg = (NF + FT - 1) / FT;
+  const long long item = (long long)blockIdx.x * 4 + wave;
+  if (item >= (long long)P * nfg) return;
+  const int fgi = (int)(item % nfg);
+  const int p = (int)(item / nfg);
+  const int f0 = fgi * FT;
+  const size_t F = (size_t)D.rp1 * D.rp2;
+  const T *B = T2 + (size_t)p * D.n0 * F;
+
+  acc C[MAX_MT][FT];
+#pragma unroll
+  for (int mt = 0; mt < MAX_MT; ++mt)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) C[mt][ft] = zero4<acc>();
+
+  for (int ka = 0; ka < (D.n0 >> 2); ++ka) {
+    const int arow = 4 * ka + lg;
+    T bf[FT];
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) bf[ft] = (f0 + ft < NF) ? B[(size_t)arow * F + 16 * (f0 + ft) + lr] : (T)0;
+#pragma unroll
+    for (int mt = 0; mt < MAX_MT; ++mt) {
+      if (mt < D.MT0) {
+        const T af = tb.V0K[(size_t)arow * D.rp0 + 16 * mt + lr];
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) C[mt][ft] = M::mma(af, bf[ft], C[mt][ft]);
+      }
+    }
+  }
+  T *out = G + (size_t)p * D.rp0 * F;
+#pragma unroll
+  for (int mt = 0; mt < MAX_MT; ++mt) {
+    if (mt < D.MT0) {
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) {
+        if (f0 + ft < NF) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) out[(size_t)(16 * mt + 4 * lg + v) * F + 16 * (f0 + ft) + lr] = C[mt][ft][v];
+        }
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------------------------------
+// core: per workgroup one pair p, one 16-wide tile bt of beta' and a range of
+// gamma' (split gs of NGS).  For each input slab alpha and each chunk of
+// KCHUNK Gaussian terms:
+//   phase A (each wavefront: KCHUNK/4 terms)
+//     W[gamma][beta']  = sum_beta G[alpha][beta][gamma] Chat1_k[beta'][beta]
+//     Z[gamma'][beta'] = sum_gamma Chat2_k[gamma'][gamma] W[gamma][beta']   (chained)
+//     Z -> LDS slot of term k
+//   phase B (each wavefront: its own gamma' rows, all alpha')
+//     Phi[alpha'][gamma'][beta'] += sum_k w_k Chat0_k[alpha'][alpha] Z_k[gamma'][beta']
+// i.e. the term sum is folded into the reduction dimension of the mode-0
+// product.  Phi stays in registers for the whole pair.
+// -------------------------------------------------------------------------------------
+template <typename T, int MT, int NGW, bool WRITE_S1>
+__global__ __launch_bounds__(256) void k_core(const T *__restrict__ G, Dims D, int P, int NGS, Tables<T> tb,
+                                              T *__restrict__ S1, double *__restrict__ epart) {
+  using M = MF<T>;
+  using acc = typename M::acc;
+  constexpr int KPW = KCHUNK / 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *Zs = reinterpret_cast<T *>(smem_raw);
+  __shared__ double red[4];
+
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
+  const int gs = blockIdx.x % NGS;
+  const int tt = blockIdx.x / NGS;
+  const int bt = tt % D.MT1;
+  const int p = tt / D.MT1;
+  if (p >= P) return;  // whole block leaves together
+
+  const int gper = (D.r2 + NGS - 1) / NGS;
+  const int g_lo = gs * gper;
+  const int g_hi = min(D.r2, g_lo + gper);
+  const int wg_lo = g_lo + wave * NGW;
+  const int wg_hi = min(g_hi, wg_lo + NGW);
+  const int mt_lo = g_lo >> 4, mt_hi = (g_hi - 1) >> 4;
+  const size_t F = (size_t)D.rp1 * D.rp2;
+  const T *Gp = G + (size_t)p * D.rp0 * F;
+
+  acc Phi[MT][NGW];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ng = 0; ng < NGW; ++ng) Phi[mt][ng] = zero4<acc>();
+
+  for (int alpha = 0; alpha < D.r0; ++alpha) {
+    const T *Ga = Gp + (size_t)alpha * F;
+    for (int kc0 = 0; kc0 < D.Kp; kc0 += KCHUNK) {
+      // ---- phase A
+#pragma unroll
+      for (int kk = 0; kk < KPW; ++kk) {
+        const int slot = wave * KPW + kk;
+        const int k = kc0 + slot;
+        T *zslot = Zs + (size_t)slot * gper * 16;
+        if (k < D.K) {
+          acc W[MT];
+#pragma unroll
+          for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
+          const T *C1k = tb.C1B + (size_t)k * D.rp1 * D.rp1 + 16 * bt + lr;
+          for (int kt = 0; kt < (D.r1k >> 2); ++kt) {
+            const int beta = 4 * kt + lg;
+            const T bf = C1k[(size_t)beta * D.rp1];
+            const T *grow = Ga + (size_t)beta * D.rp2 + lr;
+#pragma unroll
+            for (int mg = 0; mg < MT; ++mg)
+              if (mg < D.MT2) W[mg] = M::mma(grow[16 * mg], bf, W[mg]);
+          }
+          const T *C2k = tb.C2chain + (size_t)k * D.MT2 * D.MT2 * 256 + lane;
+          for (int mtp = mt_lo; mtp <= mt_hi; ++mtp) {
+            acc Z = zero4<acc>();
+#pragma unroll
+            for (int mg = 0; mg < MT; ++mg) {
+              if (mg < D.MT2) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Z = M::mma(C2k[((size_t)(mtp * D.MT2 + mg) * 4 + v) * 64], W[mg][v], Z);
+              }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int gp = 16 * mtp + 4 * lg + v;
+              if (gp >= g_lo && gp < g_hi) zslot[(gp - g_lo) * 16 + lr] = Z[v];
+            }
+          }
+        } else {
+          for (int idx = lane; idx < gper * 16; idx += 64) zslot[idx] = (T)0;
+        }
+      }
+      __syncthreads();
+      // ---- phase B
+#pragma unroll
+      for (int kt = 0; kt < KCHUNK / 4; ++kt) {
+        const int kq = 4 * kt + lg;
+        T af[MT];
+        const T *arow = tb.Ahat + ((size_t)alpha * D.Kp + kc0 + kq) * D.rp0 + lr;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) af[mt] = (mt < D.MT0) ? arow[16 * mt] : (T)0;
+        const T *zrow = Zs + (size_t)kq * gper * 16 + lr;
+#pragma unroll
+        for (int ng = 0; ng < NGW; ++ng) {
+          const int gp = wg_lo + ng;
+          if (gp < wg_hi) {
+            const T bz = zrow[(gp - g_lo) * 16];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+              if (mt < D.MT0) Phi[mt][ng] = M::mma(af[mt], bz, Phi[mt][ng]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- pair-energy partial: sum Phi[alpha'][gamma'][beta'] G[alpha'][beta'][gamma']
+  double e = 0.0;
+  const int bp = 16 * bt + lr;
+#pragma unroll
+  for (int ng = 0; ng < NGW; ++ng) {
+    const int gp = wg_lo + ng;
+    if (gp < wg_hi && bp < D.r1) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        if (mt < D.MT0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ap = 16 * mt + 4 * lg + v;
+            if (ap < D.r0) e += (double)Phi[mt][ng][v] * (double)Gp[((size_t)ap * D.rp1 + bp) * D.rp2 + gp];
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  if (lane == 0) red[wave] = e;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    epart[((size_t)p * D.MT1 + bt) * NGS + gs] = ((red[0] + red[1]) + (red[2] + red[3]));
+
+  // ---- S1[p][a][gamma'][beta'] = sum_alpha' U0[a][alpha'] Phi[alpha'][gamma'][beta']
+  if (WRITE_S1) {
+    const int nat = D.na0 >> 4;
+    for (int ma = 0; ma < nat; ++ma) {
+      T uf[MT][4];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          uf[mt][v] = (mt < D.MT0) ? tb.U0chain[(((size_t)ma * D.MT0 + mt) * 4 + v) * 64 + lane] : (T)0;
+#pragma unroll
+      for (int ng = 0; ng < NGW; ++ng) {
+        const int gp = wg_lo + ng;
+        if (gp < wg_hi) {
+          acc S = zero4<acc>();
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            if (mt < D.MT0) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) S = M::mma(uf[mt][v], Phi[mt][ng][v], S);
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int a = 16 * ma + 4 * lg + v;
+            if (a < D.n0) S1[(((size_t)p * D.n0 + a) * D.rp2 + gp) * D.rp1 + bp] = S[v];
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------------------------------
+// back: for target t, slab a and a group of NCG c-tiles, over all sources s:
+//   X[beta][c]  = sum_gamma S1[p(t,s)][a][gamma][beta] U2[c][gamma]
+//   phi[b][c]   = sum_beta U1[b][beta] X[beta][c]                      (chained)
+//   acc[b][c]  += psi_s[a][b][c] phi[b][c]
+// then Vx psi_t[a][b][c] = -scale * acc (times w(r) when weighted).
+// -------------------------------------------------------------------------------------
+template <typename T, typename Tin, int NBT, int NCG>
+__global__ __launch_bounds__(256) void k_back(const T *__restrict__ S1, const Tin *__restrict__ psi, Dims D,
+                                              PairMap pm, int N, int t_begin, int t_count, Tables<T> tb,
+                                              Tin *__restrict__ vx, const double *__restrict__ out_scale,
+                                              int weighted, const double *__restrict__ q0,
+                                              const double *__restrict__ q1, const double *__restrict__ q2) {
+  using M = MF<T>;
+  using acc = typename M::acc;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
+  const int nct = D.nc2 >> 4, nbt = D.nb1 >> 4;
+  const int ncg = (nct + NCG - 1) / NCG;
+  const long long item = (long long)blockIdx.x * 4 + wave;
+  if (item >= (long long)t_count * D.n0 * ncg) return;
+  const int cgi = (int)(item % ncg);
+  const long long rest = item / ncg;
+  const int a = (int)(rest % D.n0);
+  const int t = t_begin + (int)(rest / D.n0);          // local target index
+  const int tglob = pm.symmetric ? t : pm.i0 + t;      // orbital index of the target
+  const int c0 = cgi * NCG;
+  const size_t plane = (size_t)D.n1 * D.n2;
+  const size_t S1pair = (size_t)D.n0 * D.rp2 * D.rp1;
+
+  acc Acc[NBT][NCG];
+#pragma unroll
+  for (int mb = 0; mb < NBT; ++mb)
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) Acc[mb][cg] = zero4<acc>();
+
+  for (int s = 0; s < N; ++s) {
+    long long pg;
+    if (pm.symmetric) {
+      const int i = min(tglob, s), j = max(tglob, s);
+      pg = sym_start(i, pm.N) + (j - i);
+    } else {
+      pg = (long long)t * pm.N + s;
+    }
+    const T *S = S1 + (size_t)(pg - pm.p0) * S1pair + (size_t)a * D.rp2 * D.rp1 + lr;
+    acc X[MAX_MT][NCG];
+#pragma unroll
+    for (int mb = 0; mb < MAX_MT; ++mb)
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) X[mb][cg] = zero4<acc>();
+    for (int kt = 0; kt < (D.r2k >> 2); ++kt) {
+      const int gam = 4 * kt + lg;
+      const bool gv = gam < D.r2;
+      T bu[NCG];
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg)
+        bu[cg] = (gv && c0 + cg < nct) ? tb.U2T[(size_t)gam * D.nc2 + 16 * (c0 + cg) + lr] : (T)0;
+      const T *srow = S + (size_t)gam * D.rp1;
+#pragma unroll
+      for (int mb = 0; mb < MAX_MT; ++mb) {
+        if (mb < D.MT1) {
+          const T af = gv ? srow[16 * mb] : (T)0;
+#pragma unroll
+          for (int cg = 0; cg < NCG; ++cg) X[mb][cg] = M::mma(af, bu[cg], X[mb][cg]);
+        }
+      }
+    }
+    const Tin *ps = psi + (size_t)s * D.n0 * plane + (size_t)a * plane;
+#pragma unroll
+    for (int mbb = 0; mbb < NBT; ++mbb) {
+      if (mbb < nbt) {
+        acc ph[NCG];
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg) ph[cg] = zero4<acc>();
+#pragma unroll
+        for (int mbe = 0; mbe < MAX_MT; ++mbe) {
+          if (mbe < D.MT1) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const T af = tb.U1chain[(((size_t)mbb * D.MT1 + mbe) * 4 + v) * 64 + lane];
+#pragma unroll
+              for (int cg = 0; cg < NCG; ++cg) ph[cg] = M::mma(af, X[mbe][cg][v], ph[cg]);
+            }
+          }
+        }
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg) {
+          const int c = 16 * (c0 + cg) + lr;
+          if (c0 + cg < nct && c < D.n2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int b = 16 * mbb + 4 * lg + v;
+              if (b < D.n1) Acc[mbb][cg][v] += (T)ps[(size_t)b * D.n2 + c] * ph[cg][v];
+            }
+          }
+        }
+      }
+    }
+  }
+  const double scale = out_scale ? *out_scale : 1.0;
+  Tin *out = vx + (size_t)t * D.n0 * plane + (size_t)a * plane;
+#pragma unroll
+  for (int mbb = 0; mbb < NBT; ++mbb) {
+    if (mbb < nbt) {
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) {
+        const int c = 16 * (c0 + cg) + lr;
+        if (c0 + cg < nct && c < D.n2) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int b = 16 * mbb + 4 * lg + v;
+            if (b < D.n1) {
+              double val = -scale * (double)Acc[mbb][cg][v];
+              if (weighted) val *= q0[a] * q1[b] * q2[c];
+              out[(size_t)b * D.n2 + c] = (Tin)val;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------------------------------
+// pair energies: e_pair[p0 + p] = sum of the core kernel's partials (fixed order)
+// -------------------------------------------------------------------------------------
+__global__ void k_epair(const double *__restrict__ epart, int P, int parts, long long p0, double *__restrict__ epair) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double s = 0.0;
+  for (int q = 0; q < parts; ++q) s += epart[(size_t)p * parts + q];
+  epair[p0 + p] = s;
+}
+
+// E_x = sum_p c_p e_pair[p]; c_p = -1/2 for ordered pairs (block mode) and
+// for diagonal unique pairs, -1 for off-diagonal unique pairs.  One block,
+// fixed summation order.
+__global__ __launch_bounds__(256) void k_energy(const double *__restrict__ epair, long long np, int symmetric, int N,
+                                                double *__restrict__ ex, double *__restrict__ e_out) {
+  __shared__ double part[256];
+  double s = 0.0;
+  for (long long pg = threadIdx.x; pg < np; pg += 256) {
+    const double e = epair[pg];
+    if (e_out) e_out[pg] = e;
+    double c = -0.5;
+    if (symmetric) {
+      // pair pg is diagonal when it is the first pair of its row
+      const double Nd = (double)N;
+      const double b = 2.0 * Nd + 1.0;
+      long long ii = (long long)floor((b - sqrt(b * b - 8.0 * (double)pg)) * 0.5);
+      if (ii < 0) ii = 0;
+      if (ii > N - 1) ii = N - 1;
+      while (ii > 0 && sym_start(ii, N) > pg) --ii;
+      while (ii + 1 < N && sym_start(ii + 1, N) <= pg) ++ii;
+      c = (sym_start(ii, N) == pg) ? -0.5 : -1.0;
+    }
+    s += c * e;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && ex) *ex = part[0];
+}
+
+// -------------------------------------------------------------------------------------
+// host launchers
+// -------------------------------------------------------------------------------------
+namespace {
+
+inline unsigned blocks_for(long long waves) { return (unsigned)((waves + 3) / 4); }
+
+template <typename T, int MT, int NGW>
+hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
+  const int gper = (a.D.r2 + a.NGS - 1) / a.NGS;
+  const size_t lds = (size_t)KCHUNK * gper * 16 * sizeof(T);
+  const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
+  if (want_vx)
+    hipLaunchKernelGGL((k_core<T, MT, NGW, true>), dim3(nb), dim3(256), lds, s, a.G, a.D, a.P, a.NGS, tb, a.S1,
+                       a.epart);
+  else
+    hipLaunchKernelGGL((k_core<T, MT, NGW, false>), dim3(nb), dim3(256), lds, s, a.G, a.D, a.P, a.NGS, tb, a.S1,
+                       a.epart);
+  return hipGetLastError();
+}
+
+// register budget of the Phi accumulators: MT * NGW * 4 values per lane
+constexpr int NGW64[MAX_MT + 1] = {0, 16, 12, 10, 8, 6};
+constexpr int NGW32[MAX_MT + 1] = {0, 16, 16, 16, 12, 10};
+
+template <typename T>
+hipError_t launch_core(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
+  const int mt = max(a.D.MT0, max(a.D.MT1, a.D.MT2));
+  constexpr bool f64 = sizeof(T) == 8;
+  switch (mt) {
+    case 1: return launch_core_mt<T, 1, (f64 ? NGW64[1] : NGW32[1])>(tb, a, want_vx, s);
+    case 2: return launch_core_mt<T, 2, (f64 ? NGW64[2] : NGW32[2])>(tb, a, want_vx, s);
+    case 3: return launch_core_mt<T, 3, (f64 ? NGW64[3] : NGW32[3])>(tb, a, want_vx, s);
+    case 4: return launch_core_mt<T, 4, (f64 ? NGW64[4] : NGW32[4])>(tb, a, want_vx, s);
+    case 5: return launch_core_mt<T, 5, (f64 ? NGW64[5] : NGW32[5])>(tb, a, want_vx, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, typename Tin, int NCG>
+hipError_t launch_back_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  const int nct = a.D.nc2 >> 4, nbt = a.D.nb1 >> 4;
+  const long long waves = (long long)a.t_count * a.D.n0 * ((nct + NCG - 1) / NCG);
+  const unsigned nb = blocks_for(waves);
+  const Tin *psi = (const Tin *)a.psi;
+  Tin *vx = (Tin *)a.vx;
+#define TXE_BACK(NBTV)                                                                                     \
+  hipLaunchKernelGGL((k_back<T, Tin, NBTV, NCG>), dim3(nb), dim3(256), 0, s, a.S1, psi, a.D, a.pm, a.N,      \
+                     a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1], a.qdev[2])
+  if (nbt <= 2) TXE_BACK(2);
+  else if (nbt <= 4) TXE_BACK(4);
+  else if (nbt <= 6) TXE_BACK(6);
+  else if (nbt <= 8) TXE_BACK(8);
+  else return hipErrorInvalidValue;
+#undef TXE_BACK
+  return hipGetLastError();
+}
+
+template <typename T, typename Tin>
+hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  // two c-tiles per wavefront while the b-tile accumulators are few
+  if ((a.D.nb1 >> 4) <= 4) return launch_back_ncg<T, Tin, 2>(tb, a, s);
+  return launch_back_ncg<T, Tin, 1>(tb, a, s);
+}
+
+template <typename T, typename Tin>
+hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
+  constexpr int GT = 2, FT = 4;
+  hipError_t e;
+  {
+    const int ngg = (a.D.MT2 + GT - 1) / GT;
+    hipLaunchKernelGGL((k_proj12<T, Tin, GT>), dim3(blocks_for((long long)a.P * a.D.n0 * ngg)), dim3(256), 0, s,
+                       (const Tin *)a.psi, a.D, a.pm, a.P, tb, a.T2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  {
+    const int NF = (a.D.rp1 * a.D.rp2) >> 4;
+    const int nfg = (NF + FT - 1) / FT;
+    hipLaunchKernelGGL((k_proj3<T, FT>), dim3(blocks_for((long long)a.P * nfg)), dim3(256), 0, s, a.T2, a.D, a.P,
+                       tb, a.G);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = launch_core<T>(tb, a, want_vx, s)) != hipSuccess) return e;
+  {
+    const int parts = a.D.MT1 * a.NGS;
+    hipLaunchKernelGGL(k_epair, dim3((a.P + 255) / 256), dim3(256), 0, s, a.epart, a.P, parts, a.pm.p0, a.epair);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (want_vx) {
+    if ((e = launch_back<T, Tin>(tb, a, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+int core_ngw(bool f64, int mt) { return f64 ? NGW64[mt] : NGW32[mt]; }
+
+hipError_t run_chunk_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s) {
+  return run_chunk_t<double, double>(tb, a, want_vx, s);
+}
+
+hipError_t run_chunk_f32(const Tables<float> &tb, const ChunkArgs<float> &a, bool psi_f64, bool want_vx,
+                         hipStream_t s) {
+  if (psi_f64) return run_chunk_t<float, double>(tb, a, want_vx, s);
+  return run_chunk_t<float, float>(tb, a, want_vx, s);
+}
+
+hipError_t run_energy(const double *epair, long long npairs, int symmetric, int N, double *ex, double *e_out,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, s, epair, npairs, symmetric, N, ex, e_out);
+  return hipGetLastError();
+}
+
+}  // namespace txe

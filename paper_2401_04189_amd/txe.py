@@ -1,0 +1,262 @@
+"""ctypes binding of libtxe.so (the HIP/C++ Tucker-tensor exchange library).
+
+Argument marshalling only: every step of the exchange computation runs in the
+library's kernels.  torch supplies device memory (tensor data pointers) and
+the current HIP stream.  There is no fallback: if the library is missing or a
+call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtxe.so")
+
+COMPUTE = {"f64": 0, "f32": 1, "bf16x3": 2}
+DTYPE = {"f64": 0, "f32": 1}
+
+_c_int = ctypes.c_int32
+_c_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class SystemDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", _c_int * 3),
+        ("x", ctypes.c_void_p * 3),
+        ("q", ctypes.c_void_p * 3),
+        ("r", _c_int * 3),
+        ("U", ctypes.c_void_p * 3),
+        ("K", _c_int),
+        ("w", ctypes.c_void_p),
+        ("alpha", ctypes.c_void_p),
+    ]
+
+
+class ApplyArgs(ctypes.Structure):
+    _fields_ = [
+        ("compute", _c_int),
+        ("dtype", _c_int),
+        ("N", _c_int),
+        ("psi", ctypes.c_void_p),
+        ("symmetric", _c_int),
+        ("i0", _c_int),
+        ("Ni", _c_int),
+        ("vxpsi", ctypes.c_void_p),
+        ("out_scale", ctypes.c_void_p),
+        ("out_weighted", _c_int),
+        ("ex", ctypes.c_void_p),
+        ("e_pairs", ctypes.c_void_p),
+    ]
+
+
+# every symbol include/txe.h declares, with its ctypes signature
+SIGNATURES = {
+    "txe_abi_version": (_c_int, []),
+    "txe_status_string": (ctypes.c_char_p, [_c_int]),
+    "txe_last_error": (ctypes.c_char_p, []),
+    "txe_conv_matrix_1d": (_c_int, [_c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
+    "txe_context_create": (_c_int, [_c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "txe_context_destroy": (_c_int, [ctypes.c_void_p]),
+    "txe_context_set_stream": (_c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "txe_workspace_reserve": (_c_int, [ctypes.c_void_p, ctypes.c_size_t]),
+    "txe_system_create": (_c_int, [ctypes.c_void_p, ctypes.POINTER(SystemDesc), ctypes.POINTER(ctypes.c_void_p)]),
+    "txe_system_destroy": (_c_int, [ctypes.c_void_p]),
+    "txe_system_conv": (_c_int, [ctypes.c_void_p, _c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "txe_workspace_query": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs),
+                                     ctypes.POINTER(ctypes.c_size_t)]),
+    "txe_apply": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs)]),
+}
+
+_lib = None
+
+
+class TxeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"txe status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_04189_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        L = lib()
+        raise TxeError(st, f"{L.txe_status_string(st).decode()}: {L.txe_last_error().decode()}")
+
+
+def conv_matrix_1d(x, alpha):
+    """Host FP64 1-D convolution matrix of one Gaussian term (no GPU needed)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    C = np.empty((len(x), len(x)), dtype=np.float64)
+    _check(lib().txe_conv_matrix_1d(len(x), x.ctypes.data, float(alpha), C.ctypes.data))
+    return C
+
+
+def _stream_ptr(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Context:
+    def __init__(self, device=0, stream=None):
+        import torch
+
+        self.device = int(device)
+        torch.cuda.set_device(self.device)
+        h = ctypes.c_void_p()
+        _check(lib().txe_context_create(self.device, ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)))
+        self.h = h
+
+    def set_stream(self, stream):
+        _check(lib().txe_context_set_stream(self.h, ctypes.c_void_p(_stream_ptr(stream))))
+
+    def reserve(self, nbytes):
+        _check(lib().txe_workspace_reserve(self.h, int(nbytes)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().txe_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class System:
+    """Fixed data of one exchange problem: grid (x_d, q_d), bases U_d, (w_k, alpha_k)."""
+
+    def __init__(self, ctx: Context, x, q, U, w, alpha):
+        self.ctx = ctx
+        self._keep = []
+        d = SystemDesc()
+        for m in range(3):
+            xm = np.ascontiguousarray(x[m], dtype=np.float64)
+            qm = np.ascontiguousarray(q[m], dtype=np.float64)
+            Um = np.ascontiguousarray(U[m], dtype=np.float64)
+            self._keep += [xm, qm, Um]
+            d.n[m] = len(xm)
+            d.r[m] = Um.shape[1]
+            d.x[m] = xm.ctypes.data
+            d.q[m] = qm.ctypes.data
+            d.U[m] = Um.ctypes.data
+        wk = np.ascontiguousarray(w, dtype=np.float64)
+        ak = np.ascontiguousarray(alpha, dtype=np.float64)
+        self._keep += [wk, ak]
+        d.K = len(wk)
+        d.w = wk.ctypes.data
+        d.alpha = ak.ctypes.data
+        self.n = tuple(d.n)
+        self.r = tuple(d.r)
+        self.K = d.K
+        h = ctypes.c_void_p()
+        _check(lib().txe_system_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        self._keep = []
+
+    @classmethod
+    def from_workload(cls, ctx, s):
+        return cls(ctx, s.grid.x, s.grid.q, s.U, s.w, s.alpha)
+
+    def conv(self, mode):
+        """FP64 (C_k, Chat_k) tables of one mode, as built by the library."""
+        n, r = self.n[mode], self.r[mode]
+        C = np.empty((self.K, n, n))
+        Ch = np.empty((self.K, r, r))
+        _check(lib().txe_system_conv(self.h, mode, C.ctypes.data, Ch.ctypes.data))
+        return C, Ch
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().txe_system_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_args(psi, compute="f64", symmetric=True, i0=0, Ni=None, vx=None, ex=None, e_pairs=None,
+              out_scale=None, out_weighted=False):
+    import torch
+
+    a = ApplyArgs()
+    a.compute = COMPUTE[compute]
+    a.dtype = DTYPE["f64" if psi.dtype == torch.float64 else "f32"]
+    a.N = psi.shape[0]
+    a.psi = psi.data_ptr()
+    a.symmetric = 1 if symmetric else 0
+    a.i0 = 0 if symmetric else int(i0)
+    a.Ni = psi.shape[0] if symmetric else int(Ni)
+    a.vxpsi = vx.data_ptr() if vx is not None else None
+    a.out_scale = out_scale.data_ptr() if out_scale is not None else None
+    a.out_weighted = 1 if out_weighted else 0
+    a.ex = ex.data_ptr() if ex is not None else None
+    a.e_pairs = e_pairs.data_ptr() if e_pairs is not None else None
+    return a
+
+
+def apply(ctx: Context, sysm: System, psi, compute="f64", symmetric=True, i0=0, Ni=None, want_vx=True,
+          want_pairs=False, out_scale=None, out_weighted=False, vx_out=None):
+    """Vx psi (targets) and E_x for the orbitals `psi` (a CUDA tensor N x n0 x n1 x n2).
+
+    Returns (vx, ex, e_pairs): vx is None when want_vx is False; ex is a
+    0-d float64 CUDA tensor; e_pairs is None unless want_pairs."""
+    import torch
+
+    if not psi.is_cuda or not psi.is_contiguous():
+        raise ValueError("psi must be a contiguous CUDA tensor")
+    if tuple(psi.shape[1:]) != sysm.n:
+        raise ValueError(f"psi grid {tuple(psi.shape[1:])} does not match the system grid {sysm.n}")
+    N = psi.shape[0]
+    Ni = N if symmetric else (N - i0 if Ni is None else Ni)
+    vx = None
+    if want_vx:
+        vx = vx_out if vx_out is not None else torch.empty((Ni,) + tuple(psi.shape[1:]), dtype=psi.dtype,
+                                                             device=psi.device)
+    ex = torch.empty((), dtype=torch.float64, device=psi.device)
+    npairs = N * (N + 1) // 2 if symmetric else Ni * N
+    ep = torch.empty(npairs, dtype=torch.float64, device=psi.device) if want_pairs else None
+    a = make_args(psi, compute, symmetric, i0, Ni, vx, ex, ep, out_scale, out_weighted)
+    ctx.set_stream(torch.cuda.current_stream(psi.device))
+    _check(lib().txe_apply(ctx.h, sysm.h, ctypes.byref(a)))
+    return vx, ex, ep
+
+
+def workspace_bytes(ctx, sysm, psi, compute="f64", symmetric=True, i0=0, Ni=None, want_vx=True):
+    """Workspace bytes of one apply with these arguments (nothing is computed)."""
+    N = psi.shape[0]
+    Ni = N if symmetric else (N - i0 if Ni is None else Ni)
+    a = make_args(psi, compute, symmetric, i0, Ni)
+    # the query only inspects which outputs are requested; these addresses are
+    # placeholders that are never dereferenced
+    end = psi.data_ptr() + psi.numel() * psi.element_size()
+    a.ex = end
+    if want_vx:
+        a.vxpsi = end + 256
+    nb = ctypes.c_size_t()
+    _check(lib().txe_workspace_query(ctx.h, sysm.h, ctypes.byref(a), ctypes.byref(nb)))
+    return nb.value

@@ -1,0 +1,186 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle on
+the same seeded inputs.
+
+FP64 bar (both from the method's own tolerances): |dE_x|/|E_x| <= 1e-9 and
+max_i ||dVx psi_i||_W / ||Vx psi_i||_W <= 1e-9; pair energies e_ij to 1e-9
+of the largest.  FP32 MFMA: the same quantities against the GPU FP64 path,
+at |dE_x| <= 1e-5 Ha (the reduced-precision gate) and 1e-5 relative on Vx psi.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import txe_oracle as O
+from paper_2401_04189_amd import txe, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = txe.Context(0)
+    yield c
+    c.close()
+
+
+def wnorm(v, q):
+    w3 = O.weights3d(q)
+    return np.sqrt(np.einsum("i...,...->i", v * v, w3))
+
+
+def rel_vx_err(vx, ref, q):
+    return float((wnorm(vx - ref, q) / wnorm(ref, q)).max())
+
+
+def run_gpu(ctx, s, compute="f64", symmetric=True, i0=0, Ni=None, psi_dtype=torch.float64, **kw):
+    sysm = txe.System.from_workload(ctx, s)
+    psi = s.psi.to(device="cuda", dtype=psi_dtype).contiguous()
+    vx, ex, ep = txe.apply(ctx, sysm, psi, compute=compute, symmetric=symmetric, i0=i0, Ni=Ni,
+                           want_pairs=True, **kw)
+    torch.cuda.synchronize()
+    out = (None if vx is None else vx.double().cpu().numpy(), float(ex.item()), ep.cpu().numpy())
+    sysm.close()
+    return out
+
+
+def oracle_pairs_vector(pairs, N, symmetric, i0=0, Ni=None):
+    if symmetric:
+        return np.array([pairs[(i, j)] for i in range(N) for j in range(i, N)])
+    return np.array([pairs[(i0 + t, j)] for t in range(Ni) for j in range(N)])
+
+
+def check_f64(ctx, s, symmetric=True, i0=0, Ni=None, label=""):
+    st = O.Setup.from_system(s)
+    psi = s.psi.numpy()
+    pairs = {}
+    vref, eref = O.apply(psi, st, mode="symmetric" if symmetric else "block", i0=i0, Ni=Ni, pairs_out=pairs)
+    vx, ex, ep = run_gpu(ctx, s, "f64", symmetric, i0, Ni)
+    epref = oracle_pairs_vector(pairs, s.N, symmetric, i0, Ni)
+    e_err = np.abs(ep - epref).max() / np.abs(epref).max()
+    ex_err = abs(ex - eref) / abs(eref)
+    vx_err = rel_vx_err(vx, vref, st.q)
+    print(f"[{label}] e_ij rel {e_err:.3e}  E_x {ex:.12f} vs {eref:.12f} rel {ex_err:.3e}  Vx rel {vx_err:.3e}",
+          flush=True)
+    assert e_err <= TOL64
+    assert ex_err <= TOL64
+    assert vx_err <= TOL64
+
+
+def test_library_setup_tables_match_oracle(ctx):
+    s = W.small_system(n=16, L=5.0, N=2, r=6, K=8, seed=31)
+    st = O.Setup.from_system(s)
+    sysm = txe.System.from_workload(ctx, s)
+    for d in range(3):
+        C, Ch = sysm.conv(d)
+        assert np.abs(C - st.C[d]).max() <= 1e-13
+        assert np.abs(Ch - st.Chat[d]).max() <= 1e-12 * np.abs(st.Chat[d]).max()
+    sysm.close()
+
+
+def test_f64_tiny_symmetric(ctx):
+    check_f64(ctx, W.small_system(n=16, L=5.0, N=3, r=6, K=8, seed=31), label="n16 r6")
+
+
+def test_f64_ragged_ranks_and_grid(ctx):
+    """Ranks and grid sizes that are not multiples of 16 (padded tails)."""
+    check_f64(ctx, W.small_system(n=20, L=5.0, N=4, r=11, K=9, seed=32), label="n20 r11")
+
+
+def test_f64_non_cubic(ctx):
+    g = W.uniform_grid((16, 20, 24), (4.0, 5.0, 6.0))
+    psi, _ = W.make_orbitals(g, 3, 3, (0.5, 2.0), seed=33, box=1.5)
+    U = W.hosvd_bases(psi, g, (5, 7, 9))
+    w, a = W.exp_sum(10)
+    s = W.System(name="noncubic", grid=g, psi=psi, U=U, w=w, alpha=a)
+    check_f64(ctx, s, label="non-cubic")
+
+
+def test_f64_full_rank(ctx):
+    """r = n: the Tucker projector is the identity (dense-kernel case)."""
+    check_f64(ctx, W.small_system(n=16, L=5.0, N=2, r=16, K=6, bases="full", seed=34), label="full rank")
+
+
+def test_f64_cfg1(ctx):
+    check_f64(ctx, W.build_config("cfg1"), label="24^3 N=4 r=16 K=30")
+
+
+def test_f64_rank_tiles(ctx):
+    """Ranks spanning 2..5 tiles of 16 (every core-kernel variant)."""
+    for r in (20, 40, 48, 70):
+        s = W.small_system(n=(max(24, r) + 3) // 4 * 4, L=6.0, N=2, r=r, K=10, seed=35)
+        check_f64(ctx, s, label=f"r={r}")
+
+
+def test_f64_block_mode(ctx):
+    s = W.small_system(n=16, L=5.0, N=5, r=7, K=8, seed=36)
+    check_f64(ctx, s, symmetric=False, i0=1, Ni=3, label="block 1..3")
+
+
+def test_constant_kernel_limit_gpu(ctx):
+    """K = 1, alpha = 0, w = 1, full rank: Vx psi_i = -psi_i and E_x = -N/2."""
+    g = W.uniform_grid(16, 4.0)
+    psi, _ = W.make_orbitals(g, 3, 3, (0.5, 2.0), seed=8, box=1.0)
+    s = W.System(name="const", grid=g, psi=psi, U=W.full_rank_bases(g, 2), w=np.array([1.0]),
+                 alpha=np.array([0.0]))
+    vx, ex, _ = run_gpu(ctx, s)
+    p = psi.numpy()
+    assert np.abs(vx + p).max() <= 1e-11 * np.abs(p).max()
+    assert abs(ex + 1.5) <= 1e-11
+
+
+def test_energy_only_and_scaled_weighted_output(ctx):
+    s = W.small_system(n=16, L=5.0, N=3, r=6, K=8, seed=37)
+    sysm = txe.System.from_workload(ctx, s)
+    psi = s.psi.cuda()
+    vx, ex, _ = txe.apply(ctx, sysm, psi)
+    _, ex2, _ = txe.apply(ctx, sysm, psi, want_vx=False)
+    scale = torch.tensor(2.5, dtype=torch.float64, device="cuda")
+    vxw, ex3, _ = txe.apply(ctx, sysm, psi, out_scale=scale, out_weighted=True)
+    torch.cuda.synchronize()
+    w3 = torch.as_tensor(O.weights3d(s.grid.q), device="cuda")
+    assert float(ex2) == float(ex) == float(ex3)
+    assert torch.abs(vxw - 2.5 * w3 * vx).max().item() <= 1e-14 * torch.abs(vxw).max().item()
+    sysm.close()
+
+
+def test_deterministic_bitwise(ctx):
+    s = W.small_system(n=20, L=5.0, N=4, r=9, K=8, seed=38)
+    sysm = txe.System.from_workload(ctx, s)
+    psi = s.psi.cuda()
+    a = txe.apply(ctx, sysm, psi, want_pairs=True)
+    b = txe.apply(ctx, sysm, psi, want_pairs=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+    sysm.close()
+
+
+def test_f32_against_f64(ctx):
+    s = W.build_config("cfg1")
+    v64, e64, p64 = run_gpu(ctx, s, "f64")
+    for dt in (torch.float64, torch.float32):
+        v32, e32, p32 = run_gpu(ctx, s, "f32", psi_dtype=dt)
+        verr = rel_vx_err(v32, v64, s.grid.q)
+        print(f"[f32 psi {dt}] |dE_x| {abs(e32 - e64):.3e} Ha  Vx rel {verr:.3e}", flush=True)
+        assert abs(e32 - e64) <= 1e-5
+        assert verr <= 1e-5
+
+
+def test_validation_errors(ctx):
+    s = W.small_system(n=16, L=5.0, N=2, r=6, K=8, seed=39)
+    sysm = txe.System.from_workload(ctx, s)
+    psi = s.psi.cuda()
+    with pytest.raises(txe.TxeError):
+        txe.apply(ctx, sysm, psi.float(), compute="f64")         # FP64 compute needs FP64 orbitals
+    with pytest.raises(txe.TxeError):
+        txe.apply(ctx, sysm, psi, symmetric=False, i0=1, Ni=5)   # block outside [0, N)
+    bad = [u.copy() for u in s.U]
+    bad[1] *= 1.001
+    with pytest.raises(txe.TxeError):
+        txe.System(ctx, s.grid.x, s.grid.q, bad, s.w, s.alpha)   # U not q-orthonormal
+    with pytest.raises(txe.TxeError):
+        txe.System(ctx, s.grid.x, s.grid.q, s.U, s.w, -np.abs(s.alpha))
+    sysm.close()
