@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput of the Tucker-tensor Fock-exchange hot path on one MI355X.
+
+One step = one exchange apply (pair densities, projection onto the shared
+Tucker bases, core-space Gaussian kernel sum, back-projection, product with
+psi_j and sum over sources, E_x) over the whole 64^3 / 64-orbital workload
+(2080 unique pairs, r = 40, K = 40), inputs resident in HBM.  The metric is
+pair convolutions per second for the FP32-MFMA form, counted only when its
+E_x is within 1e-5 Ha of the FP64 form, which is timed beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2]
+
+Prints one JSON line.  Per-kernel durations come from HIP events the library
+records on its own stream around every launch (txe_profile_*).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair convolutions/s for Vx psi, MFMA-FP32 vs FP64 at dE_x<=1e-5 Ha; % roofline"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+KERNEL_SRC = os.path.join(ROOT, "paper_2401_04189_amd", "csrc", "txe_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_core.json")
+
+
+def flops_per_pair(n, r, K):
+    """Algorithmic flops of one pair convolution (2 flops per multiply-add).
+
+    projection and back-projection: n0 n1 n2 r2 + n0 n1 r1 r2 + n0 r0 r1 r2 each;
+    core-space kernel sum: K r0 r1 r2 (r0 + r1 + r2); pair energy: r0 r1 r2."""
+    n0, n1, n2 = n
+    r0, r1, r2 = r
+    proj = n0 * n1 * n2 * r2 + n0 * n1 * r1 * r2 + n0 * r0 * r1 * r2
+    core = K * r0 * r1 * r2 * (r0 + r1 + r2)
+    return 2.0 * (2 * proj + core + r0 * r1 * r2)
+
+
+def core_kernel_flops_per_pair(n, r, K):
+    """Algorithmic flops of the core kernel alone: the kernel sum, the pair
+    energy dot and the first (mode-0) back-projection stage fused into it."""
+    r0, r1, r2 = r
+    return 2.0 * (K * r0 * r1 * r2 * (r0 + r1 + r2) + r0 * r1 * r2 + n[0] * r0 * r1 * r2)
+
+
+def source_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(compute, cfg):
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    ent = t.get(f"{cfg}/{compute}")
+    if not ent or ent.get("kernel_source_sha") != source_sha():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def time_leg(txe, torch, ctx, sysm, psi, vx, compute, steps, warmup, symmetric, i0, Ni):
+    for _ in range(warmup):
+        txe.apply(ctx, sysm, psi, compute=compute, symmetric=symmetric, i0=i0, Ni=Ni, vx_out=vx)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, ex, _ = txe.apply(ctx, sysm, psi, compute=compute, symmetric=symmetric, i0=i0, Ni=Ni, vx_out=vx)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.kernel_times()
+    ctx.profile(False)
+    return wall, float(ex.item()), kt
+
+
+def cpu_baseline(s, seconds):
+    """The CPU FP64 oracle, as it stands, on the first unique pairs of the same
+    workload until `seconds` of work are done."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import txe_oracle as O
+
+    st = O.Setup.from_system(s)
+    psi = s.psi.numpy()
+    N = psi.shape[0]
+    pairs = [(i, j) for i in range(N) for j in range(i, N)]
+    done = 0
+    t0 = time.perf_counter()
+    for (i, j) in pairs:
+        O.pair(psi[i], psi[j], st)
+        done += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    return {"value": done / el, "unit": "pair-convolutions/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {done} of {len(pairs)} unique pairs of the same workload (numpy FP64, "
+                      f"{el:.1f} s, {threads} BLAS threads, host has {os.cpu_count()} CPUs)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}, "
+              f"WORLD_SIZE {world}", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2401_04189_amd import txe, workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    s = W.build_config(args.config)
+    n, r, K, N = s.grid.n, s.r, s.K, s.N
+    symmetric = True
+    npairs = N * (N + 1) // 2
+    ctx = txe.Context(0)
+    sysm = txe.System.from_workload(ctx, s)
+    psi = s.psi.cuda()
+    vx = torch.empty_like(psi)
+
+    legs = {}
+    for compute in ("f64", "f32"):
+        wall, ex, kt = time_leg(txe, torch, ctx, sysm, psi, vx, compute, args.steps, args.warmup, symmetric, 0, N)
+        legs[compute] = {"wall": wall, "ex": ex, "kt": kt}
+    dex = abs(legs["f32"]["ex"] - legs["f64"]["ex"])
+    use = "f32" if dex <= 1e-5 else "f64"
+    L = legs[use]
+    ms = 1e3 * L["wall"] / args.steps
+    value = npairs / (ms / 1e3)
+    fp64_ms = 1e3 * legs["f64"]["wall"] / args.steps
+    fp32_ms = 1e3 * legs["f32"]["wall"] / args.steps
+
+    core_ms, core_n = L["kt"]["core"]
+    per_launch_ms = core_ms / max(core_n, 1)
+    achieved = core_kernel_flops_per_pair(n, r, K) * npairs / (per_launch_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[use]
+    roof = {"bound": "mfma", "kernel": "core", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": load_traffic(use, args.config),
+            "launch_ms": round(per_launch_ms, 4)}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "pair-convolutions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": use,
+        "data": "synthetic",
+        "config": {"workload": W.WORKLOAD_NAMES[args.config], "grid": list(n), "orbitals": N, "pairs": npairs,
+                   "rank": list(r), "terms": K, "mode": "symmetric unique pairs"},
+        "fp64": {"value": round(npairs / (fp64_ms / 1e3), 1), "ms_per_step": round(fp64_ms, 4),
+                 "E_x": legs["f64"]["ex"]},
+        "fp32": {"value": round(npairs / (fp32_ms / 1e3), 1), "ms_per_step": round(fp32_ms, 4),
+                 "E_x": legs["f32"]["ex"]},
+        "fp32_over_fp64": round(fp64_ms / fp32_ms, 3),
+        "dE_x_fp32_vs_fp64_Ha": dex,
+        "whole_path_tflops": round(flops_per_pair(n, r, K) * npairs / (ms / 1e3) / 1e12, 3),
+        "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in L["kt"].items()},
+        "roofline": roof,
+    }
+    sysm.close()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

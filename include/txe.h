@@ -139,6 +139,23 @@ txe_status txe_context_set_stream(txe_context *ctx, void *hip_stream);
  * nothing).  A limit for tests: env TXE_TEST_MAX_WORKSPACE (bytes). */
 txe_status txe_workspace_reserve(txe_context *ctx, size_t bytes);
 
+/* Per-kernel timing.  When enabled (on = 1), every kernel launch of
+ * txe_apply is bracketed by HIP events recorded on the context stream; the
+ * counters restart at each txe_profile_enable call.  Not allowed while the
+ * stream is being captured (TXE_ERR_STATE).  Kernel ids:
+ *   0 proj12 (pair density, mode-2 and mode-1 projection)
+ *   1 proj3  (mode-0 projection)
+ *   2 core   (core-space Gaussian kernel sum, pair energies, first back-projection)
+ *   3 epair  (pair-energy partial sums)
+ *   4 back   (back-projection, product with psi_j, sum over sources)
+ *   5 energy (E_x reduction) */
+txe_status txe_profile_enable(txe_context *ctx, int32_t on);
+/* Waits for the recorded launches, then returns the summed duration (ms)
+ * and the number of launches of one kernel since profiling was enabled. */
+txe_status txe_profile_read(txe_context *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+/* Static name of a kernel id ("" when out of range). */
+const char *txe_kernel_name(int32_t kernel);
+
 /* System: validates the description (U orthonormality included), builds the
  * FP64 tables C_k^d, V_d, Chat_k^d on the host, rounds them to every compute
  * precision and uploads them.  Copies all host arrays; keeps no caller

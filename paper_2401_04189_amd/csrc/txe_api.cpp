@@ -43,6 +43,7 @@ struct txe_context {
   size_t ws_bytes = 0;
   bool sticky = false;
   std::string sticky_msg;
+  Prof prof;
 };
 
 template <typename T>
@@ -144,6 +145,35 @@ extern "C" txe_status txe_context_destroy(txe_context *ctx) {
   return ok();
 }
 
+extern "C" txe_status txe_profile_enable(txe_context *ctx, int32_t on) {
+  if (!ctx) return fail(TXE_ERR_ARG, "ctx is null");
+  if (on != 0 && on != 1) return fail(TXE_ERR_ARG, "on must be 0 or 1");
+  if (on) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(ctx->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone) return fail(TXE_ERR_STATE, "cannot profile while the stream is captured");
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  ctx->prof.reset();
+  ctx->prof.on = on != 0;
+  return ok();
+}
+
+extern "C" txe_status txe_profile_read(txe_context *ctx, int32_t kernel, double *total_ms, int64_t *launches) {
+  if (!ctx || !total_ms || !launches) return fail(TXE_ERR_ARG, "null argument");
+  if (kernel < 0 || kernel >= K_COUNT) return fail(TXE_ERR_ARG, "kernel id %d not in [0, %d)", kernel, (int)K_COUNT);
+  HIP_TRY(hipSetDevice(ctx->device));
+  ctx->prof.collect();
+  *total_ms = ctx->prof.total_ms[kernel];
+  *launches = ctx->prof.count[kernel];
+  return ok();
+}
+
+extern "C" const char *txe_kernel_name(int32_t kernel) {
+  static const char *names[K_COUNT] = {"proj12", "proj3", "core", "epair", "back", "energy"};
+  return (kernel >= 0 && kernel < K_COUNT) ? names[kernel] : "";
+}
+
 extern "C" txe_status txe_context_set_stream(txe_context *ctx, void *hip_stream) {
   if (!ctx) return fail(TXE_ERR_ARG, "ctx is null");
   ctx->stream = (hipStream_t)hip_stream;
@@ -209,8 +239,11 @@ struct HostTables {
   std::vector<double> V2B, V1chain, V0K, C1B, C2chain, Ahat, U0chain, U2T, U1chain;
 };
 
-static void build_tables(const txe_system &S, HostTables &H) {
+// Accumulator row of entry v in lane group lg of a 16x16x4 MFMA: 4*lg + v
+// for f32, 4*v + lg for f64.  The chain tables follow the precision's order.
+static void build_tables(const txe_system &S, HostTables &H, bool f64) {
   const Dims &D = S.D;
+  auto drow = [f64](int lg, int v) { return f64 ? 4 * v + lg : 4 * lg + v; };
   auto U = [&](int d, int i, int s) -> double { return S.U[d][(size_t)i * S.r[d] + s]; };
   auto V = [&](int d, int i, int s) -> double { return S.q[d][i] * U(d, i, s); };
   auto Ch = [&](int d, int k, int p, int s) -> double { return S.Chat[d][((size_t)k * S.r[d] + p) * S.r[d] + s]; };
@@ -225,7 +258,7 @@ static void build_tables(const txe_system &S, HostTables &H) {
     for (int mb = 0; mb < nbt; ++mb)
       for (int v = 0; v < 4; ++v)
         for (int l = 0; l < 64; ++l) {
-          const int beta = 16 * mt + (l & 15), b = 16 * mb + 4 * (l >> 4) + v;
+          const int beta = 16 * mt + (l & 15), b = 16 * mb + drow(l >> 4, v);
           if (beta < D.r1 && b < D.n1) H.V1chain[(((size_t)mt * nbt + mb) * 4 + v) * 64 + l] = V(1, b, beta);
         }
   // V0K[a][alpha]
@@ -244,7 +277,7 @@ static void build_tables(const txe_system &S, HostTables &H) {
       for (int mg = 0; mg < D.MT2; ++mg)
         for (int v = 0; v < 4; ++v)
           for (int l = 0; l < 64; ++l) {
-            const int gp = 16 * mtp + (l & 15), g = 16 * mg + 4 * (l >> 4) + v;
+            const int gp = 16 * mtp + (l & 15), g = 16 * mg + drow(l >> 4, v);
             if (gp < D.r2 && g < D.r2)
               H.C2chain[((((size_t)k * D.MT2 + mtp) * D.MT2 + mg) * 4 + v) * 64 + l] = Ch(2, k, gp, g);
           }
@@ -260,7 +293,7 @@ static void build_tables(const txe_system &S, HostTables &H) {
     for (int mt = 0; mt < D.MT0; ++mt)
       for (int v = 0; v < 4; ++v)
         for (int l = 0; l < 64; ++l) {
-          const int a = 16 * ma + (l & 15), ap = 16 * mt + 4 * (l >> 4) + v;
+          const int a = 16 * ma + (l & 15), ap = 16 * mt + drow(l >> 4, v);
           if (a < D.n0 && ap < D.r0) H.U0chain[(((size_t)ma * D.MT0 + mt) * 4 + v) * 64 + l] = U(0, a, ap);
         }
   // U2T[gamma][c] = U2[c][gamma]
@@ -273,7 +306,7 @@ static void build_tables(const txe_system &S, HostTables &H) {
     for (int me = 0; me < D.MT1; ++me)
       for (int v = 0; v < 4; ++v)
         for (int l = 0; l < 64; ++l) {
-          const int b = 16 * mb + (l & 15), be = 16 * me + 4 * (l >> 4) + v;
+          const int b = 16 * mb + (l & 15), be = 16 * me + drow(l >> 4, v);
           if (b < D.n1 && be < D.r1) H.U1chain[(((size_t)mb * D.MT1 + me) * 4 + v) * 64 + l] = U(1, b, be);
         }
 }
@@ -382,14 +415,16 @@ extern "C" txe_status txe_system_create(txe_context *ctx, const txe_system_desc 
   D.r1k = rup(D.r1, 4); D.r2k = rup(D.r2, 4);
   D.K = S->K; D.Kp = rup(S->K, KCHUNK);
 
-  HostTables H;
-  build_tables(*S, H);
+  HostTables H64, H32;
+  build_tables(*S, H64, true);
+  build_tables(*S, H32, false);
   txe_status st;
   if (hipSetDevice(ctx->device) != hipSuccess) {
     delete S;
     return fail(TXE_ERR_DEVICE, "hipSetDevice failed");
   }
-  if ((st = upload_tables(S->t64, H, ctx->stream)) != TXE_OK || (st = upload_tables(S->t32, H, ctx->stream)) != TXE_OK) {
+  if ((st = upload_tables(S->t64, H64, ctx->stream)) != TXE_OK ||
+      (st = upload_tables(S->t32, H32, ctx->stream)) != TXE_OK) {
     txe_system_destroy(S);
     return st;
   }
@@ -563,16 +598,16 @@ extern "C" txe_status txe_apply(txe_context *ctx, const txe_system *sys, const t
     if (pl.f64) {
       ChunkArgs<double> c = chunk_args<double>(sys, args, pl, ws);
       c.pm.p0 = p0; c.P = P; c.t_begin = tb; c.t_count = tcnt;
-      e = run_chunk_f64(sys->t64.t, c, pl.want_vx, ctx->stream);
+      e = run_chunk_f64(sys->t64.t, c, pl.want_vx, ctx->stream, &ctx->prof);
     } else {
       ChunkArgs<float> c = chunk_args<float>(sys, args, pl, ws);
       c.pm.p0 = p0; c.P = P; c.t_begin = tb; c.t_count = tcnt;
-      e = run_chunk_f32(sys->t32.t, c, psi64, pl.want_vx, ctx->stream);
+      e = run_chunk_f32(sys->t32.t, c, psi64, pl.want_vx, ctx->stream, &ctx->prof);
     }
   }
   if (e == hipSuccess)
     e = run_energy((const double *)(ws + pl.off_epair), pl.npairs, pl.symmetric ? 1 : 0, args->N, args->ex,
-                   args->e_pairs, ctx->stream);
+                   args->e_pairs, ctx->stream, &ctx->prof);
   if (e != hipSuccess) {
     ctx->sticky = true;
     ctx->sticky_msg = hipGetErrorString(e);

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace txe {
 
@@ -75,14 +76,79 @@ struct ChunkArgs {
   double *epair;              // all pairs of the apply, global index
 };
 
+// Optional per-kernel timing with HIP events recorded on the launch stream.
+enum KernelId { K_PROJ12 = 0, K_PROJ3 = 1, K_CORE = 2, K_EPAIR = 3, K_BACK = 4, K_ENERGY = 5, K_COUNT = 6 };
+
+struct Prof {
+  bool on = false;
+  struct Rec {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  Rec cur{};
+  double total_ms[K_COUNT] = {};
+  long long count[K_COUNT] = {};
+
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(int id, hipStream_t s) {
+    if (!on) return;
+    cur.id = id;
+    cur.a = take();
+    cur.b = take();
+    (void)hipEventRecord(cur.a, s);
+  }
+  void end(hipStream_t s) {
+    if (!on) return;
+    (void)hipEventRecord(cur.b, s);
+    pending.push_back(cur);
+  }
+  // waits for every recorded launch and adds its duration
+  void collect() {
+    for (Rec &r : pending) {
+      (void)hipEventSynchronize(r.b);
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        total_ms[r.id] += ms;
+        count[r.id] += 1;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    collect();
+    for (int i = 0; i < K_COUNT; ++i) {
+      total_ms[i] = 0;
+      count[i] = 0;
+    }
+  }
+  ~Prof() {
+    collect();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 // Runs one chunk (projection, core sum, back-projection, pair energies).
 // Returns hipSuccess or the first launch error.
-hipError_t run_chunk_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s);
+hipError_t run_chunk_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s,
+                         Prof *prof);
 hipError_t run_chunk_f32(const Tables<float> &tb, const ChunkArgs<float> &a, bool psi_f64, bool want_vx,
-                         hipStream_t s);
+                         hipStream_t s, Prof *prof);
 // E_x = sum_p c_p e_pair[p] (fixed order), and an optional copy of e_pair.
 hipError_t run_energy(const double *epair, long long npairs, int symmetric, int N, double *ex, double *e_out,
-                      hipStream_t s);
+                      hipStream_t s, Prof *prof);
 
 // Core-kernel variant choice (register budget per precision).
 int core_ngw(bool f64, int mt);

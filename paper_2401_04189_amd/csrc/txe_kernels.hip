@@ -16,7 +16,8 @@
 // All products use 16x16x4 MFMA tiles (f64 or f32) with 64-lane wavefronts.
 // Fragment layouts of a 16x16x4 MFMA for lane l (lr = l%16, lg = l/16):
 //   A[m][k]: m = lr, k = lg        B[k][n]: k = lg, n = lr
-//   D[m][n]: m = 4*lg + v, n = lr  (v = 0..3, the four accumulator entries)
+//   D[m][n]: n = lr, m = 4*lg + v (f32) or m = 4*v + lg (f64), v = 0..3 the
+//            four accumulator entries (measured on gfx950)
 // so an accumulator whose rows are the next contraction index feeds the next
 // MFMA as its B operand directly, one entry v at a time ("chained").
 #include "txe_internal.h"
@@ -42,6 +43,12 @@ struct MF<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
 };
+
+// accumulator row held by entry v of lane group lg
+template <typename T>
+__device__ __forceinline__ int drow(int lg, int v) {
+  return sizeof(T) == 8 ? 4 * v + lg : 4 * lg + v;
+}
 
 template <typename A>
 __device__ __forceinline__ A zero4() {
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dim
         if (g0 + gt < D.MT2) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int beta = 16 * mt + 4 * lg + v;
+            const int beta = 16 * mt + drow<T>(lg, v);
             const int gamma = 16 * (g0 + gt) + lr;
             out[(size_t)beta * D.rp2 + gamma] = T2a[mt][gt][v];
           }
@@ -214,7 +221,7 @@ __global__ __launch_bounds__(256) void k_proj3(const T *__restrict__ T2, Dims D,
       for (int ft = 0; ft < FT; ++ft) {
         if (f0 + ft < NF) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) out[(size_t)(16 * mt + 4 * lg + v) * F + 16 * (f0 + ft) + lr] = C[mt][ft][v];
+          for (int v = 0; v < 4; ++v) out[(size_t)(16 * mt + drow<T>(lg, v)) * F + 16 * (f0 + ft) + lr] = C[mt][ft][v];
         }
       }
     }
@@ -300,7 +307,7 @@ __global__ __launch_bounds__(256) void k_core(const T *__restrict__ G, Dims D, i
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int gp = 16 * mtp + 4 * lg + v;
+              const int gp = 16 * mtp + drow<T>(lg, v);
               if (gp >= g_lo && gp < g_hi) zslot[(gp - g_lo) * 16 + lr] = Z[v];
             }
           }
@@ -345,7 +352,7 @@ __global__ __launch_bounds__(256) void k_core(const T *__restrict__ G, Dims D, i
         if (mt < D.MT0) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int ap = 16 * mt + 4 * lg + v;
+            const int ap = 16 * mt + drow<T>(lg, v);
             if (ap < D.r0) e += (double)Phi[mt][ng][v] * (double)Gp[((size_t)ap * D.rp1 + bp) * D.rp2 + gp];
           }
         }
@@ -384,7 +391,7 @@ __global__ __launch_bounds__(256) void k_core(const T *__restrict__ G, Dims D, i
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int a = 16 * ma + 4 * lg + v;
+            const int a = 16 * ma + drow<T>(lg, v);
             if (a < D.n0) S1[(((size_t)p * D.n0 + a) * D.rp2 + gp) * D.rp1 + bp] = S[v];
           }
         }
@@ -484,7 +491,7 @@ __global__ __launch_bounds__(256) void k_back(const T *__restrict__ S1, const Ti
           if (c0 + cg < nct && c < D.n2) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int b = 16 * mbb + 4 * lg + v;
+              const int b = 16 * mbb + drow<T>(lg, v);
               if (b < D.n1) Acc[mbb][cg][v] += (T)ps[(size_t)b * D.n2 + c] * ph[cg][v];
             }
           }
@@ -503,7 +510,7 @@ __global__ __launch_bounds__(256) void k_back(const T *__restrict__ S1, const Ti
         if (c0 + cg < nct && c < D.n2) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int b = 16 * mbb + 4 * lg + v;
+            const int b = 16 * mbb + drow<T>(lg, v);
             if (b < D.n1) {
               double val = -scale * (double)Acc[mbb][cg][v];
               if (weighted) val *= q0[a] * q1[b] * q2[c];
@@ -626,30 +633,42 @@ hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s
 }
 
 template <typename T, typename Tin>
-hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
+hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s, Prof *prof) {
   constexpr int GT = 2, FT = 4;
   hipError_t e;
   {
     const int ngg = (a.D.MT2 + GT - 1) / GT;
+    prof->begin(K_PROJ12, s);
     hipLaunchKernelGGL((k_proj12<T, Tin, GT>), dim3(blocks_for((long long)a.P * a.D.n0 * ngg)), dim3(256), 0, s,
                        (const Tin *)a.psi, a.D, a.pm, a.P, tb, a.T2);
+    prof->end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   {
     const int NF = (a.D.rp1 * a.D.rp2) >> 4;
     const int nfg = (NF + FT - 1) / FT;
+    prof->begin(K_PROJ3, s);
     hipLaunchKernelGGL((k_proj3<T, FT>), dim3(blocks_for((long long)a.P * nfg)), dim3(256), 0, s, a.T2, a.D, a.P,
                        tb, a.G);
+    prof->end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if ((e = launch_core<T>(tb, a, want_vx, s)) != hipSuccess) return e;
+  prof->begin(K_CORE, s);
+  e = launch_core<T>(tb, a, want_vx, s);
+  prof->end(s);
+  if (e != hipSuccess) return e;
   {
     const int parts = a.D.MT1 * a.NGS;
+    prof->begin(K_EPAIR, s);
     hipLaunchKernelGGL(k_epair, dim3((a.P + 255) / 256), dim3(256), 0, s, a.epart, a.P, parts, a.pm.p0, a.epair);
+    prof->end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (want_vx) {
-    if ((e = launch_back<T, Tin>(tb, a, s)) != hipSuccess) return e;
+    prof->begin(K_BACK, s);
+    e = launch_back<T, Tin>(tb, a, s);
+    prof->end(s);
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -658,19 +677,22 @@ hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx,
 
 int core_ngw(bool f64, int mt) { return f64 ? NGW64[mt] : NGW32[mt]; }
 
-hipError_t run_chunk_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s) {
-  return run_chunk_t<double, double>(tb, a, want_vx, s);
+hipError_t run_chunk_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s,
+                         Prof *prof) {
+  return run_chunk_t<double, double>(tb, a, want_vx, s, prof);
 }
 
 hipError_t run_chunk_f32(const Tables<float> &tb, const ChunkArgs<float> &a, bool psi_f64, bool want_vx,
-                         hipStream_t s) {
-  if (psi_f64) return run_chunk_t<float, double>(tb, a, want_vx, s);
-  return run_chunk_t<float, float>(tb, a, want_vx, s);
+                         hipStream_t s, Prof *prof) {
+  if (psi_f64) return run_chunk_t<float, double>(tb, a, want_vx, s, prof);
+  return run_chunk_t<float, float>(tb, a, want_vx, s, prof);
 }
 
 hipError_t run_energy(const double *epair, long long npairs, int symmetric, int N, double *ex, double *e_out,
-                      hipStream_t s) {
+                      hipStream_t s, Prof *prof) {
+  prof->begin(K_ENERGY, s);
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, s, epair, npairs, symmetric, N, ex, e_out);
+  prof->end(s);
   return hipGetLastError();
 }
 

@@ -68,7 +68,13 @@ SIGNATURES = {
     "txe_workspace_query": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs),
                                      ctypes.POINTER(ctypes.c_size_t)]),
     "txe_apply": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs)]),
+    "txe_profile_enable": (_c_int, [ctypes.c_void_p, _c_int]),
+    "txe_profile_read": (_c_int, [ctypes.c_void_p, _c_int, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int64)]),
+    "txe_kernel_name": (ctypes.c_char_p, [_c_int]),
 }
+
+KERNELS = ("proj12", "proj3", "core", "epair", "back", "energy")
 
 _lib = None
 
@@ -131,6 +137,20 @@ class Context:
 
     def reserve(self, nbytes):
         _check(lib().txe_workspace_reserve(self.h, int(nbytes)))
+
+    def profile(self, on=True):
+        """Start (and reset) or stop per-kernel HIP-event timing."""
+        _check(lib().txe_profile_enable(self.h, 1 if on else 0))
+
+    def kernel_times(self):
+        """{kernel name: (total ms, launches)} since profiling was enabled."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms = ctypes.c_double()
+            n = ctypes.c_int64()
+            _check(lib().txe_profile_read(self.h, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
     def close(self):
         if getattr(self, "h", None):

@@ -29,7 +29,7 @@ def ctx():
 
 def wnorm(v, q):
     w3 = O.weights3d(q)
-    return np.sqrt(np.einsum("i...,...->i", v * v, w3))
+    return np.sqrt((v * v * w3[None]).sum(axis=(1, 2, 3)))
 
 
 def rel_vx_err(vx, ref, q):
