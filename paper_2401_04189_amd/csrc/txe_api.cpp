@@ -410,7 +410,10 @@ extern "C" txe_status txe_system_create(txe_context *ctx, const txe_system_desc 
   D.n0 = S->n[0]; D.n1 = S->n[1]; D.n2 = S->n[2];
   D.na0 = rup(D.n0, 16); D.nb1 = rup(D.n1, 16); D.nc2 = rup(D.n2, 16);
   D.r0 = S->r[0]; D.r1 = S->r[1]; D.r2 = S->r[2];
-  D.rp0 = rup(D.r0, 16); D.rp1 = rup(D.r1, 16); D.rp2 = rup(D.r2, 16);
+  // one padded core size for every mode: the core kernel's loops and strides
+  // are then compile-time constants (padded rows and columns are zero)
+  const int rpad = rup(std::max(D.r0, std::max(D.r1, D.r2)), 16);
+  D.rp0 = rpad; D.rp1 = rpad; D.rp2 = rpad;
   D.MT0 = D.rp0 / 16; D.MT1 = D.rp1 / 16; D.MT2 = D.rp2 / 16;
   D.r1k = rup(D.r1, 4); D.r2k = rup(D.r2, 4);
   D.K = S->K; D.Kp = rup(S->K, KCHUNK);

@@ -95,7 +95,8 @@ __global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dim
                                                 Tables<T> tb, T *__restrict__ T2) {
   using M = MF<T>;
   using acc = typename M::acc;
-  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
   const int ngg = (D.MT2 + GT - 1) / GT;
   const long long item = (long long)blockIdx.x * 4 + wave;
   if (item >= (long long)P * D.n0 * ngg) return;
@@ -182,7 +183,8 @@ __global__ __launch_bounds__(256) void k_proj3(const T *__restrict__ T2, Dims D,
                                                T *__restrict__ G) {
   using M = MF<T>;
   using acc = typename M::acc;
-  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
   const int NF = (D.rp1 * D.rp2) >> 4;
   const int nfg = (NF + FT - 1) / FT;
   const long long item = (long long)blockIdx.x * 4 + wave;
@@ -230,42 +232,50 @@ __global__ __launch_bounds__(256) void k_proj3(const T *__restrict__ T2, Dims D,
 
 // -------------------------------------------------------------------------------------
 // core: per workgroup one pair p, one 16-wide tile bt of beta' and a range of
-// gamma' (split gs of NGS).  For each input slab alpha and each chunk of
-// KCHUNK Gaussian terms:
-//   phase A (each wavefront: KCHUNK/4 terms)
+// gamma' (split gs of NGS).  Input slabs alpha form the outer loop; the
+// slab's MFMA fragments stay in registers while the four wavefronts walk the
+// Gaussian terms four at a time (wavefront w takes term k = 4*kq + w):
+//   phase A
 //     W[gamma][beta']  = sum_beta G[alpha][beta][gamma] Chat1_k[beta'][beta]
 //     Z[gamma'][beta'] = sum_gamma Chat2_k[gamma'][gamma] W[gamma][beta']   (chained)
-//     Z -> LDS slot of term k
+//     Z -> LDS slot w
 //   phase B (each wavefront: its own gamma' rows, all alpha')
-//     Phi[alpha'][gamma'][beta'] += sum_k w_k Chat0_k[alpha'][alpha] Z_k[gamma'][beta']
-// i.e. the term sum is folded into the reduction dimension of the mode-0
-// product.  Phi stays in registers for the whole pair.
+//     Phi[alpha'][gamma'][beta'] += sum_{k in step} w_k Chat0_k[alpha'][alpha] Z_k[gamma'][beta']
+// i.e. the term sum is folded into the reduction of the mode-0 product.  The
+// term matrices are shared by every workgroup and come from L2; Z is
+// double-buffered in LDS so each step needs one barrier; Phi stays in
+// registers for the whole pair.
 // -------------------------------------------------------------------------------------
 template <typename T, int MT, int NGW, bool WRITE_S1>
-__global__ __launch_bounds__(256) void k_core(const T *__restrict__ G, Dims D, int P, int NGS, Tables<T> tb,
-                                              T *__restrict__ S1, double *__restrict__ epart) {
+__global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D, int P, int NGS, Tables<T> tb,
+                                                 T *__restrict__ S1, double *__restrict__ epart) {
   using M = MF<T>;
   using acc = typename M::acc;
-  constexpr int KPW = KCHUNK / 4;
+  // the padded core size is the same for all three modes: rp = 16 * MT
+  constexpr int RP = 16 * MT;
+  constexpr size_t F = (size_t)RP * RP;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *Zs = reinterpret_cast<T *>(smem_raw);
   __shared__ double red[4];
 
-  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
   const int gs = blockIdx.x % NGS;
   const int tt = blockIdx.x / NGS;
-  const int bt = tt % D.MT1;
-  const int p = tt / D.MT1;
+  const int bt = tt % MT;
+  const int p = tt / MT;
   if (p >= P) return;  // whole block leaves together
 
   const int gper = (D.r2 + NGS - 1) / NGS;
   const int g_lo = gs * gper;
   const int g_hi = min(D.r2, g_lo + gper);
-  const int wg_lo = g_lo + wave * NGW;
-  const int wg_hi = min(g_hi, wg_lo + NGW);
-  const int mt_lo = g_lo >> 4, mt_hi = (g_hi - 1) >> 4;
-  const size_t F = (size_t)D.rp1 * D.rp2;
-  const T *Gp = G + (size_t)p * D.rp0 * F;
+  const int gw = (gper + 3) >> 2;                 // gamma' rows per wavefront in phase B (<= NGW)
+  const int wg_lo = g_lo + wave * gw;
+  const int wg_hi = min(g_hi, wg_lo + gw);
+  const int nrow = max(0, wg_hi - wg_lo);         // this wavefront's gamma' rows (uniform)
+  const T *Gp = G + (size_t)p * RP * F;
+
+  T *Zs = reinterpret_cast<T *>(smem_raw);        // [2][4][gper][16]
+  const int zsz = 4 * gper * 16;
 
   acc Phi[MT][NGW];
 #pragma unroll
@@ -273,71 +283,149 @@ __global__ __launch_bounds__(256) void k_core(const T *__restrict__ G, Dims D, i
 #pragma unroll
     for (int ng = 0; ng < NGW; ++ng) Phi[mt][ng] = zero4<acc>();
 
-  for (int alpha = 0; alpha < D.r0; ++alpha) {
-    const T *Ga = Gp + (size_t)alpha * F;
-    for (int kc0 = 0; kc0 < D.Kp; kc0 += KCHUNK) {
-      // ---- phase A
+  // small ranks keep the slab's A fragments in registers for all terms and
+  // load the next step's term matrices while the current step computes;
+  // large ranks re-read the slab (L1-resident) and load the terms in place.
+  // Loops run over the padded size; padded rows and columns are zero.
+  constexpr bool HOLD_G = sizeof(T) == 4 ? MT <= 3 : MT <= 2;
+  constexpr bool PF = HOLD_G;
+  constexpr int GK = HOLD_G ? 4 * MT : 1, GM = HOLD_G ? MT : 1;
+  const int nkq = (D.K + 3) >> 2;
+  const int nsteps = D.r0 * nkq;
+
+  // term matrices of one step for this wavefront: Chat1_k (16 beta' columns)
+  // as B fragments, Chat2_k in chain order as A fragments
+  struct CF {
+    T cb[4 * MT];
+    T c2[MT][MT][4];
+  };
+  auto load_terms = [&](int kq_, CF &f) {
+    const int k_ = 4 * kq_ + wave;
+    if (k_ >= D.K) return;
+    const T *C1k = tb.C1B + (size_t)k_ * F + 16 * bt + lr;
 #pragma unroll
-      for (int kk = 0; kk < KPW; ++kk) {
-        const int slot = wave * KPW + kk;
-        const int k = kc0 + slot;
-        T *zslot = Zs + (size_t)slot * gper * 16;
-        if (k < D.K) {
-          acc W[MT];
+    for (int kt = 0; kt < 4 * MT; ++kt) f.cb[kt] = C1k[(4 * kt + lg) * RP];
+    const T *C2k = tb.C2chain + (size_t)k_ * MT * MT * 256 + lane;
 #pragma unroll
-          for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
-          const T *C1k = tb.C1B + (size_t)k * D.rp1 * D.rp1 + 16 * bt + lr;
-          for (int kt = 0; kt < (D.r1k >> 2); ++kt) {
-            const int beta = 4 * kt + lg;
-            const T bf = C1k[(size_t)beta * D.rp1];
-            const T *grow = Ga + (size_t)beta * D.rp2 + lr;
+    for (int mtp = 0; mtp < MT; ++mtp)
+#pragma unroll
+      for (int mg = 0; mg < MT; ++mg)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) f.c2[mtp][mg][v] = C2k[((mtp * MT + mg) * 4 + v) * 64];
+  };
+
+  CF cur, nxt;
+  if constexpr (PF) load_terms(0, cur);
+  T gf[GK][GM];
+  const T *Ga = Gp + lr;
+  for (int step = 0; step < nsteps; ++step) {
+    const int alpha = step / nkq;
+    const int kq = step - alpha * nkq;
+    const int k = 4 * kq + wave;
+    if (kq == 0) {
+      // A fragments of the slab: G[alpha][beta = 4kt+lg][gamma = 16mg+lr]
+      Ga = Gp + (size_t)alpha * F + lr;
+      if constexpr (HOLD_G) {
+#pragma unroll
+        for (int kt = 0; kt < 4 * MT; ++kt)
+#pragma unroll
+          for (int mg = 0; mg < MT; ++mg) gf[kt][mg] = Ga[(4 * kt + lg) * RP + 16 * mg];
+      }
+    }
+    if constexpr (PF) {
+      if (step + 1 < nsteps) load_terms(kq + 1 == nkq ? 0 : kq + 1, nxt);
+    } else if (k < D.K) {
+      const T *C1k = tb.C1B + (size_t)k * F + 16 * bt + lr;
+#pragma unroll
+      for (int kt = 0; kt < 4 * MT; ++kt) cur.cb[kt] = C1k[(4 * kt + lg) * RP];
+    }
+    T *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * gper * 16;
+    // ---- phase A
+    if (k < D.K) {
+      acc W[MT];
+#pragma unroll
+      for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
+#pragma unroll
+      for (int kt = 0; kt < 4 * MT; ++kt) {
+#pragma unroll
+        for (int mg = 0; mg < MT; ++mg) {
+          T g;
+          if constexpr (HOLD_G) g = gf[kt][mg];
+          else g = Ga[(4 * kt + lg) * RP + 16 * mg];
+          W[mg] = M::mma(g, cur.cb[kt], W[mg]);
+        }
+      }
+      // all gamma' tiles; rows outside this workgroup's range are not stored.
+      // f32: the tiles' chains are interleaved (short MFMA latency, cheap
+      // accumulators); f64: one tile at a time to keep registers for Phi
+      auto store_z = [&](int mtp, const acc &Zt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gp = 16 * mtp + drow<T>(lg, v);
+          if (gp >= g_lo && gp < g_hi) Zw[(gp - g_lo) * 16 + lr] = Zt[v];
+        }
+      };
+      if constexpr (sizeof(T) == 4) {
+        acc Z[MT];
+#pragma unroll
+        for (int mtp = 0; mtp < MT; ++mtp) Z[mtp] = zero4<acc>();
+#pragma unroll
+        for (int mg = 0; mg < MT; ++mg)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int mtp = 0; mtp < MT; ++mtp) Z[mtp] = M::mma(cur.c2[mtp][mg][v], W[mg][v], Z[mtp]);
+#pragma unroll
+        for (int mtp = 0; mtp < MT; ++mtp) store_z(mtp, Z[mtp]);
+      } else {
+        const T *C2k = tb.C2chain + (size_t)k * MT * MT * 256 + lane;
+#pragma unroll
+        for (int mtp = 0; mtp < MT; ++mtp) {
+          T c2[MT][4];
+          if constexpr (PF) {
 #pragma unroll
             for (int mg = 0; mg < MT; ++mg)
-              if (mg < D.MT2) W[mg] = M::mma(grow[16 * mg], bf, W[mg]);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) c2[mg][v] = cur.c2[mtp][mg][v];
+          } else {
+#pragma unroll
+            for (int mg = 0; mg < MT; ++mg)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) c2[mg][v] = C2k[((mtp * MT + mg) * 4 + v) * 64];
           }
-          const T *C2k = tb.C2chain + (size_t)k * D.MT2 * D.MT2 * 256 + lane;
-          for (int mtp = mt_lo; mtp <= mt_hi; ++mtp) {
-            acc Z = zero4<acc>();
+          acc Z = zero4<acc>();
 #pragma unroll
-            for (int mg = 0; mg < MT; ++mg) {
-              if (mg < D.MT2) {
+          for (int mg = 0; mg < MT; ++mg)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) Z = M::mma(C2k[((size_t)(mtp * D.MT2 + mg) * 4 + v) * 64], W[mg][v], Z);
-              }
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int gp = 16 * mtp + drow<T>(lg, v);
-              if (gp >= g_lo && gp < g_hi) zslot[(gp - g_lo) * 16 + lr] = Z[v];
-            }
-          }
-        } else {
-          for (int idx = lane; idx < gper * 16; idx += 64) zslot[idx] = (T)0;
+            for (int v = 0; v < 4; ++v) Z = M::mma(c2[mg][v], W[mg][v], Z);
+          store_z(mtp, Z);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
-      __syncthreads();
-      // ---- phase B
-#pragma unroll
-      for (int kt = 0; kt < KCHUNK / 4; ++kt) {
-        const int kq = 4 * kt + lg;
-        T af[MT];
-        const T *arow = tb.Ahat + ((size_t)alpha * D.Kp + kc0 + kq) * D.rp0 + lr;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) af[mt] = (mt < D.MT0) ? arow[16 * mt] : (T)0;
-        const T *zrow = Zs + (size_t)kq * gper * 16 + lr;
-#pragma unroll
-        for (int ng = 0; ng < NGW; ++ng) {
-          const int gp = wg_lo + ng;
-          if (gp < wg_hi) {
-            const T bz = zrow[(gp - g_lo) * 16];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-              if (mt < D.MT0) Phi[mt][ng] = M::mma(af[mt], bz, Phi[mt][ng]);
-          }
-        }
-      }
-      __syncthreads();
+    } else {
+      for (int idx = lane; idx < gper * 16; idx += 64) Zw[idx] = (T)0;
     }
+    __syncthreads();
+    // ---- phase B: reduction over the step's four terms (slot lg)
+    {
+      const int kk = 4 * kq + lg;
+      T af[MT];
+      const T *ah = tb.Ahat + ((size_t)alpha * D.Kp + kk) * RP + lr;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) af[mt] = ah[16 * mt];
+      const T *zrow = Zs + (size_t)(step & 1) * zsz + (size_t)lg * gper * 16 + lr;
+      // every row of Phi is updated (no branch keeps the accumulators in
+      // place); rows past this wavefront's range read a valid LDS row and are
+      // never stored
+#pragma unroll
+      for (int ng = 0; ng < NGW; ++ng) {
+        const int row = min(wg_lo - g_lo + ng, gper - 1);
+        const T bz = zrow[row * 16];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(af[mt], bz, Phi[mt][ng]);
+      }
+    }
+    if constexpr (PF) cur = nxt;
   }
 
   // ---- pair-energy partial: sum Phi[alpha'][gamma'][beta'] G[alpha'][beta'][gamma']
@@ -349,11 +437,11 @@ __global__ __launch_bounds__(256) void k_core(const T *__restrict__ G, Dims D, i
     if (gp < wg_hi && bp < D.r1) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        if (mt < D.MT0) {
+        {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int ap = 16 * mt + drow<T>(lg, v);
-            if (ap < D.r0) e += (double)Phi[mt][ng][v] * (double)Gp[((size_t)ap * D.rp1 + bp) * D.rp2 + gp];
+            if (ap < D.r0) e += (double)Phi[mt][ng][v] * (double)Gp[((size_t)ap * RP + bp) * RP + gp];
           }
         }
       }
@@ -365,7 +453,7 @@ __global__ __launch_bounds__(256) void k_core(const T *__restrict__ G, Dims D, i
   if (lane == 0) red[wave] = e;
   __syncthreads();
   if (threadIdx.x == 0)
-    epart[((size_t)p * D.MT1 + bt) * NGS + gs] = ((red[0] + red[1]) + (red[2] + red[3]));
+    epart[((size_t)p * MT + bt) * NGS + gs] = ((red[0] + red[1]) + (red[2] + red[3]));
 
   // ---- S1[p][a][gamma'][beta'] = sum_alpha' U0[a][alpha'] Phi[alpha'][gamma'][beta']
   if (WRITE_S1) {
@@ -376,7 +464,7 @@ __global__ __launch_bounds__(256) void k_core(const T *__restrict__ G, Dims D, i
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          uf[mt][v] = (mt < D.MT0) ? tb.U0chain[(((size_t)ma * D.MT0 + mt) * 4 + v) * 64 + lane] : (T)0;
+          uf[mt][v] = tb.U0chain[(((size_t)ma * MT + mt) * 4 + v) * 64 + lane];
 #pragma unroll
       for (int ng = 0; ng < NGW; ++ng) {
         const int gp = wg_lo + ng;
@@ -384,7 +472,7 @@ __global__ __launch_bounds__(256) void k_core(const T *__restrict__ G, Dims D, i
           acc S = zero4<acc>();
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            if (mt < D.MT0) {
+            {
 #pragma unroll
               for (int v = 0; v < 4; ++v) S = M::mma(uf[mt][v], Phi[mt][ng][v], S);
             }
@@ -392,7 +480,7 @@ __global__ __launch_bounds__(256) void k_core(const T *__restrict__ G, Dims D, i
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int a = 16 * ma + drow<T>(lg, v);
-            if (a < D.n0) S1[(((size_t)p * D.n0 + a) * D.rp2 + gp) * D.rp1 + bp] = S[v];
+            if (a < D.n0) S1[(((size_t)p * D.n0 + a) * RP + gp) * RP + bp] = S[v];
           }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -416,7 +504,8 @@ __global__ __launch_bounds__(256) void k_back(const T *__restrict__ S1, const Ti
                                               const double *__restrict__ q1, const double *__restrict__ q2) {
   using M = MF<T>;
   using acc = typename M::acc;
-  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
   const int nct = D.nc2 >> 4, nbt = D.nb1 >> 4;
   const int ncg = (nct + NCG - 1) / NCG;
   const long long item = (long long)blockIdx.x * 4 + wave;
@@ -577,8 +666,13 @@ inline unsigned blocks_for(long long waves) { return (unsigned)((waves + 3) / 4)
 template <typename T, int MT, int NGW>
 hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
   const int gper = (a.D.r2 + a.NGS - 1) / a.NGS;
-  const size_t lds = (size_t)KCHUNK * gper * 16 * sizeof(T);
+  const size_t lds = (2 * 4 * (size_t)gper * 16) * sizeof(T);
   const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
+  if (lds > 64 * 1024) {  // opt in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
+    const void *fn = want_vx ? (const void *)k_core<T, MT, NGW, true> : (const void *)k_core<T, MT, NGW, false>;
+    const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (ea != hipSuccess) return ea;
+  }
   if (want_vx)
     hipLaunchKernelGGL((k_core<T, MT, NGW, true>), dim3(nb), dim3(256), lds, s, a.G, a.D, a.P, a.NGS, tb, a.S1,
                        a.epart);
@@ -589,8 +683,8 @@ hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_
 }
 
 // register budget of the Phi accumulators: MT * NGW * 4 values per lane
-constexpr int NGW64[MAX_MT + 1] = {0, 16, 12, 10, 8, 6};
-constexpr int NGW32[MAX_MT + 1] = {0, 16, 16, 16, 12, 10};
+constexpr int NGW64[MAX_MT + 1] = {0, 4, 8, 10, 8, 6};
+constexpr int NGW32[MAX_MT + 1] = {0, 4, 8, 10, 12, 10};
 
 template <typename T>
 hipError_t launch_core(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
