@@ -113,6 +113,10 @@ def main():
     ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one elementwise kernel that reads and writes 512 MiB (reference for "
+                         "the HBM byte counters)")
+    ap.add_argument("--legs", default="f64,f32", help="compute forms to time (comma separated)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -137,10 +141,22 @@ def main():
     psi = s.psi.cuda()
     vx = torch.empty_like(psi)
 
+    if args.copy_calibration:
+        # one elementwise kernel of known traffic: reads 512 MiB, writes 512 MiB
+        src = torch.empty(64 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {src.numel() * 8} bytes read and written", file=sys.stderr)
+        del src, dst
+
     legs = {}
-    for compute in ("f64", "f32"):
+    for compute in args.legs.split(","):
         wall, ex, kt = time_leg(txe, torch, ctx, sysm, psi, vx, compute, args.steps, args.warmup, symmetric, 0, N)
         legs[compute] = {"wall": wall, "ex": ex, "kt": kt}
+    if "f32" not in legs or "f64" not in legs:
+        print(json.dumps({k: {"ms_per_step": 1e3 * v["wall"] / args.steps, "E_x": v["ex"]} for k, v in legs.items()}))
+        return
     dex = abs(legs["f32"]["ex"] - legs["f64"]["ex"])
     use = "f32" if dex <= 1e-5 else "f64"
     L = legs[use]
@@ -173,13 +189,14 @@ def main():
         "config": {"workload": W.WORKLOAD_NAMES[args.config], "grid": list(n), "orbitals": N, "pairs": npairs,
                    "rank": list(r), "terms": K, "mode": "symmetric unique pairs"},
         "fp64": {"value": round(npairs / (fp64_ms / 1e3), 1), "ms_per_step": round(fp64_ms, 4),
-                 "E_x": legs["f64"]["ex"]},
+                 "E_x": legs["f64"]["ex"],
+                 "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in legs["f64"]["kt"].items()}},
         "fp32": {"value": round(npairs / (fp32_ms / 1e3), 1), "ms_per_step": round(fp32_ms, 4),
-                 "E_x": legs["f32"]["ex"]},
+                 "E_x": legs["f32"]["ex"],
+                 "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in legs["f32"]["kt"].items()}},
         "fp32_over_fp64": round(fp64_ms / fp32_ms, 3),
         "dE_x_fp32_vs_fp64_Ha": dex,
         "whole_path_tflops": round(flops_per_pair(n, r, K) * npairs / (ms / 1e3) / 1e12, 3),
-        "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in L["kt"].items()},
         "roofline": roof,
     }
     sysm.close()
