@@ -356,8 +356,9 @@ __global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D
         }
       }
       // all gamma' tiles; rows outside this workgroup's range are not stored.
-      // f32: the tiles' chains are interleaved (short MFMA latency, cheap
-      // accumulators); f64: one tile at a time to keep registers for Phi
+      // With prefetched f32 term matrices the tiles' chains are interleaved
+      // (short MFMA latency, cheap accumulators); otherwise one tile at a
+      // time, loading that tile's Chat2 fragments (keeps registers for Phi)
       auto store_z = [&](int mtp, const acc &Zt) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D
           if (gp >= g_lo && gp < g_hi) Zw[(gp - g_lo) * 16 + lr] = Zt[v];
         }
       };
-      if constexpr (sizeof(T) == 4) {
+      if constexpr (sizeof(T) == 4 && PF) {
         acc Z[MT];
 #pragma unroll
         for (int mtp = 0; mtp < MT; ++mtp) Z[mtp] = zero4<acc>();

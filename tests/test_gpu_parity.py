@@ -115,6 +115,37 @@ def test_f64_rank_tiles(ctx):
         check_f64(ctx, s, label=f"r={r}")
 
 
+def test_f32_rank_tiles_against_f64(ctx):
+    """Every FP32 core-kernel variant (2..5 rank tiles) against the GPU FP64 path."""
+    for r in (20, 40, 48, 70):
+        s = W.small_system(n=(max(24, r) + 3) // 4 * 4, L=6.0, N=2, r=r, K=10, seed=35)
+        v64, e64, p64 = run_gpu(ctx, s, "f64")
+        v32, e32, p32 = run_gpu(ctx, s, "f32")
+        verr = rel_vx_err(v32, v64, s.grid.q)
+        perr = np.abs(p32 - p64).max() / np.abs(p64).max()
+        print(f"[f32 r={r}] |dE_x| {abs(e32 - e64):.3e} Ha  e_ij rel {perr:.3e}  Vx rel {verr:.3e}", flush=True)
+        assert abs(e32 - e64) <= 1e-5 and perr <= 1e-5 and verr <= 1e-5
+
+
+def test_f32_block_chunked(ctx, monkeypatch):
+    """Block mode split into several target chunks (forced by a small
+    workspace limit) gives the same result as one chunk, in both precisions."""
+    s = W.small_system(n=16, L=5.0, N=6, r=7, K=8, seed=40)
+    sysm = txe.System.from_workload(ctx, s)
+    psi = s.psi.cuda()
+    full = {c: txe.apply(ctx, sysm, psi, compute=c, symmetric=False, i0=1, Ni=4,
+                         want_pairs=True) for c in ("f64", "f32")}
+    need = txe.workspace_bytes(ctx, sysm, psi, symmetric=False, i0=1, Ni=4)
+    monkeypatch.setenv("TXE_TEST_MAX_WORKSPACE", str(need // 3))
+    for c in ("f64", "f32"):
+        vx, ex, ep = txe.apply(ctx, sysm, psi, compute=c, symmetric=False, i0=1, Ni=4, want_pairs=True)
+        torch.cuda.synchronize()
+        assert torch.equal(vx, full[c][0]) and torch.equal(ep, full[c][2])
+        assert float(ex) == float(full[c][1])
+    monkeypatch.delenv("TXE_TEST_MAX_WORKSPACE")
+    sysm.close()
+
+
 def test_f64_block_mode(ctx):
     s = W.small_system(n=16, L=5.0, N=5, r=7, K=8, seed=36)
     check_f64(ctx, s, symmetric=False, i0=1, Ni=3, label="block 1..3")
