@@ -116,7 +116,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise kernel that reads and writes 512 MiB (reference for "
                          "the HBM byte counters)")
-    ap.add_argument("--legs", default="f64,f32", help="compute forms to time (comma separated)")
+    ap.add_argument("--legs", default="f64,f32,bf16x3,bf16x6", help="compute forms to time (comma separated)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -195,6 +195,13 @@ def main():
                  "E_x": legs["f32"]["ex"],
                  "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in legs["f32"]["kt"].items()}},
         "fp32_over_fp64": round(fp64_ms / fp32_ms, 3),
+        "split_bf16": {c: {"value": round(npairs / (1e3 * legs[c]["wall"] / args.steps / 1e3), 1),
+                           "ms_per_step": round(1e3 * legs[c]["wall"] / args.steps, 4),
+                           "over_fp64": round(fp64_ms / (1e3 * legs[c]["wall"] / args.steps), 3),
+                           "dE_x_vs_fp64_Ha": abs(legs[c]["ex"] - legs["f64"]["ex"]),
+                           "within_1e-5_Ha": abs(legs[c]["ex"] - legs["f64"]["ex"]) <= 1e-5,
+                           "core_ms": round(legs[c]["kt"]["core"][0] / max(legs[c]["kt"]["core"][1], 1), 4)}
+                       for c in legs if c.startswith("bf16")},
         "dE_x_fp32_vs_fp64_Ha": dex,
         "whole_path_tflops": round(flops_per_pair(n, r, K) * npairs / (ms / 1e3) / 1e12, 3),
         "roofline": roof,

@@ -68,12 +68,17 @@ typedef enum {
 } txe_status;
 
 /* Arithmetic of the mode products and kernel sums.  The 1-D convolution
- * matrices and Chat_k^d are always built in FP64 and then rounded; the E_x
- * reduction is always FP64. */
+ * matrices and Chat_k^d are always built in FP64 and then rounded or split;
+ * the E_x reduction is always FP64.  In the split-bf16 forms every operand x
+ * of the two chained contractions of the core-space kernel sum is taken as
+ * bf16 parts p0 + p1 (+ p2) and a product keeps the terms p_i q_j with
+ * i + j < parts (bf16 MFMA, FP32 accumulation); the projections, the
+ * back-projection and the term accumulation run in FP32 MFMA. */
 typedef enum {
   TXE_COMPUTE_F64 = 0,      /* FP64 MFMA                                                    */
   TXE_COMPUTE_F32 = 1,      /* FP32 MFMA, FP32 accumulation                                 */
-  TXE_COMPUTE_BF16X3 = 2    /* bf16 hi+lo split operands, 3 products, FP32 accumulation     */
+  TXE_COMPUTE_BF16X3 = 2,   /* bf16 hi+lo split operands, 3 products, FP32 accumulation     */
+  TXE_COMPUTE_BF16X6 = 3    /* bf16 three-part split operands, 6 products                   */
 } txe_compute;
 
 typedef enum { TXE_DTYPE_F64 = 0, TXE_DTYPE_F32 = 1 } txe_dtype;

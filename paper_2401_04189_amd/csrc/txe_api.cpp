@@ -52,6 +52,11 @@ struct DevTables {
   std::vector<void *> owned;
 };
 
+struct DevBf {
+  BfTables t{};
+  std::vector<void *> owned;
+};
+
 struct txe_system {
   txe_context *ctx = nullptr;
   int device = 0;
@@ -62,6 +67,7 @@ struct txe_system {
   std::vector<double> Chat[3];   // K x r x r
   DevTables<double> t64;
   DevTables<float> t32;
+  DevBf tbf;
   double *qdev[3] = {nullptr, nullptr, nullptr};
 };
 
@@ -311,6 +317,67 @@ static void build_tables(const txe_system &S, HostTables &H, bool f64) {
         }
 }
 
+// bf16 bit pattern of a double, rounded to nearest even (through float)
+static unsigned short bf16_bits(double x) {
+  float f = (float)x;
+  unsigned u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+static double bf16_value(unsigned short b) {
+  unsigned u = (unsigned)b << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+// three bf16 parts of x: p0 = bf16(x), p1 = bf16(x - p0), p2 = bf16(x - p0 - p1)
+static void split3(double x, unsigned short (&o)[3]) {
+  double r = x;
+  for (int sp = 0; sp < 3; ++sp) {
+    o[sp] = bf16_bits(r);
+    r -= bf16_value(o[sp]);
+  }
+}
+
+// Split-bf16 term matrices of the core kernel (layouts in BfTables).
+static void build_bf_tables(const txe_system &S, std::vector<unsigned short> &C1, std::vector<unsigned short> &C2,
+                            int &nC) {
+  const Dims &D = S.D;
+  const int MT = D.MT1, RP = D.rp1;
+  nC = (RP + 31) / 32;
+  auto Ch = [&](int d, int k, int p, int q) -> double { return S.Chat[d][((size_t)k * S.r[d] + p) * S.r[d] + q]; };
+  C1.assign((size_t)D.Kp * MT * 3 * nC * 512, 0);
+  C2.assign((size_t)D.Kp * 3 * MT * nC * 512, 0);
+  unsigned short part[3];
+  for (int k = 0; k < D.K; ++k)
+    for (int c = 0; c < nC; ++c)
+      for (int l = 0; l < 64; ++l)
+        for (int i = 0; i < 8; ++i) {
+          const int kk = 8 * (l >> 4) + i;
+          // B operand of the beta contraction: Chat1_k[beta' = 16 bt + n][beta = 32 c + kk]
+          for (int bt = 0; bt < MT; ++bt) {
+            const int bp = 16 * bt + (l & 15), be = 32 * c + kk;
+            if (bp < D.r1 && be < D.r1) {
+              split3(Ch(1, k, bp, be), part);
+              for (int sp = 0; sp < 3; ++sp)
+                C1[(((((size_t)k * MT + bt) * 3 + sp) * nC + c) * 64 + l) * 8 + i] = part[sp];
+            }
+          }
+          // A operand of the gamma contraction: Chat2_k[gamma' = 16 mtp + m][gamma(c, kk)]
+          const int g = 16 * (2 * c + (i >> 2)) + 4 * (l >> 4) + (i & 3);
+          for (int mtp = 0; mtp < MT; ++mtp) {
+            const int gp = 16 * mtp + (l & 15);
+            if (gp < D.r2 && g < D.r2) {
+              split3(Ch(2, k, gp, g), part);
+              for (int sp = 0; sp < 3; ++sp)
+                C2[(((((size_t)k * 3 + sp) * MT + mtp) * nC + c) * 64 + l) * 8 + i] = part[sp];
+            }
+          }
+        }
+}
+
 template <typename T>
 static txe_status upload_tables(DevTables<T> &dt, const HostTables &H, hipStream_t s) {
   txe_status st;
@@ -337,6 +404,7 @@ extern "C" txe_status txe_system_destroy(txe_system *sys) {
   hipSetDevice(sys->device);
   free_tables(sys->t64);
   free_tables(sys->t32);
+  for (void *p : sys->tbf.owned) hipFree(p);
   for (int d = 0; d < 3; ++d)
     if (sys->qdev[d]) hipFree(sys->qdev[d]);
   delete sys;
@@ -431,6 +499,25 @@ extern "C" txe_status txe_system_create(txe_context *ctx, const txe_system_desc 
     txe_system_destroy(S);
     return st;
   }
+  {
+    std::vector<unsigned short> C1, C2;
+    int nC = 0;
+    build_bf_tables(*S, C1, C2, nC);
+    const std::vector<unsigned short> *src[2] = {&C1, &C2};
+    for (int t = 0; t < 2; ++t) {
+      void *p = nullptr;
+      if (hipMalloc(&p, src[t]->size() * 2) != hipSuccess ||
+          hipMemcpy(p, src[t]->data(), src[t]->size() * 2, hipMemcpyHostToDevice) != hipSuccess) {
+        if (p) hipFree(p);
+        txe_system_destroy(S);
+        return fail(TXE_ERR_DEVICE, "upload of the bf16 tables failed");
+      }
+      S->tbf.owned.push_back(p);
+    }
+    S->tbf.t.C1 = (const unsigned short *)S->tbf.owned[0];
+    S->tbf.t.C2 = (const unsigned short *)S->tbf.owned[1];
+    S->tbf.t.nC = nC;
+  }
   for (int d = 0; d < 3; ++d) {
     void *p = nullptr;
     if (hipMalloc(&p, S->n[d] * sizeof(double)) != hipSuccess ||
@@ -519,9 +606,9 @@ static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, Plan
 static txe_status validate_args(const txe_context *ctx, const txe_system *sys, const txe_apply_args *a) {
   if (!ctx || !sys || !a) return fail(TXE_ERR_ARG, "null argument");
   if (sys->device != ctx->device) return fail(TXE_ERR_ARG, "system and context are on different devices");
-  if (a->compute != TXE_COMPUTE_F64 && a->compute != TXE_COMPUTE_F32 && a->compute != TXE_COMPUTE_BF16X3)
+  if (a->compute != TXE_COMPUTE_F64 && a->compute != TXE_COMPUTE_F32 && a->compute != TXE_COMPUTE_BF16X3 &&
+      a->compute != TXE_COMPUTE_BF16X6)
     return fail(TXE_ERR_ARG, "unknown compute %d", a->compute);
-  if (a->compute == TXE_COMPUTE_BF16X3) return fail(TXE_ERR_UNSUPPORTED, "BF16X3 compute is not built yet");
   if (a->dtype != TXE_DTYPE_F64 && a->dtype != TXE_DTYPE_F32) return fail(TXE_ERR_ARG, "unknown dtype %d", a->dtype);
   if (a->compute == TXE_COMPUTE_F64 && a->dtype != TXE_DTYPE_F64)
     return fail(TXE_ERR_ARG, "FP64 compute requires FP64 orbitals");
@@ -605,7 +692,11 @@ extern "C" txe_status txe_apply(txe_context *ctx, const txe_system *sys, const t
     } else {
       ChunkArgs<float> c = chunk_args<float>(sys, args, pl, ws);
       c.pm.p0 = p0; c.P = P; c.t_begin = tb; c.t_count = tcnt;
-      e = run_chunk_f32(sys->t32.t, c, psi64, pl.want_vx, ctx->stream, &ctx->prof);
+      if (args->compute == TXE_COMPUTE_F32)
+        e = run_chunk_f32(sys->t32.t, c, psi64, pl.want_vx, ctx->stream, &ctx->prof);
+      else
+        e = run_chunk_bf16(sys->t32.t, sys->tbf.t, args->compute == TXE_COMPUTE_BF16X3 ? 2 : 3, c, psi64,
+                           pl.want_vx, ctx->stream, &ctx->prof);
     }
   }
   if (e == hipSuccess)

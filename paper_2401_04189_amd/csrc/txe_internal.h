@@ -57,6 +57,20 @@ struct Tables {
   T *U1chain;   // [nb1/16][MT1][4][64]  U1[b][beta]
 };
 
+// Split-bf16 copies of the core kernel's term matrices (bf16 bit patterns).
+// Each FP64 value x is split into up to three bf16 parts, x ~ p0 + p1 + p2
+// (p0 = bf16(x), p1 = bf16(x - p0), p2 = bf16(x - p0 - p1)); a two-part
+// product keeps p0q0 + p0q1 + p1q0, a three-part one adds p0q2 + p1q1 + p2q0.
+// K = 32 MFMA fragments hold 8 values per lane: lane l, element i is
+// k = 8*(l/16) + i, m or n = l % 16.
+struct BfTables {
+  const unsigned short *C1;   // [Kp][MT][3][nC][64][8]: B operand, Chat1_k[beta' = 16 bt + n][beta = 32 c + k]
+  const unsigned short *C2;   // [Kp][3][MT][nC][64][8]: A operand, Chat2_k[gamma' = 16 mtp + m][gamma(c, k)],
+                              //   gamma(c, k) = 16 (2c + i/4) + 4 (l/16) + i%4 (the row order of two
+                              //   f32 accumulator tiles)
+  int nC;                     // ceil(rp / 32)
+};
+
 // Everything one chunk of pairs needs.
 template <typename T>
 struct ChunkArgs {
@@ -146,6 +160,10 @@ hipError_t run_chunk_f64(const Tables<double> &tb, const ChunkArgs<double> &a, b
                          Prof *prof);
 hipError_t run_chunk_f32(const Tables<float> &tb, const ChunkArgs<float> &a, bool psi_f64, bool want_vx,
                          hipStream_t s, Prof *prof);
+// FP32 projection and back-projection with the core kernel sum in split bf16
+// products (nsplit = 2: three products, 3: six products).
+hipError_t run_chunk_bf16(const Tables<float> &tb, const BfTables &bt, int nsplit, const ChunkArgs<float> &a,
+                          bool psi_f64, bool want_vx, hipStream_t s, Prof *prof);
 // E_x = sum_p c_p e_pair[p] (fixed order), and an optional copy of e_pair.
 hipError_t run_energy(const double *epair, long long npairs, int symmetric, int N, double *ex, double *e_out,
                       hipStream_t s, Prof *prof);

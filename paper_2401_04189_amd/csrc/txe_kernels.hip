@@ -230,6 +230,79 @@ __global__ __launch_bounds__(256) void k_proj3(const T *__restrict__ T2, Dims D,
   }
 }
 
+// Epilogue shared by the core kernels: the pair-energy partial
+// sum Phi[alpha'][gamma'][beta'] G[alpha'][beta'][gamma'] (FP64, fixed order)
+// and the first back-projection S1[a][gamma'][beta'] = sum_alpha' U0[a][alpha'] Phi[alpha'][gamma'][beta'],
+// chained on the Phi accumulators.
+template <typename T, int MT, int NGW, bool WRITE_S1>
+__device__ __forceinline__ void core_epilogue(typename MF<T>::acc (&Phi)[MT][NGW], const T *__restrict__ Gp, const Dims &D,
+                                              int p, int bt, int gs, int NGS, int wg_lo, int wg_hi, int lane, int lr,
+                                              int lg, int wave, const Tables<T> &tb, T *__restrict__ S1,
+                                              double *__restrict__ epart) {
+  using M = MF<T>;
+  using acc = typename M::acc;
+  constexpr int RP = 16 * MT;
+  __shared__ double red[4];
+  double e = 0.0;
+  const int bp = 16 * bt + lr;
+#pragma unroll
+  for (int ng = 0; ng < NGW; ++ng) {
+    const int gp = wg_lo + ng;
+    if (gp < wg_hi && bp < D.r1) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ap = 16 * mt + drow<T>(lg, v);
+            if (ap < D.r0) e += (double)Phi[mt][ng][v] * (double)Gp[((size_t)ap * RP + bp) * RP + gp];
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  if (lane == 0) red[wave] = e;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    epart[((size_t)p * MT + bt) * NGS + gs] = ((red[0] + red[1]) + (red[2] + red[3]));
+
+  // ---- S1[p][a][gamma'][beta'] = sum_alpha' U0[a][alpha'] Phi[alpha'][gamma'][beta']
+  if (WRITE_S1) {
+    const int nat = D.na0 >> 4;
+    for (int ma = 0; ma < nat; ++ma) {
+      T uf[MT][4];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          uf[mt][v] = tb.U0chain[(((size_t)ma * MT + mt) * 4 + v) * 64 + lane];
+#pragma unroll
+      for (int ng = 0; ng < NGW; ++ng) {
+        const int gp = wg_lo + ng;
+        if (gp < wg_hi) {
+          acc S = zero4<acc>();
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) S = M::mma(uf[mt][v], Phi[mt][ng][v], S);
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int a = 16 * ma + drow<T>(lg, v);
+            if (a < D.n0) S1[(((size_t)p * D.n0 + a) * RP + gp) * RP + bp] = S[v];
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+}
+
 // -------------------------------------------------------------------------------------
 // core: per workgroup one pair p, one 16-wide tile bt of beta' and a range of
 // gamma' (split gs of NGS).  Input slabs alpha form the outer loop; the
@@ -255,7 +328,6 @@ __global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D
   constexpr int RP = 16 * MT;
   constexpr size_t F = (size_t)RP * RP;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[4];
 
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
@@ -429,65 +501,192 @@ __global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D
     if constexpr (PF) cur = nxt;
   }
 
-  // ---- pair-energy partial: sum Phi[alpha'][gamma'][beta'] G[alpha'][beta'][gamma']
-  double e = 0.0;
-  const int bp = 16 * bt + lr;
+  core_epilogue<T, MT, NGW, WRITE_S1>(Phi, Gp, D, p, bt, gs, NGS, wg_lo, wg_hi, lane, lr, lg, wave, tb, S1, epart);
+}
+
+// -------------------------------------------------------------------------------------
+// core, split-bf16 form: the same loop as k_core<float>, with the two chained
+// contractions of phase A (over beta, then gamma) done on bf16 MFMA (16x16x32)
+// with split operands and FP32 accumulation: every operand x is taken as
+// p0 + p1 (+ p2) in bf16 and each product keeps the terms p_i q_j with
+// i + j < NS.  The accumulation of phase B stays FP32 MFMA.
+// -------------------------------------------------------------------------------------
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+template <int NS>
+__device__ __forceinline__ void split8(const float (&x)[8], bf8 (&o)[NS]) {
+  float r[8];
 #pragma unroll
-  for (int ng = 0; ng < NGW; ++ng) {
-    const int gp = wg_lo + ng;
-    if (gp < wg_hi && bp < D.r1) {
+  for (int i = 0; i < 8; ++i) r[i] = x[i];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        {
+  for (int sp = 0; sp < NS; ++sp) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int ap = 16 * mt + drow<T>(lg, v);
-            if (ap < D.r0) e += (double)Phi[mt][ng][v] * (double)Gp[((size_t)ap * RP + bp) * RP + gp];
+    for (int i = 0; i < 8; ++i) {
+      const __bf16 h = (__bf16)r[i];
+      o[sp][i] = h;
+      if (sp + 1 < NS) r[i] -= (float)h;
+    }
+  }
+}
+
+template <int NS>
+__device__ __forceinline__ f4 mma_split(const bf8 (&a)[NS], const bf8 (&b)[NS], f4 c) {
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int j = 0; j < NS - i; ++j) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], c, 0, 0, 0);
+  return c;
+}
+
+__device__ __forceinline__ bf8 ld_bf8(const unsigned short *p) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  const u4 v = *reinterpret_cast<const u4 *>(p);
+  bf8 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+
+template <int MT, int NGW, int NS, bool WRITE_S1>
+__global__ __launch_bounds__(256, 1) void k_core_bf(const float *__restrict__ G, Dims D, int P, int NGS,
+                                                    Tables<float> tb, BfTables bft, float *__restrict__ S1,
+                                                    double *__restrict__ epart) {
+  using M = MF<float>;
+  using acc = f4;
+  constexpr int RP = 16 * MT;
+  constexpr size_t F = (size_t)RP * RP;
+  constexpr int NC = (RP + 31) / 32;              // K = 32 chunks of the core size
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gs = blockIdx.x % NGS;
+  const int tt = blockIdx.x / NGS;
+  const int bt = tt % MT;
+  const int p = tt / MT;
+  if (p >= P) return;
+
+  const int gper = (D.r2 + NGS - 1) / NGS;
+  const int g_lo = gs * gper;
+  const int g_hi = min(D.r2, g_lo + gper);
+  const int gw = (gper + 3) >> 2;
+  const int wg_lo = g_lo + wave * gw;
+  const int wg_hi = min(g_hi, wg_lo + gw);
+  const float *Gp = G + (size_t)p * RP * F;
+  float *Zs = reinterpret_cast<float *>(smem_raw);
+  const int zsz = 4 * gper * 16;
+
+  acc Phi[MT][NGW];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ng = 0; ng < NGW; ++ng) Phi[mt][ng] = zero4<acc>();
+
+  constexpr bool HOLD_G = MT <= 3;
+  bf8 gsp[HOLD_G ? MT : 1][HOLD_G ? NC : 1][NS];
+  const float *Ga = Gp + lr;
+  // A fragment (m = gamma = 16 mg + lr, k = beta = 32 c + 8 lg + i) of the slab, split
+  auto load_g = [&](int mg, int c, bf8 (&o)[NS]) {
+    float x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int beta = 32 * c + 8 * lg + i;
+      x[i] = (beta < RP) ? Ga[beta * RP + 16 * mg] : 0.f;
+    }
+    split8<NS>(x, o);
+  };
+
+  const int nkq = (D.K + 3) >> 2;
+  const int nsteps = D.r0 * nkq;
+  for (int step = 0; step < nsteps; ++step) {
+    const int alpha = step / nkq;
+    const int kq = step - alpha * nkq;
+    const int k = 4 * kq + wave;
+    if (kq == 0) {
+      Ga = Gp + (size_t)alpha * F + lr;
+      if constexpr (HOLD_G) {
+#pragma unroll
+        for (int mg = 0; mg < MT; ++mg)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) load_g(mg, c, gsp[mg][c]);
+      }
+    }
+    float *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * gper * 16;
+    if (k < D.K) {
+      // ---- W[gamma][beta'] = sum_beta G[alpha][beta][gamma] Chat1_k[beta'][beta]
+      bf8 cb[NC][NS];
+      const unsigned short *c1 = bft.C1 + (((size_t)k * MT + bt) * 3) * NC * 512 + lane * 8;
+#pragma unroll
+      for (int sp = 0; sp < NS; ++sp)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) cb[c][sp] = ld_bf8(c1 + ((size_t)sp * NC + c) * 512);
+      acc W[MT];
+#pragma unroll
+      for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+#pragma unroll
+        for (int mg = 0; mg < MT; ++mg) {
+          if constexpr (HOLD_G) {
+            W[mg] = mma_split<NS>(gsp[mg][c], cb[c], W[mg]);
+          } else {
+            bf8 g[NS];
+            load_g(mg, c, g);
+            W[mg] = mma_split<NS>(g, cb[c], W[mg]);
           }
         }
       }
+      // ---- Z[gamma'][beta'] = sum_gamma Chat2_k[gamma'][gamma] W[gamma][beta'], two W tiles per K = 32
+      bf8 wsp[NC][NS];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        float x[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          x[i] = W[2 * c][i];
+          x[4 + i] = (2 * c + 1 < MT) ? W[(2 * c + 1 < MT) ? 2 * c + 1 : 0][i] : 0.f;
+        }
+        split8<NS>(x, wsp[c]);
+      }
+      const unsigned short *c2 = bft.C2 + (size_t)k * 3 * MT * NC * 512 + lane * 8;
+#pragma unroll
+      for (int mtp = 0; mtp < MT; ++mtp) {
+        acc Z = zero4<acc>();
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          bf8 a[NS];
+#pragma unroll
+          for (int sp = 0; sp < NS; ++sp) a[sp] = ld_bf8(c2 + (((size_t)sp * MT + mtp) * NC + c) * 512);
+          Z = mma_split<NS>(a, wsp[c], Z);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gp = 16 * mtp + 4 * lg + v;
+          if (gp >= g_lo && gp < g_hi) Zw[(gp - g_lo) * 16 + lr] = Z[v];
+        }
+      }
+    } else {
+      for (int idx = lane; idx < gper * 16; idx += 64) Zw[idx] = 0.f;
     }
-    __builtin_amdgcn_sched_barrier(0);
-  }
+    __syncthreads();
+    // ---- phase B (FP32 MFMA): Phi += sum_{k in step} w_k Chat0_k[alpha'][alpha] Z_k
+    {
+      const int kk = 4 * kq + lg;
+      float af[MT];
+      const float *ah = tb.Ahat + ((size_t)alpha * D.Kp + kk) * RP + lr;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
-  if (lane == 0) red[wave] = e;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    epart[((size_t)p * MT + bt) * NGS + gs] = ((red[0] + red[1]) + (red[2] + red[3]));
-
-  // ---- S1[p][a][gamma'][beta'] = sum_alpha' U0[a][alpha'] Phi[alpha'][gamma'][beta']
-  if (WRITE_S1) {
-    const int nat = D.na0 >> 4;
-    for (int ma = 0; ma < nat; ++ma) {
-      T uf[MT][4];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          uf[mt][v] = tb.U0chain[(((size_t)ma * MT + mt) * 4 + v) * 64 + lane];
+      for (int mt = 0; mt < MT; ++mt) af[mt] = ah[16 * mt];
+      const float *zrow = Zs + (size_t)(step & 1) * zsz + (size_t)lg * gper * 16 + lr;
 #pragma unroll
       for (int ng = 0; ng < NGW; ++ng) {
-        const int gp = wg_lo + ng;
-        if (gp < wg_hi) {
-          acc S = zero4<acc>();
+        const int row = min(wg_lo - g_lo + ng, gper - 1);
+        const float bz = zrow[row * 16];
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            {
-#pragma unroll
-              for (int v = 0; v < 4; ++v) S = M::mma(uf[mt][v], Phi[mt][ng][v], S);
-            }
-          }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int a = 16 * ma + drow<T>(lg, v);
-            if (a < D.n0) S1[(((size_t)p * D.n0 + a) * RP + gp) * RP + bp] = S[v];
-          }
-        }
-        __builtin_amdgcn_sched_barrier(0);
+        for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(af[mt], bz, Phi[mt][ng]);
       }
     }
   }
+  core_epilogue<float, MT, NGW, WRITE_S1>(Phi, Gp, D, p, bt, gs, NGS, wg_lo, wg_hi, lane, lr, lg, wave, tb, S1,
+                                           epart);
 }
 
 // -------------------------------------------------------------------------------------
@@ -701,6 +900,34 @@ hipError_t launch_core(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx,
   return hipErrorInvalidValue;
 }
 
+template <int MT, int NGW, int NS>
+hipError_t launch_core_bf_mt(const Tables<float> &tb, const BfTables &bft, const ChunkArgs<float> &a, bool want_vx,
+                             hipStream_t s) {
+  const int gper = (a.D.r2 + a.NGS - 1) / a.NGS;
+  const size_t lds = (2 * 4 * (size_t)gper * 16) * sizeof(float);
+  const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
+  if (want_vx)
+    hipLaunchKernelGGL((k_core_bf<MT, NGW, NS, true>), dim3(nb), dim3(256), lds, s, (const float *)a.G, a.D, a.P,
+                       a.NGS, tb, bft, a.S1, a.epart);
+  else
+    hipLaunchKernelGGL((k_core_bf<MT, NGW, NS, false>), dim3(nb), dim3(256), lds, s, (const float *)a.G, a.D, a.P,
+                       a.NGS, tb, bft, a.S1, a.epart);
+  return hipGetLastError();
+}
+
+template <int NS>
+hipError_t launch_core_bf(const Tables<float> &tb, const BfTables &bft, const ChunkArgs<float> &a, bool want_vx,
+                          hipStream_t s) {
+  switch (a.D.MT0) {
+    case 1: return launch_core_bf_mt<1, NGW32[1], NS>(tb, bft, a, want_vx, s);
+    case 2: return launch_core_bf_mt<2, NGW32[2], NS>(tb, bft, a, want_vx, s);
+    case 3: return launch_core_bf_mt<3, NGW32[3], NS>(tb, bft, a, want_vx, s);
+    case 4: return launch_core_bf_mt<4, NGW32[4], NS>(tb, bft, a, want_vx, s);
+    case 5: return launch_core_bf_mt<5, NGW32[5], NS>(tb, bft, a, want_vx, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T, typename Tin, int NCG>
 hipError_t launch_back_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
   const int nct = a.D.nc2 >> 4, nbt = a.D.nb1 >> 4;
@@ -728,7 +955,8 @@ hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s
 }
 
 template <typename T, typename Tin>
-hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s, Prof *prof) {
+hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s, Prof *prof,
+                       const BfTables *bft = nullptr, int nsplit = 0) {
   constexpr int GT = 2, FT = 4;
   hipError_t e;
   {
@@ -749,7 +977,13 @@ hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx,
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   prof->begin(K_CORE, s);
-  e = launch_core<T>(tb, a, want_vx, s);
+  if constexpr (sizeof(T) == 4) {
+    if (nsplit == 2) e = launch_core_bf<2>(tb, *bft, a, want_vx, s);
+    else if (nsplit == 3) e = launch_core_bf<3>(tb, *bft, a, want_vx, s);
+    else e = launch_core<T>(tb, a, want_vx, s);
+  } else {
+    e = launch_core<T>(tb, a, want_vx, s);
+  }
   prof->end(s);
   if (e != hipSuccess) return e;
   {
@@ -781,6 +1015,12 @@ hipError_t run_chunk_f32(const Tables<float> &tb, const ChunkArgs<float> &a, boo
                          hipStream_t s, Prof *prof) {
   if (psi_f64) return run_chunk_t<float, double>(tb, a, want_vx, s, prof);
   return run_chunk_t<float, float>(tb, a, want_vx, s, prof);
+}
+
+hipError_t run_chunk_bf16(const Tables<float> &tb, const BfTables &bft, int nsplit, const ChunkArgs<float> &a,
+                          bool psi_f64, bool want_vx, hipStream_t s, Prof *prof) {
+  if (psi_f64) return run_chunk_t<float, double>(tb, a, want_vx, s, prof, &bft, nsplit);
+  return run_chunk_t<float, float>(tb, a, want_vx, s, prof, &bft, nsplit);
 }
 
 hipError_t run_energy(const double *epair, long long npairs, int symmetric, int N, double *ex, double *e_out,

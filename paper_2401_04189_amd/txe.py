@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtxe.so")
 
-COMPUTE = {"f64": 0, "f32": 1, "bf16x3": 2}
+COMPUTE = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16x6": 3}
 DTYPE = {"f64": 0, "f32": 1}
 
 _c_int = ctypes.c_int32

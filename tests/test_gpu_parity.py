@@ -127,6 +127,23 @@ def test_f32_rank_tiles_against_f64(ctx):
         assert abs(e32 - e64) <= 1e-5 and perr <= 1e-5 and verr <= 1e-5
 
 
+@pytest.mark.parametrize("form,tol", [("bf16x6", 1e-5), ("bf16x3", 2e-4)])
+def test_bf16_split_against_f64(ctx, form, tol):
+    """Split-bf16 core kernel sums (three- or two-part operands) against the
+    GPU FP64 path, every rank-tile variant.  The three-product form keeps
+    ~16 bits per operand (2^-16 relative per product), the six-product form
+    ~24 (FP32 level)."""
+    for r in (20, 40, 48, 70):
+        s = W.small_system(n=(max(24, r) + 3) // 4 * 4, L=6.0, N=2, r=r, K=10, seed=35)
+        v64, e64, p64 = run_gpu(ctx, s, "f64")
+        vb, eb, pb = run_gpu(ctx, s, form)
+        verr = rel_vx_err(vb, v64, s.grid.q)
+        perr = np.abs(pb - p64).max() / np.abs(p64).max()
+        print(f"[{form} r={r}] |dE_x| {abs(eb - e64):.3e} Ha (of {abs(e64):.3f})  e_ij rel {perr:.3e}  "
+              f"Vx rel {verr:.3e}", flush=True)
+        assert abs(eb - e64) <= tol * abs(e64) and perr <= tol and verr <= tol
+
+
 def test_f32_block_chunked(ctx, monkeypatch):
     """Block mode split into several target chunks (forced by a small
     workspace limit) gives the same result as one chunk, in both precisions."""
