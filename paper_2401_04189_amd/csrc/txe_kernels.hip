@@ -20,6 +20,8 @@
 //            four accumulator entries (measured on gfx950)
 // so an accumulator whose rows are the next contraction index feeds the next
 // MFMA as its B operand directly, one entry v at a time ("chained").
+#include <algorithm>
+
 #include "txe_internal.h"
 
 namespace txe {
@@ -90,16 +92,31 @@ __device__ __forceinline__ void pair_ij(const PairMap &pm, long long pg, int &i,
 // proj12: T2[p][a][beta][gamma] = sum_b V1[b][beta] sum_c psi_i[a,b,c] psi_j[a,b,c] V2[c][gamma]
 // one wavefront per (pair, a-slab, group of GT gamma tiles)
 // -------------------------------------------------------------------------------------
-template <typename T, typename Tin, int GT>
+template <typename T, typename Tin, int GT, bool LDS_TAB>
 __global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dims D, PairMap pm, int P,
                                                 Tables<T> tb, T *__restrict__ T2) {
   using M = MF<T>;
   using acc = typename M::acc;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
   const int ngg = (D.MT2 + GT - 1) / GT;
-  const long long item = (long long)blockIdx.x * 4 + wave;
-  if (item >= (long long)P * D.n0 * ngg) return;
+  const int nbt = D.nb1 >> 4, nct = D.nc2 >> 4;
+  // the shared operands (V2 and the chained V1 fragments) are staged once per
+  // workgroup; the workgroup then walks its items
+  const T *V2 = tb.V2B, *V1c = tb.V1chain;
+  if constexpr (LDS_TAB) {
+    T *s2 = reinterpret_cast<T *>(smem_raw);
+    T *s1 = s2 + (size_t)D.nc2 * D.rp2;
+    const int m2 = D.nc2 * D.rp2, m1 = D.MT1 * nbt * 256;
+    for (int idx = threadIdx.x; idx < m2; idx += 256) s2[idx] = tb.V2B[idx];
+    for (int idx = threadIdx.x; idx < m1; idx += 256) s1[idx] = tb.V1chain[idx];
+    __syncthreads();
+    V2 = s2;
+    V1c = s1;
+  }
+  const long long total = (long long)P * D.n0 * ngg;
+  for (long long item = (long long)blockIdx.x * 4 + wave; item < total; item += (long long)gridDim.x * 4) {
   const int gg = (int)(item % ngg);
   const long long rest = item / ngg;
   const int a = (int)(rest % D.n0);
@@ -117,7 +134,6 @@ __global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dim
 #pragma unroll
     for (int gt = 0; gt < GT; ++gt) T2a[mt][gt] = zero4<acc>();
 
-  const int nbt = D.nb1 >> 4, nct = D.nc2 >> 4;
   for (int mb = 0; mb < nbt; ++mb) {
     acc T1[GT];
 #pragma unroll
@@ -135,7 +151,7 @@ __global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dim
       }
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        const T *vrow = tb.V2B + (size_t)(c + jj) * D.rp2 + 16 * g0 + lr;
+        const T *vrow = V2 + (size_t)(c + jj) * D.rp2 + 16 * g0 + lr;
         const T rho = (T)x[jj];
 #pragma unroll
         for (int gt = 0; gt < GT; ++gt)
@@ -147,7 +163,7 @@ __global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dim
       if (mt < D.MT1) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const T af = tb.V1chain[(((size_t)mt * nbt + mb) * 4 + v) * 64 + lane];
+          const T af = V1c[(((size_t)mt * nbt + mb) * 4 + v) * 64 + lane];
 #pragma unroll
           for (int gt = 0; gt < GT; ++gt)
             if (g0 + gt < D.MT2) T2a[mt][gt] = M::mma(af, T1[gt][v], T2a[mt][gt]);
@@ -171,6 +187,7 @@ __global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dim
         }
       }
     }
+  }
   }
 }
 
@@ -696,7 +713,7 @@ __global__ __launch_bounds__(256, 1) void k_core_bf(const float *__restrict__ G,
 //   acc[b][c]  += psi_s[a][b][c] phi[b][c]
 // then Vx psi_t[a][b][c] = -scale * acc (times w(r) when weighted).
 // -------------------------------------------------------------------------------------
-template <typename T, typename Tin, int NBT, int NCG>
+template <typename T, typename Tin, int NBT, int NCG, bool LDS_TAB>
 __global__ __launch_bounds__(256) void k_back(const T *__restrict__ S1, const Tin *__restrict__ psi, Dims D,
                                               PairMap pm, int N, int t_begin, int t_count, Tables<T> tb,
                                               Tin *__restrict__ vx, const double *__restrict__ out_scale,
@@ -704,12 +721,25 @@ __global__ __launch_bounds__(256) void k_back(const T *__restrict__ S1, const Ti
                                               const double *__restrict__ q1, const double *__restrict__ q2) {
   using M = MF<T>;
   using acc = typename M::acc;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
   const int nct = D.nc2 >> 4, nbt = D.nb1 >> 4;
   const int ncg = (nct + NCG - 1) / NCG;
-  const long long item = (long long)blockIdx.x * 4 + wave;
-  if (item >= (long long)t_count * D.n0 * ncg) return;
+  // shared operands (U2^T and the chained U1 fragments) staged once per workgroup
+  const T *U2t = tb.U2T, *U1c = tb.U1chain;
+  if constexpr (LDS_TAB) {
+    T *s2 = reinterpret_cast<T *>(smem_raw);
+    T *s1 = s2 + (size_t)D.rp2 * D.nc2;
+    const int m2 = D.rp2 * D.nc2, m1 = nbt * D.MT1 * 256;
+    for (int idx = threadIdx.x; idx < m2; idx += 256) s2[idx] = tb.U2T[idx];
+    for (int idx = threadIdx.x; idx < m1; idx += 256) s1[idx] = tb.U1chain[idx];
+    __syncthreads();
+    U2t = s2;
+    U1c = s1;
+  }
+  const long long total = (long long)t_count * D.n0 * ncg;
+  for (long long item = (long long)blockIdx.x * 4 + wave; item < total; item += (long long)gridDim.x * 4) {
   const int cgi = (int)(item % ncg);
   const long long rest = item / ncg;
   const int a = (int)(rest % D.n0);
@@ -745,7 +775,7 @@ __global__ __launch_bounds__(256) void k_back(const T *__restrict__ S1, const Ti
       T bu[NCG];
 #pragma unroll
       for (int cg = 0; cg < NCG; ++cg)
-        bu[cg] = (gv && c0 + cg < nct) ? tb.U2T[(size_t)gam * D.nc2 + 16 * (c0 + cg) + lr] : (T)0;
+        bu[cg] = (gv && c0 + cg < nct) ? U2t[(size_t)gam * D.nc2 + 16 * (c0 + cg) + lr] : (T)0;
       const T *srow = S + (size_t)gam * D.rp1;
 #pragma unroll
       for (int mb = 0; mb < MAX_MT; ++mb) {
@@ -768,7 +798,7 @@ __global__ __launch_bounds__(256) void k_back(const T *__restrict__ S1, const Ti
           if (mbe < D.MT1) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const T af = tb.U1chain[(((size_t)mbb * D.MT1 + mbe) * 4 + v) * 64 + lane];
+              const T af = U1c[(((size_t)mbb * D.MT1 + mbe) * 4 + v) * 64 + lane];
 #pragma unroll
               for (int cg = 0; cg < NCG; ++cg) ph[cg] = M::mma(af, X[mbe][cg][v], ph[cg]);
             }
@@ -809,6 +839,7 @@ __global__ __launch_bounds__(256) void k_back(const T *__restrict__ S1, const Ti
         }
       }
     }
+  }
   }
 }
 
@@ -935,9 +966,20 @@ hipError_t launch_back_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream
   const unsigned nb = blocks_for(waves);
   const Tin *psi = (const Tin *)a.psi;
   Tin *vx = (Tin *)a.vx;
-#define TXE_BACK(NBTV)                                                                                     \
-  hipLaunchKernelGGL((k_back<T, Tin, NBTV, NCG>), dim3(nb), dim3(256), 0, s, a.S1, psi, a.D, a.pm, a.N,      \
-                     a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1], a.qdev[2])
+  // shared operands in LDS when they fit in 64 KiB; the grid is then capped
+  // and each workgroup walks several items
+  const size_t tab = ((size_t)a.D.rp2 * a.D.nc2 + (size_t)nbt * a.D.MT1 * 256) * sizeof(T);
+  const bool lds_tab = tab <= 64 * 1024;
+  const unsigned nbl = lds_tab ? std::min(nb, 2048u) : nb;
+#define TXE_BACK(NBTV)                                                                                         \
+  if (lds_tab)                                                                                                   \
+    hipLaunchKernelGGL((k_back<T, Tin, NBTV, NCG, true>), dim3(nbl), dim3(256), tab, s, a.S1, psi, a.D, a.pm,  \
+                       a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1],         \
+                       a.qdev[2]);                                                                               \
+  else                                                                                                           \
+    hipLaunchKernelGGL((k_back<T, Tin, NBTV, NCG, false>), dim3(nb), dim3(256), 0, s, a.S1, psi, a.D, a.pm,    \
+                       a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1],         \
+                       a.qdev[2])
   if (nbt <= 2) TXE_BACK(2);
   else if (nbt <= 4) TXE_BACK(4);
   else if (nbt <= 6) TXE_BACK(6);
@@ -961,9 +1003,15 @@ hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx,
   hipError_t e;
   {
     const int ngg = (a.D.MT2 + GT - 1) / GT;
+    const unsigned nb = blocks_for((long long)a.P * a.D.n0 * ngg);
+    const size_t tab = ((size_t)a.D.nc2 * a.D.rp2 + (size_t)a.D.MT1 * (a.D.nb1 >> 4) * 256) * sizeof(T);
     prof->begin(K_PROJ12, s);
-    hipLaunchKernelGGL((k_proj12<T, Tin, GT>), dim3(blocks_for((long long)a.P * a.D.n0 * ngg)), dim3(256), 0, s,
-                       (const Tin *)a.psi, a.D, a.pm, a.P, tb, a.T2);
+    if (tab <= 64 * 1024)
+      hipLaunchKernelGGL((k_proj12<T, Tin, GT, true>), dim3(std::min(nb, 2048u)), dim3(256), tab, s,
+                         (const Tin *)a.psi, a.D, a.pm, a.P, tb, a.T2);
+    else
+      hipLaunchKernelGGL((k_proj12<T, Tin, GT, false>), dim3(nb), dim3(256), 0, s, (const Tin *)a.psi, a.D, a.pm,
+                         a.P, tb, a.T2);
     prof->end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
