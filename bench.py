@@ -10,6 +10,11 @@ E_x is within 1e-5 Ha of the FP64 form, which is timed beside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2]
 
+`--config cfg5` times the batched workload instead: 24 uneven systems
+(grids 48^3..96^3, 10..120 orbitals, r = 24..64, K = 40) as one captured
+graph replay against 24 separate applies, FP32 MFMA, with every system's
+E_x checked against its FP64 form.
+
 Prints one JSON line.  Per-kernel durations come from HIP events the library
 records on its own stream around every launch (txe_profile_*).
 """
@@ -29,6 +34,7 @@ METRIC = "pair convolutions/s for Vx psi, MFMA-FP32 vs FP64 at dE_x<=1e-5 Ha; % 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 KERNEL_SRC = os.path.join(ROOT, "paper_2401_04189_amd", "csrc", "txe_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_core.json")
+TUNE_CACHE = os.path.join(ROOT, "paper_2401_04189_amd", "tuned_shapes.json")
 
 
 def flops_per_pair(n, r, K):
@@ -80,6 +86,98 @@ def time_leg(txe, torch, ctx, sysm, psi, vx, compute, steps, warmup, symmetric, 
     return wall, float(ex.item()), kt
 
 
+def shapes(args, txe, ctx, sysm, psi, compute):
+    """Launch shapes for one leg: the committed tuning cache, else a live
+    search before the timed region (saved with --retune)."""
+    if args.no_tune:
+        return "defaults"
+    kn, tuned = txe.plan(ctx, sysm, psi, compute)
+    if tuned and not args.retune:
+        return {"source": "cache", **kn}
+    ms, kn = txe.tune(ctx, sysm, psi, compute, reps=2)
+    return {"source": "tuned live", **kn}
+
+
+def load_cache(args, txe, ctx):
+    # with --retune the file's other entries are kept (merged) and rewritten
+    if not args.no_tune and os.path.exists(TUNE_CACHE):
+        txe.tune_load(ctx, TUNE_CACHE)
+
+
+def bench_batched(args, txe, torch, W):
+    """cfg5: one graph replay of all systems against separate applies."""
+    t0 = time.perf_counter()
+    systems = W.build_cfg5(device="cuda")
+    print(f"generated {len(systems)} systems in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = txe.Context(0)
+    handles = [txe.System.from_workload(ctx, s) for s in systems]
+    items = [(h, s.psi.contiguous()) for h, s in zip(handles, systems)]
+    npairs = sum(s.N * (s.N + 1) // 2 for s in systems)
+    ex64 = [float(txe.apply(ctx, h, p, compute="f64", want_vx=False)[1]) for h, p in items]
+    load_cache(args, txe, ctx)
+    tuned = [shapes(args, txe, ctx, h, p, "f32") for h, p in items]
+    if args.retune:
+        txe.tune_save(ctx, TUNE_CACHE)
+    print(f"launch shapes: {sum(isinstance(t, dict) and t['source'] == 'cache' for t in tuned)} from the cache, "
+          f"{sum(isinstance(t, dict) and t['source'] != 'cache' for t in tuned)} tuned live", file=sys.stderr, flush=True)
+    vxs = [torch.empty_like(p) for _, p in items]
+
+    def separate():
+        return [txe.apply(ctx, h, p, compute="f32", vx_out=v)[1] for (h, p), v in zip(items, vxs)]
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / args.steps
+
+    sep_s = timed(separate)
+    ctx.profile(True)
+    separate()
+    torch.cuda.synchronize()
+    kt = ctx.kernel_times()
+    ctx.profile(False)
+    lanes = 4
+    bat_s = timed(lambda: txe.apply_batched(ctx, items, compute="f32", lanes=lanes))
+    g = txe.Graph(ctx, items, compute="f32", lanes=lanes)
+    graph_s = timed(g.launch)
+    ex32 = [float(o[1]) for o in g.outputs]
+    g.close()
+    dE = [abs(a - b) for a, b in zip(ex32, ex64)]
+    core_ms = kt["core"][0]
+    core_flops = sum(core_kernel_flops_per_pair(s.grid.n, s.r, s.K) * s.N * (s.N + 1) // 2 for s in systems)
+    achieved = core_flops / (core_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(npairs / graph_s, 1),
+        "unit": "pair-convolutions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * graph_s, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": W.WORKLOAD_NAMES["cfg5"], "systems": len(systems), "pairs": npairs,
+                   "mode": "one captured graph, symmetric unique pairs per system", "lanes": lanes},
+        "separate_launches": {"value": round(npairs / sep_s, 1), "ms_per_step": round(1e3 * sep_s, 4)},
+        "batched_eager": {"value": round(npairs / bat_s, 1), "ms_per_step": round(1e3 * bat_s, 4)},
+        "graph_over_separate": round(sep_s / graph_s, 3),
+        "max_dE_x_fp32_vs_fp64_Ha": max(dE),
+        "all_within_1e-5_Ha": max(dE) <= 1e-5,
+        "launch_shapes": "defaults" if args.no_tune else
+        {"from_cache": sum(t["source"] == "cache" for t in tuned), "tuned_live": sum(t["source"] != "cache" for t in tuned)},
+        "roofline": {"bound": "mfma", "kernel": "core", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f32"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f32"], 4), "traffic": None,
+                     "launch_ms": round(core_ms / max(kt["core"][1], 1), 4)},
+    }
+    for h in handles:
+        h.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(s, seconds):
     """The CPU FP64 oracle, as it stands, on the first unique pairs of the same
     workload until `seconds` of work are done."""
@@ -110,7 +208,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes")
+    ap.add_argument("--retune", action="store_true",
+                    help="search launch shapes live (before the timed region) and write them to the cache file")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -132,6 +233,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.config == "cfg5":
+        bench_batched(args, txe, torch, W)
+        return
     s = W.build_config(args.config)
     n, r, K, N = s.grid.n, s.r, s.K, s.N
     symmetric = True
@@ -151,7 +255,10 @@ def main():
         del src, dst
 
     legs = {}
+    tuned = {}
+    load_cache(args, txe, ctx)
     for compute in args.legs.split(","):
+        tuned[compute] = shapes(args, txe, ctx, sysm, psi, compute)
         wall, ex, kt = time_leg(txe, torch, ctx, sysm, psi, vx, compute, args.steps, args.warmup, symmetric, 0, N)
         legs[compute] = {"wall": wall, "ex": ex, "kt": kt}
     if "f32" not in legs or "f64" not in legs:
@@ -205,7 +312,10 @@ def main():
         "dE_x_fp32_vs_fp64_Ha": dex,
         "whole_path_tflops": round(flops_per_pair(n, r, K) * npairs / (ms / 1e3) / 1e12, 3),
         "roofline": roof,
+        "launch_shapes": tuned,
     }
+    if args.retune:
+        txe.tune_save(ctx, TUNE_CACHE)
     sysm.close()
     ctx.close()
     if not args.no_cpu_baseline:

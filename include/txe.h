@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define TXE_ABI_VERSION 1
+#define TXE_ABI_VERSION 2
 
 typedef enum {
   TXE_OK = 0,
@@ -85,6 +85,7 @@ typedef enum { TXE_DTYPE_F64 = 0, TXE_DTYPE_F32 = 1 } txe_dtype;
 
 typedef struct txe_context txe_context;
 typedef struct txe_system txe_system;
+typedef struct txe_graph txe_graph;
 
 /* One exchange problem's fixed data (grid, bases, kernel).  All host arrays. */
 typedef struct {
@@ -179,6 +180,64 @@ txe_status txe_workspace_query(txe_context *ctx, const txe_system *sys, const tx
 
 /* One exchange apply (Vx psi for the targets and/or E_x). */
 txe_status txe_apply(txe_context *ctx, const txe_system *sys, const txe_apply_args *args);
+
+/* Batched apply: S independent problems (each its own system, orbitals and
+ * outputs, e.g. the uneven molecules of a screening run) enqueued as one
+ * unit.  The systems are spread over `lanes` concurrent HIP streams
+ * (1..16, default priority) that fork from and join back into the context
+ * stream, longest estimated work first on the least-loaded lane; each lane
+ * has its own slice of the context workspace.  Every problem runs exactly
+ * the kernels and launch shapes txe_apply would run for it, so its outputs
+ * are bitwise identical to a separate txe_apply.  args: host array of S;
+ * systems: host array of S.  Outputs of different problems must not overlap
+ * (TXE_ERR_ARG).  1 <= S <= 4096. */
+txe_status txe_apply_batched(txe_context *ctx, int32_t S, const txe_system *const *systems,
+                             const txe_apply_args *args, int32_t lanes);
+
+/* Graph of a batched apply: captured once (on a private stream of the
+ * context, with its own workspace allocated before the capture) and then
+ * replayed on the context's current stream by txe_graph_launch with a
+ * single host call.  The graph keeps the device pointers of `args`: the
+ * orbitals and outputs, and the systems, must stay alive until
+ * txe_graph_destroy; a replay reads the orbitals' current contents.  The
+ * graph holds no memset nodes.  Replays of one graph on one stream are
+ * ordered; replays of one graph overlapping on different streams race on
+ * its workspace. */
+txe_status txe_graph_capture_batched(txe_context *ctx, int32_t S, const txe_system *const *systems,
+                                     const txe_apply_args *args, int32_t lanes, txe_graph **out);
+txe_status txe_graph_launch(txe_graph *graph);
+/* Waits for the context stream, then frees the graph and its workspace. */
+txe_status txe_graph_destroy(txe_graph *graph);
+
+/* Tuner.  Launch shapes of one problem: knobs[0] gamma' splits of the core
+ * kernel as a multiple (1, 2, 4) of the fewest that fit its accumulator
+ * registers; knobs[1] gamma tiles per wavefront of the projection kernel
+ * (1..3); knobs[2] c tiles per wavefront of the back-projection kernel (1, 2;
+ * 0 = chosen by size); knobs[3] workgroups of the persistent projection and
+ * back-projection kernels.  Results do not depend on knobs[1..3]; knobs[0]
+ * changes the summation order of the pair energies only.
+ *
+ * txe_tune times txe_apply with these args (each candidate: one warm-up and
+ * `reps` timed applies, HIP events on the context stream; the host waits) in
+ * coordinate descent from the defaults {1, 2, 0, 2048}, at most two sweeps,
+ * and keeps the fastest in the context under a key made of the device
+ * architecture, grid, ranks, K, N, Ni, compute, mode and whether Vx psi is
+ * wanted.  Later applies, batches and graphs with the same key use it.  The
+ * outputs of args are overwritten.  best_ms (host, may be NULL): the mean
+ * time of the chosen shape.  Not allowed during capture (TXE_ERR_STATE). */
+txe_status txe_tune(txe_context *ctx, const txe_system *sys, const txe_apply_args *args, int32_t reps,
+                    double *best_ms);
+/* The launch shape an apply with these args would use (host knobs[4]);
+ * *tuned (host, may be NULL) = 1 if it came from the tuner or a cache. */
+txe_status txe_plan_get(txe_context *ctx, const txe_system *sys, const txe_apply_args *args, int32_t knobs[4],
+                        int32_t *tuned);
+/* The context's tuned shapes as a JSON object {key: {"ngs_mul", "proj_gt",
+ * "back_ncg", "grid_cap"}}, one entry per line (overwrites `path`). */
+txe_status txe_tune_save(txe_context *ctx, const char *path);
+/* Merges a file written by txe_tune_save into the context; *loaded (host,
+ * may be NULL) = entries read.  A malformed entry or an out-of-range shape
+ * fails the whole load (TXE_ERR_ARG) and changes nothing. */
+txe_status txe_tune_load(txe_context *ctx, const char *path, int32_t *loaded);
 
 #ifdef __cplusplus
 }

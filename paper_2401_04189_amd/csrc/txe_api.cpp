@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -36,6 +37,14 @@ static txe_status ok() {
   return TXE_OK;
 }
 
+// Launch-shape choices of one apply (the tuner's search space).
+struct Knobs {
+  int ngs_mul = 1;     // gamma' splits of the core kernel, as a multiple of the fewest that fit the registers
+  int proj_gt = 2;     // gamma tiles per wavefront in proj12 (1, 2, 3)
+  int back_ncg = 0;    // c tiles per wavefront in back (1, 2; 0 = by size)
+  int grid_cap = 2048; // workgroups of the persistent proj12 / back kernels
+};
+
 struct txe_context {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -44,6 +53,12 @@ struct txe_context {
   bool sticky = false;
   std::string sticky_msg;
   Prof prof;
+  std::string arch;                      // gcnArchName of the device
+  std::map<std::string, Knobs> plans;    // tuned launch shapes by problem key
+  std::vector<hipStream_t> lanes;        // concurrent streams of batched applies
+  std::vector<hipEvent_t> lane_done;
+  hipEvent_t fork = nullptr;
+  hipStream_t cap = nullptr;             // private stream for graph capture
 };
 
 template <typename T>
@@ -134,19 +149,26 @@ extern "C" txe_status txe_context_create(int32_t device, void *hip_stream, txe_c
   int ndev = 0;
   HIP_TRY(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(TXE_ERR_ARG, "device %d not in [0, %d)", device, ndev);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
   auto *c = new txe_context();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  c->arch = prop.gcnArchName;
+  const size_t colon = c->arch.find(':');
+  if (colon != std::string::npos) c->arch.resize(colon);
   *out = c;
   return ok();
 }
 
 extern "C" txe_status txe_context_destroy(txe_context *ctx) {
   if (!ctx) return fail(TXE_ERR_ARG, "ctx is null");
-  if (ctx->ws) {
-    hipSetDevice(ctx->device);
-    hipFree(ctx->ws);
-  }
+  hipSetDevice(ctx->device);
+  if (ctx->ws) hipFree(ctx->ws);
+  for (hipStream_t l : ctx->lanes) hipStreamDestroy(l);
+  for (hipEvent_t e : ctx->lane_done) hipEventDestroy(e);
+  if (ctx->fork) hipEventDestroy(ctx->fork);
+  if (ctx->cap) hipStreamDestroy(ctx->cap);
   delete ctx;
   return ok();
 }
@@ -549,6 +571,7 @@ struct Plan {
   bool want_vx;
   long long npairs;
   int NGS;
+  Knobs kn;
   int tchunk;          // targets per chunk (block mode)
   long long Pmax;      // pairs per chunk
   size_t elt;
@@ -571,8 +594,9 @@ static void plan_sizes(const Dims &D, Plan &pl) {
   pl.total = off;
 }
 
-static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, Plan &pl) {
+static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, const Knobs &kn, Plan &pl) {
   const Dims &D = sys->D;
+  pl.kn = kn;
   pl.f64 = a->compute == TXE_COMPUTE_F64;
   pl.symmetric = a->symmetric != 0;
   pl.want_vx = a->vxpsi != nullptr;
@@ -580,7 +604,11 @@ static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, Plan
   pl.npairs = pl.symmetric ? (long long)a->N * (a->N + 1) / 2 : (long long)a->Ni * a->N;
   const int mt = std::max(D.MT0, std::max(D.MT1, D.MT2));
   const int ngw = core_ngw(pl.f64, mt);
-  pl.NGS = (D.r2 + 4 * ngw - 1) / (4 * ngw);
+  // fewest gamma' splits whose rows fit the accumulator registers, times the
+  // tuned multiplier; then trimmed so that no split is empty
+  int ngs = (D.r2 + 4 * ngw - 1) / (4 * ngw) * std::max(1, kn.ngs_mul);
+  const int gper = (D.r2 + ngs - 1) / ngs;
+  pl.NGS = (D.r2 + gper - 1) / gper;
   const size_t limit = workspace_limit();
   if (pl.symmetric) {
     pl.tchunk = a->N;
@@ -601,6 +629,28 @@ static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, Plan
     tc = (tc + 1) / 2;
   }
   return TXE_OK;
+}
+
+// Key of the tuning cache: device architecture and every size that selects
+// a kernel instance or changes the work per launch.
+static std::string plan_key(const txe_context *ctx, const txe_system *sys, const txe_apply_args *a) {
+  static const char *cname[] = {"f64", "f32", "bf16x3", "bf16x6"};
+  const Dims &D = sys->D;
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s|n=%d,%d,%d|r=%d,%d,%d|K=%d|N=%d|Ni=%d|%s|%s|%s", ctx->arch.c_str(), D.n0, D.n1, D.n2,
+           D.r0, D.r1, D.r2, D.K, a->N, a->symmetric ? a->N : a->Ni, cname[a->compute & 3],
+           a->symmetric ? "sym" : "block", a->vxpsi ? "vx" : "energy");
+  return buf;
+}
+
+static Knobs knobs_for(const txe_context *ctx, const txe_system *sys, const txe_apply_args *a) {
+  auto it = ctx->plans.find(plan_key(ctx, sys, a));
+  return it == ctx->plans.end() ? Knobs{} : it->second;
+}
+
+static bool knobs_valid(const Knobs &k) {
+  return (k.ngs_mul == 1 || k.ngs_mul == 2 || k.ngs_mul == 4) && k.proj_gt >= 1 && k.proj_gt <= 3 &&
+         k.back_ncg >= 0 && k.back_ncg <= 2 && k.grid_cap >= 256 && k.grid_cap <= 16384;
 }
 
 static txe_status validate_args(const txe_context *ctx, const txe_system *sys, const txe_apply_args *a) {
@@ -641,7 +691,7 @@ extern "C" txe_status txe_workspace_query(txe_context *ctx, const txe_system *sy
   txe_status st = validate_args(ctx, sys, args);
   if (st != TXE_OK) return st;
   Plan pl;
-  if ((st = make_plan(sys, args, pl)) != TXE_OK) return st;
+  if ((st = make_plan(sys, args, knobs_for(ctx, sys, args), pl)) != TXE_OK) return st;
   *bytes = pl.total;
   return ok();
 }
@@ -655,6 +705,9 @@ static ChunkArgs<T> chunk_args(const txe_system *sys, const txe_apply_args *a, c
   c.pm.i0 = a->i0;
   c.N = a->N;
   c.NGS = pl.NGS;
+  c.proj_gt = pl.kn.proj_gt;
+  c.back_ncg = pl.kn.back_ncg;
+  c.grid_cap = pl.kn.grid_cap;
   c.psi = a->psi;
   c.vx = a->vxpsi;
   c.out_scale = a->out_scale;
@@ -668,15 +721,9 @@ static ChunkArgs<T> chunk_args(const txe_system *sys, const txe_apply_args *a, c
   return c;
 }
 
-extern "C" txe_status txe_apply(txe_context *ctx, const txe_system *sys, const txe_apply_args *args) {
-  txe_status st = validate_args(ctx, sys, args);
-  if (st != TXE_OK) return st;
-  if (ctx->sticky) return fail(TXE_ERR_DEVICE, "context has a previous device error: %s", ctx->sticky_msg.c_str());
-  Plan pl;
-  if ((st = make_plan(sys, args, pl)) != TXE_OK) return st;
-  if ((st = ensure_workspace(ctx, pl.total)) != TXE_OK) return st;
-  HIP_TRY(hipSetDevice(ctx->device));
-  char *ws = (char *)ctx->ws;
+// Enqueues one planned apply on stream s with workspace ws (pl.total bytes).
+static hipError_t run_plan(const txe_system *sys, const txe_apply_args *args, const Plan &pl, char *ws,
+                           hipStream_t s, Prof *prof) {
   hipError_t e = hipSuccess;
   const bool psi64 = args->dtype == TXE_DTYPE_F64;
   const int nchunks = pl.symmetric ? 1 : (args->Ni + pl.tchunk - 1) / pl.tchunk;
@@ -688,24 +735,394 @@ extern "C" txe_status txe_apply(txe_context *ctx, const txe_system *sys, const t
     if (pl.f64) {
       ChunkArgs<double> c = chunk_args<double>(sys, args, pl, ws);
       c.pm.p0 = p0; c.P = P; c.t_begin = tb; c.t_count = tcnt;
-      e = run_chunk_f64(sys->t64.t, c, pl.want_vx, ctx->stream, &ctx->prof);
+      e = run_chunk_f64(sys->t64.t, c, pl.want_vx, s, prof);
     } else {
       ChunkArgs<float> c = chunk_args<float>(sys, args, pl, ws);
       c.pm.p0 = p0; c.P = P; c.t_begin = tb; c.t_count = tcnt;
       if (args->compute == TXE_COMPUTE_F32)
-        e = run_chunk_f32(sys->t32.t, c, psi64, pl.want_vx, ctx->stream, &ctx->prof);
+        e = run_chunk_f32(sys->t32.t, c, psi64, pl.want_vx, s, prof);
       else
         e = run_chunk_bf16(sys->t32.t, sys->tbf.t, args->compute == TXE_COMPUTE_BF16X3 ? 2 : 3, c, psi64,
-                           pl.want_vx, ctx->stream, &ctx->prof);
+                           pl.want_vx, s, prof);
     }
   }
   if (e == hipSuccess)
     e = run_energy((const double *)(ws + pl.off_epair), pl.npairs, pl.symmetric ? 1 : 0, args->N, args->ex,
-                   args->e_pairs, ctx->stream, &ctx->prof);
-  if (e != hipSuccess) {
-    ctx->sticky = true;
-    ctx->sticky_msg = hipGetErrorString(e);
-    return fail(TXE_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+                   args->e_pairs, s, prof);
+  return e;
+}
+
+static txe_status device_failed(txe_context *ctx, hipError_t e) {
+  ctx->sticky = true;
+  ctx->sticky_msg = hipGetErrorString(e);
+  return fail(TXE_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+}
+
+static txe_status apply_with(txe_context *ctx, const txe_system *sys, const txe_apply_args *args, const Knobs &kn) {
+  txe_status st = validate_args(ctx, sys, args);
+  if (st != TXE_OK) return st;
+  if (ctx->sticky) return fail(TXE_ERR_DEVICE, "context has a previous device error: %s", ctx->sticky_msg.c_str());
+  Plan pl;
+  if ((st = make_plan(sys, args, kn, pl)) != TXE_OK) return st;
+  if ((st = ensure_workspace(ctx, pl.total)) != TXE_OK) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const hipError_t e = run_plan(sys, args, pl, (char *)ctx->ws, ctx->stream, &ctx->prof);
+  if (e != hipSuccess) return device_failed(ctx, e);
+  return ok();
+}
+
+extern "C" txe_status txe_apply(txe_context *ctx, const txe_system *sys, const txe_apply_args *args) {
+  if (!ctx || !sys || !args) return fail(TXE_ERR_ARG, "null argument");
+  return apply_with(ctx, sys, args, knobs_for(ctx, sys, args));
+}
+
+// ------------------------------------------------------------------------------------
+// batched apply: S independent systems on L concurrent lanes
+// ------------------------------------------------------------------------------------
+struct Batch {
+  std::vector<Plan> plans;
+  std::vector<int> order;            // systems by decreasing estimated cost
+  std::vector<int> lane_of;          // lane of each system
+  std::vector<size_t> lane_off;      // workspace offset of each lane
+  int lanes = 0;
+  size_t total = 0;
+};
+
+// Work estimate of one apply (multiply-adds of the dominant stages): the
+// core's chained contractions K * rp^3 * (rp1 + rp2) plus the projections
+// and back-projection n^3 * rp per pair.
+static double cost_estimate(const txe_system *sys, const Plan &pl) {
+  const Dims &D = sys->D;
+  const double rp = D.rp0, n3 = (double)D.n0 * D.n1 * D.n2;
+  const double core = (double)D.K * rp * rp * rp * (D.rp1 + D.rp2);
+  const double proj = n3 * rp * (pl.want_vx ? 4.0 : 2.0);
+  return (double)pl.npairs * (core + proj);
+}
+
+static txe_status batch_plan(txe_context *ctx, int S, const txe_system *const *systems, const txe_apply_args *args,
+                             int lanes, Batch &b) {
+  if (!ctx || !systems || !args) return fail(TXE_ERR_ARG, "null argument");
+  if (S < 1 || S > 4096) return fail(TXE_ERR_SHAPE, "S = %d not in [1, 4096]", S);
+  if (lanes < 1 || lanes > 16) return fail(TXE_ERR_ARG, "lanes = %d not in [1, 16]", lanes);
+  if (ctx->sticky) return fail(TXE_ERR_DEVICE, "context has a previous device error: %s", ctx->sticky_msg.c_str());
+  b.plans.resize(S);
+  std::vector<double> cost(S);
+  for (int i = 0; i < S; ++i) {
+    txe_status st = validate_args(ctx, systems[i], &args[i]);
+    if (st != TXE_OK) return fail(st, "system %d: %s", i, g_last_error.c_str());
+    if ((st = make_plan(systems[i], &args[i], knobs_for(ctx, systems[i], &args[i]), b.plans[i])) != TXE_OK)
+      return fail(st, "system %d: %s", i, g_last_error.c_str());
+    cost[i] = cost_estimate(systems[i], b.plans[i]);
   }
+  // outputs of different systems run concurrently and must not overlap
+  struct Range { const char *lo, *hi; int sys; };
+  std::vector<Range> outs;
+  for (int i = 0; i < S; ++i) {
+    const txe_apply_args &a = args[i];
+    const size_t elt = a.dtype == TXE_DTYPE_F64 ? 8 : 4;
+    const size_t grid = (size_t)systems[i]->n[0] * systems[i]->n[1] * systems[i]->n[2];
+    if (a.vxpsi) outs.push_back({(const char *)a.vxpsi, (const char *)a.vxpsi + (size_t)a.Ni * grid * elt, i});
+    if (a.ex) outs.push_back({(const char *)a.ex, (const char *)a.ex + 8, i});
+    if (a.e_pairs) outs.push_back({(const char *)a.e_pairs, (const char *)a.e_pairs + b.plans[i].npairs * 8, i});
+  }
+  std::sort(outs.begin(), outs.end(), [](const Range &x, const Range &y) { return x.lo < y.lo; });
+  for (size_t k = 1; k < outs.size(); ++k)
+    if (outs[k].lo < outs[k - 1].hi && outs[k].sys != outs[k - 1].sys)
+      return fail(TXE_ERR_ARG, "outputs of systems %d and %d overlap", outs[k - 1].sys, outs[k].sys);
+  // longest-processing-time-first assignment of systems to lanes
+  b.lanes = std::min(lanes, S);
+  b.order.resize(S);
+  for (int i = 0; i < S; ++i) b.order[i] = i;
+  std::stable_sort(b.order.begin(), b.order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<double> load(b.lanes, 0.0);
+  std::vector<size_t> need(b.lanes, 0);
+  b.lane_of.assign(S, 0);
+  for (int i : b.order) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b.lane_of[i] = l;
+    load[l] += cost[i];
+    need[l] = std::max(need[l], b.plans[i].total);  // a lane runs its systems one after another
+  }
+  b.lane_off.resize(b.lanes);
+  size_t off = 0;
+  for (int l = 0; l < b.lanes; ++l) {
+    b.lane_off[l] = off;
+    off = align256(off + need[l]);
+  }
+  b.total = off;
+  if (b.total > workspace_limit())
+    return fail(TXE_ERR_NOMEM, "batched workspace of %zu bytes exceeds the limit of %zu bytes", b.total,
+                workspace_limit());
+  return TXE_OK;
+}
+
+// Streams and events of the lanes (created outside any capture).
+static txe_status ensure_lanes(txe_context *ctx, int lanes) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (!ctx->fork) HIP_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+  while ((int)ctx->lanes.size() < lanes) {
+    hipStream_t s = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    ctx->lanes.push_back(s);
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->lane_done.push_back(e);
+  }
+  return TXE_OK;
+}
+
+// Enqueues the batch: lanes fork from s, run their systems in cost order,
+// and s waits for every lane (the fork/join pattern also joins the lanes
+// into a capture of s).
+static hipError_t batch_enqueue(txe_context *ctx, const txe_system *const *systems, const txe_apply_args *args,
+                                const Batch &b, char *ws, hipStream_t s) {
+  Prof off;  // per-kernel timing is not taken inside batches
+  if (b.lanes == 1) {
+    for (int i : b.order) {
+      const hipError_t e = run_plan(systems[i], &args[i], b.plans[i], ws, s, &off);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  hipError_t e = hipEventRecord(ctx->fork, s);
+  for (int l = 0; l < b.lanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(ctx->lanes[l], ctx->fork, 0);
+  for (int i : b.order) {
+    if (e != hipSuccess) break;
+    const int l = b.lane_of[i];
+    e = run_plan(systems[i], &args[i], b.plans[i], ws + b.lane_off[l], ctx->lanes[l], &off);
+  }
+  for (int l = 0; l < b.lanes; ++l) {
+    // the join is recorded even after a failure so that a capture can end
+    const hipError_t e1 = hipEventRecord(ctx->lane_done[l], ctx->lanes[l]);
+    const hipError_t e2 = hipStreamWaitEvent(s, ctx->lane_done[l], 0);
+    if (e == hipSuccess) e = e1 != hipSuccess ? e1 : e2;
+  }
+  return e;
+}
+
+extern "C" txe_status txe_apply_batched(txe_context *ctx, int32_t S, const txe_system *const *systems,
+                                        const txe_apply_args *args, int32_t lanes) {
+  Batch b;
+  txe_status st = batch_plan(ctx, S, systems, args, lanes, b);
+  if (st != TXE_OK) return st;
+  if ((st = ensure_workspace(ctx, b.total)) != TXE_OK) return st;
+  if ((st = ensure_lanes(ctx, b.lanes)) != TXE_OK) return st;
+  const hipError_t e = batch_enqueue(ctx, systems, args, b, (char *)ctx->ws, ctx->stream);
+  if (e != hipSuccess) return device_failed(ctx, e);
+  return ok();
+}
+
+// ------------------------------------------------------------------------------------
+// graph: a batch captured once and replayed
+// ------------------------------------------------------------------------------------
+struct txe_graph {
+  txe_context *ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void *ws = nullptr;  // the graph's own workspace
+  size_t ws_bytes = 0;
+};
+
+static void graph_free(txe_graph *g) {
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  if (g->ws) hipFree(g->ws);
+  delete g;
+}
+
+extern "C" txe_status txe_graph_capture_batched(txe_context *ctx, int32_t S, const txe_system *const *systems,
+                                                const txe_apply_args *args, int32_t lanes, txe_graph **out) {
+  if (!out) return fail(TXE_ERR_ARG, "out is null");
+  *out = nullptr;
+  Batch b;
+  txe_status st = batch_plan(ctx, S, systems, args, lanes, b);
+  if (st != TXE_OK) return st;
+  if ((st = ensure_lanes(ctx, b.lanes)) != TXE_OK) return st;
+  if (!ctx->cap) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+  auto *g = new txe_graph();
+  g->ctx = ctx;
+  g->ws_bytes = std::max<size_t>(b.total, 256);
+  if (hipMalloc(&g->ws, g->ws_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    g->ws = nullptr;
+    graph_free(g);
+    return fail(TXE_ERR_NOMEM, "hipMalloc of %zu bytes for the graph workspace failed", b.total);
+  }
+  hipError_t e = hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const hipError_t el = batch_enqueue(ctx, systems, args, b, (char *)g->ws, ctx->cap);
+    const hipError_t ec = hipStreamEndCapture(ctx->cap, &g->graph);
+    e = el != hipSuccess ? el : ec;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    graph_free(g);
+    return fail(TXE_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  *out = g;
+  return ok();
+}
+
+extern "C" txe_status txe_graph_launch(txe_graph *g) {
+  if (!g) return fail(TXE_ERR_ARG, "graph is null");
+  txe_context *ctx = g->ctx;
+  if (ctx->sticky) return fail(TXE_ERR_DEVICE, "context has a previous device error: %s", ctx->sticky_msg.c_str());
+  HIP_TRY(hipSetDevice(ctx->device));
+  const hipError_t e = hipGraphLaunch(g->exec, ctx->stream);
+  if (e != hipSuccess) return device_failed(ctx, e);
+  return ok();
+}
+
+extern "C" txe_status txe_graph_destroy(txe_graph *g) {
+  if (!g) return fail(TXE_ERR_ARG, "graph is null");
+  HIP_TRY(hipSetDevice(g->ctx->device));
+  HIP_TRY(hipStreamSynchronize(g->ctx->stream));
+  graph_free(g);
+  return ok();
+}
+
+// ------------------------------------------------------------------------------------
+// tuner: coordinate descent over the launch shapes, timed on the device
+// ------------------------------------------------------------------------------------
+static txe_status time_apply(txe_context *ctx, const txe_system *sys, const txe_apply_args *args, const Knobs &kn,
+                             int reps, double *ms) {
+  txe_status st = apply_with(ctx, sys, args, kn);  // warm-up (and workspace growth)
+  if (st != TXE_OK) return st;
+  hipEvent_t a = nullptr, z = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  if (hipEventCreate(&z) != hipSuccess) {
+    hipEventDestroy(a);
+    return fail(TXE_ERR_DEVICE, "hipEventCreate failed");
+  }
+  hipError_t e = hipEventRecord(a, ctx->stream);
+  for (int i = 0; i < reps && e == hipSuccess && st == TXE_OK; ++i) st = apply_with(ctx, sys, args, kn);
+  if (e == hipSuccess) e = hipEventRecord(z, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(z);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, z);
+  hipEventDestroy(a);
+  hipEventDestroy(z);
+  if (st != TXE_OK) return st;
+  if (e != hipSuccess) return fail(TXE_ERR_DEVICE, "timing failed: %s", hipGetErrorString(e));
+  *ms = t / reps;
+  return TXE_OK;
+}
+
+extern "C" txe_status txe_tune(txe_context *ctx, const txe_system *sys, const txe_apply_args *args, int32_t reps,
+                               double *best_ms) {
+  if (!ctx || !sys || !args) return fail(TXE_ERR_ARG, "null argument");
+  if (reps < 1 || reps > 1000) return fail(TXE_ERR_ARG, "reps = %d not in [1, 1000]", reps);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(ctx->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone) return fail(TXE_ERR_STATE, "cannot tune while the stream is captured");
+  const bool prof_on = ctx->prof.on;
+  ctx->prof.on = false;
+  Knobs best{};
+  double best_t = 0.0;
+  txe_status st = time_apply(ctx, sys, args, best, reps, &best_t);
+  const std::vector<int> ngs = {1, 2, 4}, gt = {1, 2, 3}, ncg = {1, 2}, cap = {1024, 2048, 4096};
+  for (int sweep = 0; sweep < 2 && st == TXE_OK; ++sweep) {
+    const Knobs start = best;
+    for (int knob = 0; knob < 4 && st == TXE_OK; ++knob) {
+      const std::vector<int> &vals = knob == 0 ? ngs : knob == 1 ? gt : knob == 2 ? ncg : cap;
+      for (int v : vals) {
+        Knobs k = best;
+        int &field = knob == 0 ? k.ngs_mul : knob == 1 ? k.proj_gt : knob == 2 ? k.back_ncg : k.grid_cap;
+        if (field == v) continue;
+        field = v;
+        double t = 0.0;
+        if ((st = time_apply(ctx, sys, args, k, reps, &t)) != TXE_OK) break;
+        if (t < best_t) {
+          best_t = t;
+          best = k;
+        }
+      }
+    }
+    if (start.ngs_mul == best.ngs_mul && start.proj_gt == best.proj_gt && start.back_ncg == best.back_ncg &&
+        start.grid_cap == best.grid_cap)
+      break;
+  }
+  ctx->prof.on = prof_on;
+  if (st != TXE_OK) return st;
+  ctx->plans[plan_key(ctx, sys, args)] = best;
+  if (best_ms) *best_ms = best_t;
+  return ok();
+}
+
+extern "C" txe_status txe_plan_get(txe_context *ctx, const txe_system *sys, const txe_apply_args *args,
+                                   int32_t knobs[4], int32_t *tuned) {
+  if (!ctx || !sys || !args || !knobs) return fail(TXE_ERR_ARG, "null argument");
+  txe_status st = validate_args(ctx, sys, args);
+  if (st != TXE_OK) return st;
+  const std::string key = plan_key(ctx, sys, args);
+  auto it = ctx->plans.find(key);
+  const Knobs k = it == ctx->plans.end() ? Knobs{} : it->second;
+  knobs[0] = k.ngs_mul; knobs[1] = k.proj_gt; knobs[2] = k.back_ncg; knobs[3] = k.grid_cap;
+  if (tuned) *tuned = it != ctx->plans.end();
+  return ok();
+}
+
+// Cache file: a JSON object mapping each problem key to its launch shape,
+// one entry per line:
+//   {
+//    "gfx950|n=64,64,64|...": {"ngs_mul": 1, "proj_gt": 2, "back_ncg": 0, "grid_cap": 2048},
+//    ...
+//   }
+extern "C" txe_status txe_tune_save(txe_context *ctx, const char *path) {
+  if (!ctx || !path) return fail(TXE_ERR_ARG, "null argument");
+  FILE *f = fopen(path, "w");
+  if (!f) return fail(TXE_ERR_ARG, "cannot open %s for writing", path);
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto &kv : ctx->plans) {
+    const Knobs &k = kv.second;
+    fprintf(f, " \"%s\": {\"ngs_mul\": %d, \"proj_gt\": %d, \"back_ncg\": %d, \"grid_cap\": %d}%s\n",
+            kv.first.c_str(), k.ngs_mul, k.proj_gt, k.back_ncg, k.grid_cap, ++i < ctx->plans.size() ? "," : "");
+  }
+  fprintf(f, "}\n");
+  const bool bad = ferror(f) != 0;
+  if (fclose(f) != 0 || bad) return fail(TXE_ERR_ARG, "write to %s failed", path);
+  return ok();
+}
+
+static bool read_int_field(const std::string &line, const char *name, int *v) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t at = line.find(pat);
+  if (at == std::string::npos) return false;
+  char *end = nullptr;
+  const long x = strtol(line.c_str() + at + pat.size(), &end, 10);
+  if (end == line.c_str() + at + pat.size()) return false;
+  *v = (int)x;
+  return true;
+}
+
+extern "C" txe_status txe_tune_load(txe_context *ctx, const char *path, int32_t *loaded) {
+  if (!ctx || !path) return fail(TXE_ERR_ARG, "null argument");
+  FILE *f = fopen(path, "r");
+  if (!f) return fail(TXE_ERR_ARG, "cannot open %s", path);
+  std::map<std::string, Knobs> got;
+  char buf[1024];
+  int lineno = 0;
+  txe_status st = TXE_OK;
+  while (fgets(buf, sizeof buf, f)) {
+    ++lineno;
+    const std::string line(buf);
+    const size_t q0 = line.find('"');
+    if (q0 == std::string::npos) continue;  // braces
+    const size_t q1 = line.find('"', q0 + 1);
+    Knobs k;
+    if (q1 == std::string::npos || !read_int_field(line, "ngs_mul", &k.ngs_mul) ||
+        !read_int_field(line, "proj_gt", &k.proj_gt) || !read_int_field(line, "back_ncg", &k.back_ncg) ||
+        !read_int_field(line, "grid_cap", &k.grid_cap) || !knobs_valid(k)) {
+      st = fail(TXE_ERR_ARG, "%s:%d: not a valid cache entry", path, lineno);
+      break;
+    }
+    got[line.substr(q0 + 1, q1 - q0 - 1)] = k;
+  }
+  fclose(f);
+  if (st != TXE_OK) return st;
+  for (const auto &kv : got) ctx->plans[kv.first] = kv.second;
+  if (loaded) *loaded = (int32_t)got.size();
   return ok();
 }

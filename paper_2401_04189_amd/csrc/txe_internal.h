@@ -80,6 +80,9 @@ struct ChunkArgs {
   int N;                      // sources (all orbitals)
   int t_begin, t_count;       // targets of the back-projection (local target indices)
   int NGS;                    // gamma' splits in the core kernel
+  int proj_gt;                // gamma tiles per wavefront in proj12 (1, 2 or 3)
+  int back_ncg;               // c tiles per wavefront in back (1 or 2; 0 = by size)
+  int grid_cap;               // workgroups of the persistent kernels
   const void *psi;
   void *vx;
   const double *out_scale;

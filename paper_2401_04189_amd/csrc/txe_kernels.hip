@@ -970,7 +970,7 @@ hipError_t launch_back_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream
   // and each workgroup walks several items
   const size_t tab = ((size_t)a.D.rp2 * a.D.nc2 + (size_t)nbt * a.D.MT1 * 256) * sizeof(T);
   const bool lds_tab = tab <= 64 * 1024;
-  const unsigned nbl = lds_tab ? std::min(nb, 2048u) : nb;
+  const unsigned nbl = lds_tab ? std::min(nb, (unsigned)a.grid_cap) : nb;
 #define TXE_BACK(NBTV)                                                                                         \
   if (lds_tab)                                                                                                   \
     hipLaunchKernelGGL((k_back<T, Tin, NBTV, NCG, true>), dim3(nbl), dim3(256), tab, s, a.S1, psi, a.D, a.pm,  \
@@ -992,29 +992,35 @@ hipError_t launch_back_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream
 template <typename T, typename Tin>
 hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
   // two c-tiles per wavefront while the b-tile accumulators are few
-  if ((a.D.nb1 >> 4) <= 4) return launch_back_ncg<T, Tin, 2>(tb, a, s);
+  const int ncg = a.back_ncg ? a.back_ncg : ((a.D.nb1 >> 4) <= 4 ? 2 : 1);
+  if (ncg == 2) return launch_back_ncg<T, Tin, 2>(tb, a, s);
   return launch_back_ncg<T, Tin, 1>(tb, a, s);
+}
+
+template <typename T, typename Tin, int GT>
+void launch_proj12(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  const int ngg = (a.D.MT2 + GT - 1) / GT;
+  const unsigned nb = blocks_for((long long)a.P * a.D.n0 * ngg);
+  const size_t tab = ((size_t)a.D.nc2 * a.D.rp2 + (size_t)a.D.MT1 * (a.D.nb1 >> 4) * 256) * sizeof(T);
+  if (tab <= 64 * 1024)
+    hipLaunchKernelGGL((k_proj12<T, Tin, GT, true>), dim3(std::min(nb, (unsigned)a.grid_cap)), dim3(256), tab, s,
+                       (const Tin *)a.psi, a.D, a.pm, a.P, tb, a.T2);
+  else
+    hipLaunchKernelGGL((k_proj12<T, Tin, GT, false>), dim3(nb), dim3(256), 0, s, (const Tin *)a.psi, a.D, a.pm,
+                       a.P, tb, a.T2);
 }
 
 template <typename T, typename Tin>
 hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s, Prof *prof,
                        const BfTables *bft = nullptr, int nsplit = 0) {
-  constexpr int GT = 2, FT = 4;
+  constexpr int FT = 4;
   hipError_t e;
-  {
-    const int ngg = (a.D.MT2 + GT - 1) / GT;
-    const unsigned nb = blocks_for((long long)a.P * a.D.n0 * ngg);
-    const size_t tab = ((size_t)a.D.nc2 * a.D.rp2 + (size_t)a.D.MT1 * (a.D.nb1 >> 4) * 256) * sizeof(T);
-    prof->begin(K_PROJ12, s);
-    if (tab <= 64 * 1024)
-      hipLaunchKernelGGL((k_proj12<T, Tin, GT, true>), dim3(std::min(nb, 2048u)), dim3(256), tab, s,
-                         (const Tin *)a.psi, a.D, a.pm, a.P, tb, a.T2);
-    else
-      hipLaunchKernelGGL((k_proj12<T, Tin, GT, false>), dim3(nb), dim3(256), 0, s, (const Tin *)a.psi, a.D, a.pm,
-                         a.P, tb, a.T2);
-    prof->end(s);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
+  prof->begin(K_PROJ12, s);
+  if (a.proj_gt == 1) launch_proj12<T, Tin, 1>(tb, a, s);
+  else if (a.proj_gt == 3) launch_proj12<T, Tin, 3>(tb, a, s);
+  else launch_proj12<T, Tin, 2>(tb, a, s);
+  prof->end(s);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   {
     const int NF = (a.D.rp1 * a.D.rp2) >> 4;
     const int nfg = (NF + FT - 1) / FT;

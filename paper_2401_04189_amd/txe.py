@@ -72,6 +72,18 @@ SIGNATURES = {
     "txe_profile_read": (_c_int, [ctypes.c_void_p, _c_int, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]),
     "txe_kernel_name": (ctypes.c_char_p, [_c_int]),
+    "txe_apply_batched": (_c_int, [ctypes.c_void_p, _c_int, ctypes.POINTER(ctypes.c_void_p),
+                                   ctypes.POINTER(ApplyArgs), _c_int]),
+    "txe_graph_capture_batched": (_c_int, [ctypes.c_void_p, _c_int, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ApplyArgs), _c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "txe_graph_launch": (_c_int, [ctypes.c_void_p]),
+    "txe_graph_destroy": (_c_int, [ctypes.c_void_p]),
+    "txe_tune": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs), _c_int,
+                          ctypes.POINTER(ctypes.c_double)]),
+    "txe_plan_get": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "txe_tune_save": (_c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "txe_tune_load": (_c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
 }
 
 KERNELS = ("proj12", "proj3", "core", "epair", "back", "energy")
@@ -239,12 +251,9 @@ def make_args(psi, compute="f64", symmetric=True, i0=0, Ni=None, vx=None, ex=Non
     return a
 
 
-def apply(ctx: Context, sysm: System, psi, compute="f64", symmetric=True, i0=0, Ni=None, want_vx=True,
-          want_pairs=False, out_scale=None, out_weighted=False, vx_out=None):
-    """Vx psi (targets) and E_x for the orbitals `psi` (a CUDA tensor N x n0 x n1 x n2).
-
-    Returns (vx, ex, e_pairs): vx is None when want_vx is False; ex is a
-    0-d float64 CUDA tensor; e_pairs is None unless want_pairs."""
+def _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_scale=None, out_weighted=False,
+             vx_out=None):
+    """ApplyArgs for one problem with freshly allocated outputs."""
     import torch
 
     if not psi.is_cuda or not psi.is_contiguous():
@@ -261,9 +270,109 @@ def apply(ctx: Context, sysm: System, psi, compute="f64", symmetric=True, i0=0, 
     npairs = N * (N + 1) // 2 if symmetric else Ni * N
     ep = torch.empty(npairs, dtype=torch.float64, device=psi.device) if want_pairs else None
     a = make_args(psi, compute, symmetric, i0, Ni, vx, ex, ep, out_scale, out_weighted)
+    return a, vx, ex, ep
+
+
+def apply(ctx: Context, sysm: System, psi, compute="f64", symmetric=True, i0=0, Ni=None, want_vx=True,
+          want_pairs=False, out_scale=None, out_weighted=False, vx_out=None):
+    """Vx psi (targets) and E_x for the orbitals `psi` (a CUDA tensor N x n0 x n1 x n2).
+
+    Returns (vx, ex, e_pairs): vx is None when want_vx is False; ex is a
+    0-d float64 CUDA tensor; e_pairs is None unless want_pairs."""
+    import torch
+
+    a, vx, ex, ep = _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_scale, out_weighted,
+                             vx_out)
     ctx.set_stream(torch.cuda.current_stream(psi.device))
     _check(lib().txe_apply(ctx.h, sysm.h, ctypes.byref(a)))
     return vx, ex, ep
+
+
+def _batch(items, compute, want_vx, want_pairs):
+    """Argument arrays of a batch of (System, psi) problems in symmetric mode."""
+    args = (ApplyArgs * len(items))()
+    systems = (ctypes.c_void_p * len(items))()
+    outs = []
+    for k, (sysm, psi) in enumerate(items):
+        a, vx, ex, ep = _prepare(sysm, psi, compute, True, 0, None, want_vx, want_pairs)
+        args[k] = a
+        systems[k] = sysm.h
+        outs.append((vx, ex, ep))
+    return systems, args, outs
+
+
+def apply_batched(ctx: Context, items, compute="f32", lanes=4, want_vx=True, want_pairs=False):
+    """Symmetric-mode apply of several independent problems, items = [(System, psi), ...],
+    enqueued as one batch over `lanes` concurrent streams.  Returns [(vx, ex, e_pairs)]."""
+    import torch
+
+    systems, args, outs = _batch(items, compute, want_vx, want_pairs)
+    ctx.set_stream(torch.cuda.current_stream())
+    _check(lib().txe_apply_batched(ctx.h, len(items), systems, args, int(lanes)))
+    return outs
+
+
+class Graph:
+    """A batch captured once as a HIP graph; `launch()` replays it on the
+    current stream.  The outputs (`outputs`, as in apply_batched) are the
+    graph's own and are overwritten by every replay; the inputs are read
+    where they were at capture time."""
+
+    def __init__(self, ctx: Context, items, compute="f32", lanes=4, want_vx=True, want_pairs=False):
+        self.ctx = ctx
+        self.items = list(items)  # keeps systems and orbitals alive
+        systems, args, self.outputs = _batch(self.items, compute, want_vx, want_pairs)
+        h = ctypes.c_void_p()
+        _check(lib().txe_graph_capture_batched(ctx.h, len(self.items), systems, args, int(lanes), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self):
+        import torch
+
+        self.ctx.set_stream(torch.cuda.current_stream())
+        _check(lib().txe_graph_launch(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().txe_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune(ctx: Context, sysm: System, psi, compute="f32", symmetric=True, i0=0, Ni=None, want_vx=True, reps=3):
+    """Search the launch shapes of this problem on the device; the context
+    keeps the fastest.  Returns (mean ms of the chosen shape, knobs)."""
+    import torch
+
+    a, vx, ex, ep = _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, False)
+    ctx.set_stream(torch.cuda.current_stream(psi.device))
+    ms = ctypes.c_double()
+    _check(lib().txe_tune(ctx.h, sysm.h, ctypes.byref(a), int(reps), ctypes.byref(ms)))
+    return ms.value, plan(ctx, sysm, psi, compute, symmetric, i0, Ni, want_vx)[0]
+
+
+def plan(ctx: Context, sysm: System, psi, compute="f32", symmetric=True, i0=0, Ni=None, want_vx=True):
+    """(knobs dict, tuned flag) an apply with these arguments would use."""
+    a, vx, ex, ep = _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, False)
+    k = (ctypes.c_int32 * 4)()
+    tuned = ctypes.c_int32()
+    _check(lib().txe_plan_get(ctx.h, sysm.h, ctypes.byref(a), k, ctypes.byref(tuned)))
+    return dict(ngs_mul=k[0], proj_gt=k[1], back_ncg=k[2], grid_cap=k[3]), bool(tuned.value)
+
+
+def tune_save(ctx: Context, path):
+    _check(lib().txe_tune_save(ctx.h, os.fsencode(path)))
+
+
+def tune_load(ctx: Context, path):
+    n = ctypes.c_int32()
+    _check(lib().txe_tune_load(ctx.h, os.fsencode(path), ctypes.byref(n)))
+    return n.value
 
 
 def workspace_bytes(ctx, sysm, psi, compute="f64", symmetric=True, i0=0, Ni=None, want_vx=True):

@@ -33,7 +33,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     L = txe.lib()
-    assert L.txe_abi_version() == 1
+    hdr = open(HEADER).read()
+    ver = int(re.search(r"#define TXE_ABI_VERSION (\d+)", hdr).group(1))
+    assert L.txe_abi_version() == ver == 2
     for st in range(7):
         assert len(L.txe_status_string(st)) > 0
 
