@@ -603,10 +603,10 @@ static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, cons
   pl.elt = pl.f64 ? sizeof(double) : sizeof(float);
   pl.npairs = pl.symmetric ? (long long)a->N * (a->N + 1) / 2 : (long long)a->Ni * a->N;
   const int mt = std::max(D.MT0, std::max(D.MT1, D.MT2));
-  const int ngw = core_ngw(pl.f64, mt);
+  const int rows = core_rows(pl.f64, a->compute == TXE_COMPUTE_BF16X3 || a->compute == TXE_COMPUTE_BF16X6, mt);
   // fewest gamma' splits whose rows fit the accumulator registers, times the
   // tuned multiplier; then trimmed so that no split is empty
-  int ngs = (D.r2 + 4 * ngw - 1) / (4 * ngw) * std::max(1, kn.ngs_mul);
+  int ngs = (D.r2 + rows - 1) / rows * std::max(1, kn.ngs_mul);
   const int gper = (D.r2 + ngs - 1) / ngs;
   pl.NGS = (D.r2 + gper - 1) / gper;
   const size_t limit = workspace_limit();

@@ -172,6 +172,6 @@ hipError_t run_energy(const double *epair, long long npairs, int symmetric, int 
                       hipStream_t s, Prof *prof);
 
 // Core-kernel variant choice (register budget per precision).
-int core_ngw(bool f64, int mt);
+int core_rows(bool f64, bool split_bf16, int mt);  // gamma' rows one core workgroup covers
 
 }  // namespace txe

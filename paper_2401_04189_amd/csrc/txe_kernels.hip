@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void k_proj3(const T *__restrict__ T2, Dims D,
 // sum Phi[alpha'][gamma'][beta'] G[alpha'][beta'][gamma'] (FP64, fixed order)
 // and the first back-projection S1[a][gamma'][beta'] = sum_alpha' U0[a][alpha'] Phi[alpha'][gamma'][beta'],
 // chained on the Phi accumulators.
-template <typename T, int MT, int NGW, bool WRITE_S1>
+template <typename T, int MT, int NGW, int NW, bool WRITE_S1>
 __device__ __forceinline__ void core_epilogue(typename MF<T>::acc (&Phi)[MT][NGW], const T *__restrict__ Gp, const Dims &D,
                                               int p, int bt, int gs, int NGS, int wg_lo, int wg_hi, int lane, int lr,
                                               int lg, int wave, const Tables<T> &tb, T *__restrict__ S1,
@@ -259,7 +259,7 @@ __device__ __forceinline__ void core_epilogue(typename MF<T>::acc (&Phi)[MT][NGW
   using M = MF<T>;
   using acc = typename M::acc;
   constexpr int RP = 16 * MT;
-  __shared__ double red[4];
+  __shared__ double red[NW];
   double e = 0.0;
   const int bp = 16 * bt + lr;
 #pragma unroll
@@ -283,8 +283,11 @@ __device__ __forceinline__ void core_epilogue(typename MF<T>::acc (&Phi)[MT][NGW
   for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
   if (lane == 0) red[wave] = e;
   __syncthreads();
-  if (threadIdx.x == 0)
-    epart[((size_t)p * MT + bt) * NGS + gs] = ((red[0] + red[1]) + (red[2] + red[3]));
+  if (threadIdx.x == 0) {
+    double t = (red[0] + red[1]) + (red[2] + red[3]);
+    if constexpr (NW == 8) t += (red[4] + red[5]) + (red[6] + red[7]);
+    epart[((size_t)p * MT + bt) * NGS + gs] = t;
+  }
 
   // ---- S1[p][a][gamma'][beta'] = sum_alpha' U0[a][alpha'] Phi[alpha'][gamma'][beta']
   if (WRITE_S1) {
@@ -336,8 +339,8 @@ __device__ __forceinline__ void core_epilogue(typename MF<T>::acc (&Phi)[MT][NGW
 // double-buffered in LDS so each step needs one barrier; Phi stays in
 // registers for the whole pair.
 // -------------------------------------------------------------------------------------
-template <typename T, int MT, int NGW, bool WRITE_S1>
-__global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D, int P, int NGS, Tables<T> tb,
+template <typename T, int MT, int NGW, int NW, bool WRITE_S1>
+__global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Dims D, int P, int NGS, Tables<T> tb,
                                                  T *__restrict__ S1, double *__restrict__ epart) {
   using M = MF<T>;
   using acc = typename M::acc;
@@ -357,14 +360,22 @@ __global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D
   const int gper = (D.r2 + NGS - 1) / NGS;
   const int g_lo = gs * gper;
   const int g_hi = min(D.r2, g_lo + gper);
-  const int gw = (gper + 3) >> 2;                 // gamma' rows per wavefront in phase B (<= NGW)
+  const int gw = (gper + NW - 1) / NW;            // gamma' rows per wavefront in phase B (<= NGW)
   const int wg_lo = g_lo + wave * gw;
   const int wg_hi = min(g_hi, wg_lo + gw);
   const int nrow = max(0, wg_hi - wg_lo);         // this wavefront's gamma' rows (uniform)
   const T *Gp = G + (size_t)p * RP * F;
 
-  T *Zs = reinterpret_cast<T *>(smem_raw);        // [2][4][gper][16]
-  const int zsz = 4 * gper * 16;
+  // eight-wavefront rank-3 form: the slab lives in LDS (double-buffered,
+  // row stride padded so the four lane groups hit different banks)
+  constexpr bool PF = sizeof(T) == 4 ? MT <= 3 : MT <= 2;
+  constexpr bool HOLD_G = PF && (NW == 4 || MT <= 2);
+  constexpr bool LDS_G = PF && !HOLD_G;
+  constexpr int SROW = RP % 32 == 0 ? RP + 16 : RP;
+  constexpr int SLAB = LDS_G ? RP * SROW : 0;
+  T *Gs = reinterpret_cast<T *>(smem_raw);        // [2][RP][SROW] (LDS_G)
+  T *Zs = Gs + 2 * SLAB;                          // [2][NW][gper][16]
+  const int zsz = NW * gper * 16;
 
   acc Phi[MT][NGW];
 #pragma unroll
@@ -376,57 +387,99 @@ __global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D
   // load the next step's term matrices while the current step computes;
   // large ranks re-read the slab (L1-resident) and load the terms in place.
   // Loops run over the padded size; padded rows and columns are zero.
-  constexpr bool HOLD_G = sizeof(T) == 4 ? MT <= 3 : MT <= 2;
-  constexpr bool PF = HOLD_G;
   constexpr int GK = HOLD_G ? 4 * MT : 1, GM = HOLD_G ? MT : 1;
-  const int nkq = (D.K + 3) >> 2;
+  constexpr int NTG = NW / 4;  // groups of four terms per step
+  const int nkq = (D.K + NW - 1) / NW;
   const int nsteps = D.r0 * nkq;
 
-  // term matrices of one step for this wavefront: Chat1_k (16 beta' columns)
-  // as B fragments, Chat2_k in chain order as A fragments
+  // Operands of a step for this wavefront's term k: Chat1_k (16 beta'
+  // columns) as B fragments and Ahat[alpha][4kq + lg] (the phase-B column
+  // fragments) are prefetched one step ahead; Chat2_k (A fragments in chain
+  // order) is loaded at the start of its own step and first used after the
+  // W chain.  Loads are issued in the order they are waited for, so the
+  // in-order wait counts never wait on a prefetch.
   struct CF {
     T cb[4 * MT];
-    T c2[MT][MT][4];
+    T af[NTG][MT];
   };
-  auto load_terms = [&](int kq_, CF &f) {
-    const int k_ = 4 * kq_ + wave;
+  auto load_terms = [&](int alpha_, int kq_, CF &f) {
+#pragma unroll
+    for (int tg = 0; tg < NTG; ++tg) {
+      const T *ah = tb.Ahat + ((size_t)alpha_ * D.Kp + NW * kq_ + 4 * tg + lg) * RP + lr;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) f.af[tg][mt] = ah[16 * mt];
+    }
+    const int k_ = NW * kq_ + wave;
     if (k_ >= D.K) return;
     const T *C1k = tb.C1B + (size_t)k_ * F + 16 * bt + lr;
 #pragma unroll
     for (int kt = 0; kt < 4 * MT; ++kt) f.cb[kt] = C1k[(4 * kt + lg) * RP];
-    const T *C2k = tb.C2chain + (size_t)k_ * MT * MT * 256 + lane;
+  };
+  // A fragments of slab alpha: G[alpha][beta = 4kt+lg][gamma = 16mg+lr]
+  auto load_slab = [&](int alpha_, T (&g)[GK][GM]) {
+    const T *Ga_ = Gp + (size_t)alpha_ * F + lr;
 #pragma unroll
-    for (int mtp = 0; mtp < MT; ++mtp)
+    for (int kt = 0; kt < GK; ++kt)
 #pragma unroll
-      for (int mg = 0; mg < MT; ++mg)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) f.c2[mtp][mg][v] = C2k[((mtp * MT + mg) * 4 + v) * 64];
+      for (int mg = 0; mg < GM; ++mg) g[kt][mg] = Ga_[(4 * kt + lg) * RP + 16 * mg];
   };
 
-  CF cur, nxt;
-  if constexpr (PF) load_terms(0, cur);
-  T gf[GK][GM];
+  CF ca, cb2;
+  T gf[GK][GM];  // held slab fragments
+  if constexpr (PF) load_terms(0, 0, ca);
   const T *Ga = Gp + lr;
-  for (int step = 0; step < nsteps; ++step) {
+  // LDS slab: the next slab arrives in 512-element chunks, chunk kq during
+  // step kq (a load at the start of the step, its store before the step's
+  // barrier); the loads are unconditional (clamped addresses) so every step
+  // issues the same loads
+  constexpr int NCH = LDS_G ? (RP * RP + 64 * NW - 1) / (64 * NW) : 0;
+  const int tid = threadIdx.x;
+  auto slab_elem = [&](int c) { return min(c * 64 * NW + tid, (int)(RP * RP) - 1); };
+  auto slab_store = [&](int c, int buf, T v) {
+    const int e = c * 64 * NW + tid;
+    if (e < RP * RP) Gs[buf * SLAB + (e / RP) * SROW + (e % RP)] = v;
+  };
+  if constexpr (LDS_G) {
+    for (int c = 0; c < NCH; ++c) slab_store(c, 0, Gp[slab_elem(c)]);
+    __syncthreads();
+  }
+  // one step: uses cur, prefetches the next step's operands into nxt
+  auto step_body = [&](const int step, CF &cur, CF &nxt) __attribute__((always_inline)) {
     const int alpha = step / nkq;
     const int kq = step - alpha * nkq;
-    const int k = 4 * kq + wave;
+    const int k = NW * kq + wave;
     if (kq == 0) {
-      // A fragments of the slab: G[alpha][beta = 4kt+lg][gamma = 16mg+lr]
       Ga = Gp + (size_t)alpha * F + lr;
       if constexpr (HOLD_G) {
-#pragma unroll
-        for (int kt = 0; kt < 4 * MT; ++kt)
-#pragma unroll
-          for (int mg = 0; mg < MT; ++mg) gf[kt][mg] = Ga[(4 * kt + lg) * RP + 16 * mg];
+        load_slab(alpha, gf);
+        // settle the slab (and this step's prefetched terms) here, once per
+        // slab: later steps then wait only on their own operands, never on
+        // the prefetch they issue
+        if constexpr (PF) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
       }
     }
+    T gnext = (T)0;
+    if constexpr (LDS_G) gnext = Gp[(size_t)min(alpha + 1, D.r0 - 1) * F + slab_elem(min(kq, NCH - 1))];
+    T c2s[PF ? MT : 1][PF ? MT : 1][4];
     if constexpr (PF) {
-      if (step + 1 < nsteps) load_terms(kq + 1 == nkq ? 0 : kq + 1, nxt);
-    } else if (k < D.K) {
-      const T *C1k = tb.C1B + (size_t)k * F + 16 * bt + lr;
+      if (k < D.K) {
+      const T *C2k = tb.C2chain + (size_t)k * MT * MT * 256 + lane;
 #pragma unroll
-      for (int kt = 0; kt < 4 * MT; ++kt) cur.cb[kt] = C1k[(4 * kt + lg) * RP];
+      for (int mtp = 0; mtp < MT; ++mtp)
+#pragma unroll
+        for (int mg = 0; mg < MT; ++mg)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) c2s[mtp][mg][v] = C2k[((mtp * MT + mg) * 4 + v) * 64];
+      }
+      const bool wrap = kq + 1 == nkq;
+      if (step + 1 < nsteps) load_terms(wrap ? alpha + 1 : alpha, wrap ? 0 : kq + 1, nxt);
+    }
+    if constexpr (!PF) {
+      if (k < D.K) {
+        const T *C1k = tb.C1B + (size_t)k * F + 16 * bt + lr;
+#pragma unroll
+        for (int kt = 0; kt < 4 * MT; ++kt) cur.cb[kt] = C1k[(4 * kt + lg) * RP];
+      }
     }
     T *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * gper * 16;
     // ---- phase A
@@ -440,6 +493,7 @@ __global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D
         for (int mg = 0; mg < MT; ++mg) {
           T g;
           if constexpr (HOLD_G) g = gf[kt][mg];
+          else if constexpr (LDS_G) g = Gs[(alpha & 1) * SLAB + (4 * kt + lg) * SROW + 16 * mg + lr];
           else g = Ga[(4 * kt + lg) * RP + 16 * mg];
           W[mg] = M::mma(g, cur.cb[kt], W[mg]);
         }
@@ -464,7 +518,7 @@ __global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D
 #pragma unroll
           for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int mtp = 0; mtp < MT; ++mtp) Z[mtp] = M::mma(cur.c2[mtp][mg][v], W[mg][v], Z[mtp]);
+            for (int mtp = 0; mtp < MT; ++mtp) Z[mtp] = M::mma(c2s[mtp][mg][v], W[mg][v], Z[mtp]);
 #pragma unroll
         for (int mtp = 0; mtp < MT; ++mtp) store_z(mtp, Z[mtp]);
       } else {
@@ -476,7 +530,7 @@ __global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D
 #pragma unroll
             for (int mg = 0; mg < MT; ++mg)
 #pragma unroll
-              for (int v = 0; v < 4; ++v) c2[mg][v] = cur.c2[mtp][mg][v];
+              for (int v = 0; v < 4; ++v) c2[mg][v] = c2s[mtp][mg][v];
           } else {
 #pragma unroll
             for (int mg = 0; mg < MT; ++mg)
@@ -495,30 +549,53 @@ __global__ __launch_bounds__(256, 1) void k_core(const T *__restrict__ G, Dims D
     } else {
       for (int idx = lane; idx < gper * 16; idx += 64) Zw[idx] = (T)0;
     }
+    if constexpr (LDS_G) {
+      if (alpha + 1 < D.r0) {
+        if (kq < NCH) slab_store(kq, (alpha + 1) & 1, gnext);
+        if (kq + 1 == nkq)  // fewer steps than chunks: the rest now
+          for (int c = nkq; c < NCH; ++c) slab_store(c, (alpha + 1) & 1, Gp[(size_t)(alpha + 1) * F + slab_elem(c)]);
+      }
+    }
     __syncthreads();
-    // ---- phase B: reduction over the step's four terms (slot lg)
-    {
-      const int kk = 4 * kq + lg;
-      T af[MT];
-      const T *ah = tb.Ahat + ((size_t)alpha * D.Kp + kk) * RP + lr;
+    // ---- phase B: reduction over the step's terms, four at a time (slot lg
+    // of group tg)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) af[mt] = ah[16 * mt];
-      const T *zrow = Zs + (size_t)(step & 1) * zsz + (size_t)lg * gper * 16 + lr;
-      // every row of Phi is updated (no branch keeps the accumulators in
-      // place); rows past this wavefront's range read a valid LDS row and are
-      // never stored
+    for (int tg = 0; tg < NTG; ++tg) {
+      T af[MT];
+      if constexpr (PF) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) af[mt] = cur.af[tg][mt];
+      } else {
+        const T *ah = tb.Ahat + ((size_t)alpha * D.Kp + NW * kq + 4 * tg + lg) * RP + lr;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) af[mt] = ah[16 * mt];
+      }
+      const T *zrow = Zs + (size_t)(step & 1) * zsz + (size_t)(4 * tg + lg) * gper * 16 + lr;
+      // rows past this wavefront's range read a valid LDS row and are never
+      // stored; with eight wavefronts a uniform bound skips the spare rows
 #pragma unroll
       for (int ng = 0; ng < NGW; ++ng) {
+        if (NW == 8 && ng >= gw) break;
         const int row = min(wg_lo - g_lo + ng, gper - 1);
         const T bz = zrow[row * 16];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(af[mt], bz, Phi[mt][ng]);
       }
     }
-    if constexpr (PF) cur = nxt;
+  };
+  // two steps per iteration with the operand buffers swapping roles, so the
+  // prefetched registers are never copied (a copy would wait for the loads)
+  int step = 0;
+  if constexpr (PF) {
+    for (; step + 1 < nsteps; step += 2) {
+      step_body(step, ca, cb2);
+      step_body(step + 1, cb2, ca);
+    }
   }
+  for (; step < nsteps; ++step) step_body(step, ca, cb2);
 
-  core_epilogue<T, MT, NGW, WRITE_S1>(Phi, Gp, D, p, bt, gs, NGS, wg_lo, wg_hi, lane, lr, lg, wave, tb, S1, epart);
+  core_epilogue<T, MT, NGW, NW, WRITE_S1>(Phi, Gp, D, p, bt, gs, NGS, wg_lo, wg_hi, lane, lr, lg, wave, tb, S1,
+                                          epart);
 }
 
 // -------------------------------------------------------------------------------------
@@ -702,7 +779,7 @@ __global__ __launch_bounds__(256, 1) void k_core_bf(const float *__restrict__ G,
       }
     }
   }
-  core_epilogue<float, MT, NGW, WRITE_S1>(Phi, Gp, D, p, bt, gs, NGS, wg_lo, wg_hi, lane, lr, lg, wave, tb, S1,
+  core_epilogue<float, MT, NGW, 4, WRITE_S1>(Phi, Gp, D, p, bt, gs, NGS, wg_lo, wg_hi, lane, lr, lg, wave, tb, S1,
                                            epart);
 }
 
@@ -894,39 +971,54 @@ namespace {
 
 inline unsigned blocks_for(long long waves) { return (unsigned)((waves + 3) / 4); }
 
-template <typename T, int MT, int NGW>
+template <typename T, int MT, int NGW, int NW>
 hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
   const int gper = (a.D.r2 + a.NGS - 1) / a.NGS;
-  const size_t lds = (2 * 4 * (size_t)gper * 16) * sizeof(T);
+  if ((gper + NW - 1) / NW > NGW) return hipErrorInvalidValue;  // the plan gives every wavefront <= NGW rows
+  constexpr int RP = 16 * MT;
+  constexpr bool lds_g = NW == 8 && sizeof(T) == 4 && MT == 3;  // the slab-in-LDS form of k_core
+  constexpr size_t slab = lds_g ? (size_t)RP * (RP % 32 == 0 ? RP + 16 : RP) : 0;
+  const size_t lds = (2 * slab + 2 * NW * (size_t)gper * 16) * sizeof(T);
   const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
   if (lds > 64 * 1024) {  // opt in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
-    const void *fn = want_vx ? (const void *)k_core<T, MT, NGW, true> : (const void *)k_core<T, MT, NGW, false>;
+    const void *fn =
+        want_vx ? (const void *)k_core<T, MT, NGW, NW, true> : (const void *)k_core<T, MT, NGW, NW, false>;
     const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
   }
   if (want_vx)
-    hipLaunchKernelGGL((k_core<T, MT, NGW, true>), dim3(nb), dim3(256), lds, s, a.G, a.D, a.P, a.NGS, tb, a.S1,
-                       a.epart);
+    hipLaunchKernelGGL((k_core<T, MT, NGW, NW, true>), dim3(nb), dim3(64 * NW), lds, s, a.G, a.D, a.P, a.NGS, tb,
+                       a.S1, a.epart);
   else
-    hipLaunchKernelGGL((k_core<T, MT, NGW, false>), dim3(nb), dim3(256), lds, s, a.G, a.D, a.P, a.NGS, tb, a.S1,
-                       a.epart);
+    hipLaunchKernelGGL((k_core<T, MT, NGW, NW, false>), dim3(nb), dim3(64 * NW), lds, s, a.G, a.D, a.P, a.NGS, tb,
+                       a.S1, a.epart);
   return hipGetLastError();
 }
 
 // register budget of the Phi accumulators: MT * NGW * 4 values per lane
 constexpr int NGW64[MAX_MT + 1] = {0, 4, 8, 10, 8, 6};
 constexpr int NGW32[MAX_MT + 1] = {0, 4, 8, 10, 12, 10};
+// FP32 core at small ranks: eight wavefronts per workgroup (two per SIMD, so
+// one hides the other's latencies), each with fewer Phi rows
+constexpr int NW32[MAX_MT + 1] = {0, 8, 8, 8, 4, 4};
+constexpr int NGW32x8[MAX_MT + 1] = {0, 2, 4, 6, 0, 0};
 
 template <typename T>
 hipError_t launch_core(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
   const int mt = max(a.D.MT0, max(a.D.MT1, a.D.MT2));
   constexpr bool f64 = sizeof(T) == 8;
   switch (mt) {
-    case 1: return launch_core_mt<T, 1, (f64 ? NGW64[1] : NGW32[1])>(tb, a, want_vx, s);
-    case 2: return launch_core_mt<T, 2, (f64 ? NGW64[2] : NGW32[2])>(tb, a, want_vx, s);
-    case 3: return launch_core_mt<T, 3, (f64 ? NGW64[3] : NGW32[3])>(tb, a, want_vx, s);
-    case 4: return launch_core_mt<T, 4, (f64 ? NGW64[4] : NGW32[4])>(tb, a, want_vx, s);
-    case 5: return launch_core_mt<T, 5, (f64 ? NGW64[5] : NGW32[5])>(tb, a, want_vx, s);
+    case 1:
+      if constexpr (f64) return launch_core_mt<T, 1, NGW64[1], 4>(tb, a, want_vx, s);
+      else return launch_core_mt<T, 1, NGW32x8[1], 8>(tb, a, want_vx, s);
+    case 2:
+      if constexpr (f64) return launch_core_mt<T, 2, NGW64[2], 4>(tb, a, want_vx, s);
+      else return launch_core_mt<T, 2, NGW32x8[2], 8>(tb, a, want_vx, s);
+    case 3:
+      if constexpr (f64) return launch_core_mt<T, 3, NGW64[3], 4>(tb, a, want_vx, s);
+      else return launch_core_mt<T, 3, NGW32x8[3], 8>(tb, a, want_vx, s);
+    case 4: return launch_core_mt<T, 4, (f64 ? NGW64[4] : NGW32[4]), 4>(tb, a, want_vx, s);
+    case 5: return launch_core_mt<T, 5, (f64 ? NGW64[5] : NGW32[5]), 4>(tb, a, want_vx, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1058,7 +1150,11 @@ hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx,
 
 }  // namespace
 
-int core_ngw(bool f64, int mt) { return f64 ? NGW64[mt] : NGW32[mt]; }
+int core_rows(bool f64, bool split_bf16, int mt) {
+  if (f64) return 4 * NGW64[mt];
+  if (split_bf16 || NW32[mt] == 4) return 4 * NGW32[mt];
+  return 8 * NGW32x8[mt];
+}
 
 hipError_t run_chunk_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s,
                          Prof *prof) {
