@@ -141,8 +141,12 @@ def bench_batched(args, txe, torch, W):
     torch.cuda.synchronize()
     kt = ctx.kernel_times()
     ctx.profile(False)
-    lanes = 4
-    bat_s = timed(lambda: txe.apply_batched(ctx, items, compute="f32", lanes=lanes))
+    # concurrency of the batch: the lane count with the fastest eager batch
+    lane_ms = {}
+    for ln in (1, 2, 4):
+        lane_ms[ln] = 1e3 * timed(lambda: txe.apply_batched(ctx, items, compute="f32", lanes=ln))
+    lanes = min(lane_ms, key=lane_ms.get)
+    bat_s = lane_ms[lanes] / 1e3
     g = txe.Graph(ctx, items, compute="f32", lanes=lanes)
     graph_s = timed(g.launch)
     ex32 = [float(o[1]) for o in g.outputs]
@@ -162,7 +166,8 @@ def bench_batched(args, txe, torch, W):
         "config": {"workload": W.WORKLOAD_NAMES["cfg5"], "systems": len(systems), "pairs": npairs,
                    "mode": "one captured graph, symmetric unique pairs per system", "lanes": lanes},
         "separate_launches": {"value": round(npairs / sep_s, 1), "ms_per_step": round(1e3 * sep_s, 4)},
-        "batched_eager": {"value": round(npairs / bat_s, 1), "ms_per_step": round(1e3 * bat_s, 4)},
+        "batched_eager": {"value": round(npairs / bat_s, 1), "ms_per_step": round(1e3 * bat_s, 4),
+                          "ms_by_lanes": {str(k): round(v, 3) for k, v in lane_ms.items()}},
         "graph_over_separate": round(sep_s / graph_s, 3),
         "max_dE_x_fp32_vs_fp64_Ha": max(dE),
         "all_within_1e-5_Ha": max(dE) <= 1e-5,
@@ -276,9 +281,11 @@ def main():
     per_launch_ms = core_ms / max(core_n, 1)
     achieved = core_kernel_flops_per_pair(n, r, K) * npairs / (per_launch_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[use]
+    measured = ctx.ceiling(use)  # this device's MFMA rate for the same dtype (microbenchmark)
     roof = {"bound": "mfma", "kernel": "core", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": load_traffic(use, args.config),
-            "launch_ms": round(per_launch_ms, 4)}
+            "launch_ms": round(per_launch_ms, 4), "measured_peak": round(measured, 1),
+            "frac_of_measured": round(achieved / measured, 4)}
 
     out = {
         "metric": METRIC,
@@ -313,6 +320,10 @@ def main():
         "whole_path_tflops": round(flops_per_pair(n, r, K) * npairs / (ms / 1e3) / 1e12, 3),
         "roofline": roof,
         "launch_shapes": tuned,
+        "measured_ceilings": {"f64_mfma_tflops": round(ctx.ceiling("f64"), 1),
+                              "f32_mfma_tflops": round(ctx.ceiling("f32"), 1),
+                              "bf16_mfma_tflops": round(ctx.ceiling("bf16"), 1),
+                              "hbm_stream_gbs": round(ctx.ceiling("hbm"), 1)},
     }
     if args.retune:
         txe.tune_save(ctx, TUNE_CACHE)

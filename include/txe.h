@@ -98,6 +98,11 @@ typedef struct {
   int32_t K;                /* number of Gaussian terms, 1 <= K <= 256                      */
   const double *w;          /* host: K weights w_k (finite)                                 */
   const double *alpha;      /* host: K exponents alpha_k >= 0 (finite)                      */
+  const double *C[3];       /* optional host: K x n[d] x n[d] row-major 1-D convolution     */
+                            /* matrices C_k^d[a][b] of mode d (e.g. of another element      */
+                            /* order or a non-uniform mesh, eq. `discInteg`); NULL = the    */
+                            /* built-in linear-FE closed form, which needs uniform nodes.   */
+                            /* With C[d] given, x[d] need only be strictly increasing.      */
 } txe_system_desc;
 
 /* Arguments of one apply. */
@@ -238,6 +243,15 @@ txe_status txe_tune_save(txe_context *ctx, const char *path);
  * may be NULL) = entries read.  A malformed entry or an out-of-range shape
  * fails the whole load (TXE_ERR_ARG) and changes nothing. */
 txe_status txe_tune_load(txe_context *ctx, const char *path, int32_t *loaded);
+
+/* Measured ceilings of this device (the denominators a roofline can use
+ * next to the published peaks): kind 0 = FP64 MFMA 16x16x4, 1 = FP32 MFMA
+ * 16x16x4, 2 = bf16 MFMA 16x16x32 (TFLOP/s, 8 independent accumulator
+ * chains per wavefront, 4 workgroups of 256 per CU); 3 = HBM stream
+ * dst = 2*src over 512 MiB (GB/s, bytes read + written).  *value (host)
+ * receives the rate.  Allocates (kind 3: 1 GiB, freed before return) and
+ * waits for the context stream. */
+txe_status txe_measure_ceiling(txe_context *ctx, int32_t kind, double *value);
 
 #ifdef __cplusplus
 }

@@ -118,7 +118,7 @@ static bool finite_all(const double *p, size_t n) {
   return true;
 }
 
-static txe_status check_grid_1d(int n, const double *x, const char *what) {
+static txe_status check_grid_1d(int n, const double *x, const char *what, bool uniform = true) {
   if (!x) return fail(TXE_ERR_ARG, "%s: null node array", what);
   if (!finite_all(x, n)) return fail(TXE_ERR_ARG, "%s: non-finite node", what);
   const double h = x[1] - x[0];
@@ -126,7 +126,8 @@ static txe_status check_grid_1d(int n, const double *x, const char *what) {
   for (int i = 1; i < n; ++i) {
     const double hi = x[i] - x[i - 1];
     if (!(hi > 0)) return fail(TXE_ERR_ARG, "%s: nodes must be strictly increasing", what);
-    if (std::fabs(hi - h) > 1e-9 * std::fabs(h)) return fail(TXE_ERR_UNSUPPORTED, "%s: nodes must be uniformly spaced", what);
+    if (uniform && std::fabs(hi - h) > 1e-9 * std::fabs(h))
+      return fail(TXE_ERR_UNSUPPORTED, "%s: nodes must be uniformly spaced (or give C)", what);
   }
   return TXE_OK;
 }
@@ -441,7 +442,8 @@ extern "C" txe_status txe_system_create(txe_context *ctx, const txe_system_desc 
     if (r < 1 || r > n || r > 16 * MAX_MT) return fail(TXE_ERR_SHAPE, "r[%d] = %d must be in [1, min(n, %d)]", d, r, 16 * MAX_MT);
     char what[16];
     snprintf(what, sizeof what, "x[%d]", d);
-    txe_status st = check_grid_1d(n, desc->x[d], what);
+    // the built-in linear-FE builder needs uniform nodes; user matrices do not
+    txe_status st = check_grid_1d(n, desc->x[d], what, desc->C[d] == nullptr);
     if (st != TXE_OK) return st;
     if (!desc->q[d] || !desc->U[d]) return fail(TXE_ERR_ARG, "q[%d] or U[%d] is null", d, d);
     if (!finite_all(desc->q[d], n)) return fail(TXE_ERR_ARG, "q[%d] has a non-finite entry", d);
@@ -466,6 +468,9 @@ extern "C" txe_status txe_system_create(txe_context *ctx, const txe_system_desc 
     return fail(TXE_ERR_ARG, "w and alpha must be finite");
   for (int k = 0; k < desc->K; ++k)
     if (desc->alpha[k] < 0) return fail(TXE_ERR_ARG, "alpha[%d] < 0", k);
+  for (int d = 0; d < 3; ++d)
+    if (desc->C[d] && !finite_all(desc->C[d], (size_t)desc->K * desc->n[d] * desc->n[d]))
+      return fail(TXE_ERR_ARG, "C[%d] has a non-finite entry", d);
 
   auto *S = new txe_system();
   S->ctx = ctx;
@@ -486,8 +491,12 @@ extern "C" txe_status txe_system_create(txe_context *ctx, const txe_system_desc 
     S->C[d].assign((size_t)S->K * n * n, 0.0);
     S->Chat[d].assign((size_t)S->K * r * r, 0.0);
     bool reused = false;
+    if (desc->C[d]) {  // caller's matrices (e.g. another element order or mesh)
+      S->C[d].assign(desc->C[d], desc->C[d] + (size_t)S->K * n * n);
+      reused = true;
+    }
     for (int e = 0; e < d && !reused; ++e)
-      if (S->x[e] == S->x[d]) {
+      if (!desc->C[e] && S->x[e] == S->x[d]) {
         S->C[d] = S->C[e];
         reused = true;
       }
@@ -1124,5 +1133,24 @@ extern "C" txe_status txe_tune_load(txe_context *ctx, const char *path, int32_t 
   if (st != TXE_OK) return st;
   for (const auto &kv : got) ctx->plans[kv.first] = kv.second;
   if (loaded) *loaded = (int32_t)got.size();
+  return ok();
+}
+
+// ------------------------------------------------------------------------------------
+// measured ceilings
+// ------------------------------------------------------------------------------------
+extern "C" txe_status txe_measure_ceiling(txe_context *ctx, int32_t kind, double *value) {
+  if (!ctx || !value) return fail(TXE_ERR_ARG, "null argument");
+  if (kind < 0 || kind > 3) return fail(TXE_ERR_ARG, "kind %d not in [0, 3]", kind);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(ctx->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone) return fail(TXE_ERR_STATE, "cannot measure while the stream is captured");
+  HIP_TRY(hipSetDevice(ctx->device));
+  const hipError_t e = measure_ceiling(kind, ctx->stream, value);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    return fail(TXE_ERR_NOMEM, "no memory for the stream buffers");
+  }
+  if (e != hipSuccess) return device_failed(ctx, e);
   return ok();
 }

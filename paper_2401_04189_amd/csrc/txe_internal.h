@@ -171,6 +171,10 @@ hipError_t run_chunk_bf16(const Tables<float> &tb, const BfTables &bt, int nspli
 hipError_t run_energy(const double *epair, long long npairs, int symmetric, int N, double *ex, double *e_out,
                       hipStream_t s, Prof *prof);
 
+// Ceiling microbenchmarks (txe_ceiling.hip): kind 0 f64, 1 f32, 2 bf16 MFMA
+// in TFLOP/s; 3 HBM stream in GB/s.  Allocates, synchronises the stream.
+hipError_t measure_ceiling(int kind, hipStream_t s, double *value);
+
 // Core-kernel variant choice (register budget per precision).
 int core_rows(bool f64, bool split_bf16, int mt);  // gamma' rows one core workgroup covers
 

@@ -32,6 +32,7 @@ class SystemDesc(ctypes.Structure):
         ("K", _c_int),
         ("w", ctypes.c_void_p),
         ("alpha", ctypes.c_void_p),
+        ("C", ctypes.c_void_p * 3),
     ]
 
 
@@ -84,6 +85,7 @@ SIGNATURES = {
                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "txe_tune_save": (_c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "txe_tune_load": (_c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
+    "txe_measure_ceiling": (_c_int, [ctypes.c_void_p, _c_int, ctypes.POINTER(ctypes.c_double)]),
 }
 
 KERNELS = ("proj12", "proj3", "core", "epair", "back", "energy")
@@ -164,6 +166,12 @@ class Context:
             out[name] = (ms.value, n.value)
         return out
 
+    def ceiling(self, kind):
+        """Measured rate of this device: "f64", "f32", "bf16" MFMA (TFLOP/s) or "hbm" (GB/s)."""
+        v = ctypes.c_double()
+        _check(lib().txe_measure_ceiling(self.h, {"f64": 0, "f32": 1, "bf16": 2, "hbm": 3}[kind], ctypes.byref(v)))
+        return v.value
+
     def close(self):
         if getattr(self, "h", None):
             lib().txe_context_destroy(self.h)
@@ -179,10 +187,18 @@ class Context:
 class System:
     """Fixed data of one exchange problem: grid (x_d, q_d), bases U_d, (w_k, alpha_k)."""
 
-    def __init__(self, ctx: Context, x, q, U, w, alpha):
+    def __init__(self, ctx: Context, x, q, U, w, alpha, C=None):
+        """C: optional per-mode (K, n, n) 1-D convolution matrices (None = built-in)."""
         self.ctx = ctx
         self._keep = []
         d = SystemDesc()
+        for m in range(3):
+            if C is not None and C[m] is not None:
+                Cm = np.ascontiguousarray(C[m], dtype=np.float64)
+                if Cm.shape != (len(w), len(x[m]), len(x[m])):
+                    raise ValueError(f"C[{m}] must have shape (K, n, n) = {(len(w), len(x[m]), len(x[m]))}")
+                self._keep.append(Cm)
+                d.C[m] = Cm.ctypes.data
         for m in range(3):
             xm = np.ascontiguousarray(x[m], dtype=np.float64)
             qm = np.ascontiguousarray(q[m], dtype=np.float64)

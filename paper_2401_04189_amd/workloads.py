@@ -61,6 +61,22 @@ class Grid:
         return q[0][:, None, None] * q[1][None, :, None] * q[2][None, None, :]
 
 
+def graded_grid(n, L, stretch=1.5) -> Grid:
+    """Non-uniform nodes x = L sinh(stretch t) / sinh(stretch), t uniform on
+    [-1, 1] (fine at the centre, coarse at the ends); q = the integral of each
+    node's linear hat, with one mirrored ghost node beyond each end."""
+    n = tuple(int(v) for v in (n if isinstance(n, (tuple, list)) else (n, n, n)))
+    L = tuple(float(v) for v in (L if isinstance(L, (tuple, list)) else (L, L, L)))
+    xs, qs = [], []
+    for nd, Ld in zip(n, L):
+        t = np.linspace(-1.0, 1.0, nd)
+        x = Ld * np.sinh(stretch * t) / np.sinh(stretch)
+        xg = np.concatenate([[2 * x[0] - x[1]], x, [2 * x[-1] - x[-2]]])
+        xs.append(x)
+        qs.append(0.5 * (xg[2:] - xg[:-2]))
+    return Grid(n=n, L=L, x=xs, q=qs)
+
+
 def uniform_grid(n, L) -> Grid:
     n = tuple(int(v) for v in (n if isinstance(n, (tuple, list)) else (n, n, n)))
     L = tuple(float(v) for v in (L if isinstance(L, (tuple, list)) else (L, L, L)))
@@ -315,8 +331,8 @@ def make_orbitals(grid, N, ng, exp_range, seed, atoms=None, box=None, device="cp
 
 def make_system(name, n, L, N, ng, exp_range, r, K, seed, atoms=None, box=None,
                 mode="symmetric", i0=0, Ni=0, device="cpu", bases="hosvd",
-                s_range=(-8.0, 4.0), cond_max=1e8):
-    grid = uniform_grid(n, L)
+                s_range=(-8.0, 4.0), cond_max=1e8, grid=None):
+    grid = uniform_grid(n, L) if grid is None else grid
     psi, meta = make_orbitals(grid, N, ng, exp_range, seed, atoms=atoms, box=box, device=device,
                               cond_max=cond_max)
     if bases == "full":
