@@ -27,8 +27,9 @@ CAL_BYTES = 512 << 20
 
 
 def short(name):
+    name = name.replace("(anonymous namespace)::", "")
     name = re.sub(r"\(.*", "", name)
-    return name.replace("txe::", "").replace("void ", "")
+    return name.replace("txe::", "").replace("void ", "") or "(torch / runtime kernel)"
 
 
 def ktrace(stats_csv, out_md, cmd):
