@@ -104,6 +104,75 @@ def load_cache(args, txe, ctx):
         txe.tune_load(ctx, TUNE_CACHE)
 
 
+def bench_block(args, txe, torch, W):
+    """cfg4: a block of targets against all 1,842 sources at 128^3, r = 80,
+    K = 50, in FP64, FP32 MFMA and split-bf16; errors of each reduced form
+    against FP64 per result (block energy, Vx psi per orbital in the W-norm,
+    exchange-matrix diagonal <psi_i, Vx psi_i>_W)."""
+    t0 = time.perf_counter()
+    s = W.build_config("cfg4", device="cuda")
+    torch.cuda.empty_cache()
+    print(f"generated cfg4 in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = txe.Context(0)
+    sysm = txe.System.from_workload(ctx, s)
+    load_cache(args, txe, ctx)
+    psi = s.psi
+    N, Ni = s.N, args.targets
+    npairs = Ni * N
+    w3 = s.grid.weights3d(device="cuda")
+    legs = {}
+    for comp in ("f64", "f32", "bf16x3", "bf16x6"):
+        vx = torch.empty((Ni,) + tuple(psi.shape[1:]), dtype=psi.dtype, device="cuda")
+        for _ in range(max(args.warmup, 1)):
+            txe.apply(ctx, sysm, psi, compute=comp, symmetric=False, i0=0, Ni=Ni, vx_out=vx)
+        torch.cuda.synchronize()
+        print(f"{comp}: warm-up done", file=sys.stderr, flush=True)
+        ctx.profile(True)
+        t = time.perf_counter()
+        steps = max(1, min(args.steps, 3))
+        for it in range(steps):
+            _, ex, _ = txe.apply(ctx, sysm, psi, compute=comp, symmetric=False, i0=0, Ni=Ni, vx_out=vx)
+            torch.cuda.synchronize()
+            print(f"{comp}: step {it} done", file=sys.stderr, flush=True)
+        sec = (time.perf_counter() - t) / steps
+        kt = ctx.kernel_times()
+        ctx.profile(False)
+        diag = (psi[:Ni] * vx * w3).sum(dim=(1, 2, 3))
+        legs[comp] = dict(sec=sec, ex=float(ex), vx=vx, diag=diag, kt=kt, steps=steps)
+        print(f"{comp}: {sec * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    ref = legs["f64"]
+    out_legs = {}
+    for comp, L in legs.items():
+        e = {"value": round(npairs / L["sec"], 1), "ms_per_step": round(1e3 * L["sec"], 3), "E_block": L["ex"],
+             "core_ms": round(L["kt"]["core"][0] / max(L["kt"]["core"][1], 1), 3)}
+        if comp != "f64":
+            num = ((L["vx"] - ref["vx"]) ** 2 * w3).sum(dim=(1, 2, 3))
+            den = (ref["vx"] ** 2 * w3).sum(dim=(1, 2, 3))
+            e["dE_block_Ha"] = abs(L["ex"] - ref["ex"])
+            e["vx_rel_wnorm_max"] = float(torch.sqrt(num / den).max())
+            e["diag_abs_max_Ha"] = float((L["diag"] - ref["diag"]).abs().max())
+            e["over_fp64"] = round(ref["sec"] / L["sec"], 3)
+        out_legs[comp] = e
+    use = "f32" if out_legs["f32"]["dE_block_Ha"] <= 1e-5 else "f64"
+    core_ms = out_legs[use]["core_ms"]
+    achieved = core_kernel_flops_per_pair(s.grid.n, s.r, s.K) * npairs / (core_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": out_legs[use]["value"], "unit": "pair-convolutions/s",
+        "n_gpus": 1, "steps": legs[use]["steps"], "warmup": args.warmup,
+        "ms_per_step": out_legs[use]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": use, "data": "synthetic",
+        "config": {"workload": W.WORKLOAD_NAMES["cfg4"], "timed_block": f"targets 0..{Ni - 1} x {N} sources",
+                   "pairs": npairs, "rank": list(s.r), "terms": s.K},
+        "legs": out_legs,
+        "roofline": {"bound": "mfma", "kernel": "core", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[use],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[use], 4), "traffic": None,
+                     "launch_ms": core_ms},
+    }
+    sysm.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_batched(args, txe, torch, W):
     """cfg5: one graph replay of all systems against separate applies."""
     t0 = time.perf_counter()
@@ -113,9 +182,15 @@ def bench_batched(args, txe, torch, W):
     handles = [txe.System.from_workload(ctx, s) for s in systems]
     items = [(h, s.psi.contiguous()) for h, s in zip(handles, systems)]
     npairs = sum(s.N * (s.N + 1) // 2 for s in systems)
-    ex64 = [float(txe.apply(ctx, h, p, compute="f64", want_vx=False)[1]) for h, p in items]
+    ex64 = []
+    for k, (h, p) in enumerate(items):
+        ex64.append(float(txe.apply(ctx, h, p, compute="f64", want_vx=False)[1]))
+        print(f"FP64 energy of system {k}: {ex64[-1]:.10f}", file=sys.stderr, flush=True)
     load_cache(args, txe, ctx)
-    tuned = [shapes(args, txe, ctx, h, p, "f32") for h, p in items]
+    tuned = []
+    for k, (h, p) in enumerate(items):
+        tuned.append(shapes(args, txe, ctx, h, p, "f32"))
+        print(f"launch shape of system {k}: {tuned[-1]}", file=sys.stderr, flush=True)
     if args.retune:
         txe.tune_save(ctx, TUNE_CACHE)
     print(f"launch shapes: {sum(isinstance(t, dict) and t['source'] == 'cache' for t in tuned)} from the cache, "
@@ -213,7 +288,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--targets", type=int, default=8, help="cfg4: targets of the timed block (all 1,842 sources)")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--retune", action="store_true",
                     help="search launch shapes live (before the timed region) and write them to the cache file")
@@ -240,6 +316,9 @@ def main():
         sys.exit(2)
     if args.config == "cfg5":
         bench_batched(args, txe, torch, W)
+        return
+    if args.config == "cfg4":
+        bench_block(args, txe, torch, W)
         return
     s = W.build_config(args.config)
     n, r, K, N = s.grid.n, s.r, s.K, s.N

@@ -71,6 +71,16 @@ __device__ __forceinline__ void load4(const float *p, double (&o)[4]) {
 
 __device__ __forceinline__ long long sym_start(long long i, long long N) { return i * N - i * (i - 1) / 2; }
 
+// Workgroups are handed to the eight XCDs round-robin (block b runs on XCD
+// b mod 8), and each XCD has its own L2.  This bijection renumbers the grid
+// so that each XCD receives one contiguous range of logical block indices:
+// the workgroups of one pair (its beta' tiles and gamma' splits, which all
+// read the pair's core tensor G) then share an L2.
+__device__ __forceinline__ int xcd_order(int b, int nb) {
+  const int x = b & 7, slot = b >> 3, q = nb >> 3, rem = nb & 7;
+  return x * q + min(x, rem) + slot;
+}
+
 __device__ __forceinline__ void pair_ij(const PairMap &pm, long long pg, int &i, int &j) {
   if (!pm.symmetric) {
     i = pm.i0 + (int)(pg / pm.N);
@@ -351,8 +361,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
 
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
-  const int gs = blockIdx.x % NGS;
-  const int tt = blockIdx.x / NGS;
+  const int bid = xcd_order(blockIdx.x, gridDim.x);
+  const int gs = bid % NGS;
+  const int tt = bid / NGS;
   const int bt = tt % MT;
   const int p = tt / MT;
   if (p >= P) return;  // whole block leaves together
@@ -366,11 +377,18 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   const int nrow = max(0, wg_hi - wg_lo);         // this wavefront's gamma' rows (uniform)
   const T *Gp = G + (size_t)p * RP * F;
 
-  // eight-wavefront rank-3 form: the slab lives in LDS (double-buffered,
-  // row stride padded so the four lane groups hit different banks)
-  constexpr bool PF = sizeof(T) == 4 ? MT <= 3 : MT <= 2;
-  constexpr bool HOLD_G = PF && (NW == 4 || MT <= 2);
-  constexpr bool LDS_G = PF && !HOLD_G;
+  // Register plan per precision and rank tile:
+  //   PF     Chat1 / Ahat fragments prefetched one step ahead
+  //   C2S    Chat2 fragments loaded whole at the start of the step (else one
+  //          gamma' tile at a time inside the Z chain)
+  //   HOLD_G the slab's A fragments held in registers for all of its steps
+  //   LDS_G  the slab in LDS instead (double-buffered, row stride padded so
+  //          the four lane groups of a fragment load hit different banks)
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr bool PF = F32 || MT <= 2;
+  constexpr bool C2S = F32 ? MT <= 3 : MT <= 2;
+  constexpr bool HOLD_G = C2S && (NW == 4 || MT <= 2);
+  constexpr bool LDS_G = F32 && !HOLD_G;
   constexpr int SROW = RP % 32 == 0 ? RP + 16 : RP;
   constexpr int SLAB = LDS_G ? RP * SROW : 0;
   T *Gs = reinterpret_cast<T *>(smem_raw);        // [2][RP][SROW] (LDS_G)
@@ -383,10 +401,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
 #pragma unroll
     for (int ng = 0; ng < NGW; ++ng) Phi[mt][ng] = zero4<acc>();
 
-  // small ranks keep the slab's A fragments in registers for all terms and
-  // load the next step's term matrices while the current step computes;
-  // large ranks re-read the slab (L1-resident) and load the terms in place.
-  // Loops run over the padded size; padded rows and columns are zero.
+  // Loops run over the padded size; padded rows and columns of G and of the
+  // term matrices are zero.
   constexpr int GK = HOLD_G ? 4 * MT : 1, GM = HOLD_G ? MT : 1;
   constexpr int NTG = NW / 4;  // groups of four terms per step
   const int nkq = (D.K + NW - 1) / NW;
@@ -428,19 +444,32 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   T gf[GK][GM];  // held slab fragments
   if constexpr (PF) load_terms(0, 0, ca);
   const T *Ga = Gp + lr;
-  // LDS slab: the next slab arrives in 512-element chunks, chunk kq during
-  // step kq (a load at the start of the step, its store before the step's
-  // barrier); the loads are unconditional (clamped addresses) so every step
-  // issues the same loads
-  constexpr int NCH = LDS_G ? (RP * RP + 64 * NW - 1) / (64 * NW) : 0;
+  // LDS slab: the next slab arrives in (about) four chunks of EPT elements
+  // per thread, chunk kq during step kq (loaded at the start of the step,
+  // stored before the step's barrier); the loads are unconditional (clamped
+  // addresses) so every step issues the same loads
+  constexpr int CHT = 64 * NW;
+  constexpr int EPT = LDS_G ? (int)((F + 4 * CHT - 1) / (4 * CHT)) : 1;
+  constexpr int CH = EPT * CHT;
+  constexpr int NCH = LDS_G ? (int)((F + CH - 1) / CH) : 0;
   const int tid = threadIdx.x;
-  auto slab_elem = [&](int c) { return min(c * 64 * NW + tid, (int)(RP * RP) - 1); };
-  auto slab_store = [&](int c, int buf, T v) {
-    const int e = c * 64 * NW + tid;
-    if (e < RP * RP) Gs[buf * SLAB + (e / RP) * SROW + (e % RP)] = v;
+  auto slab_load = [&](int c, int a_, T (&v)[EPT]) {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) v[j] = Gp[(size_t)a_ * F + min(c * CH + j * CHT + tid, (int)F - 1)];
+  };
+  auto slab_store = [&](int c, int buf, const T (&v)[EPT]) {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = c * CH + j * CHT + tid;
+      if (e < (int)F) Gs[buf * SLAB + (e / RP) * SROW + (e % RP)] = v[j];
+    }
   };
   if constexpr (LDS_G) {
-    for (int c = 0; c < NCH; ++c) slab_store(c, 0, Gp[slab_elem(c)]);
+    for (int c = 0; c < NCH; ++c) {
+      T v[EPT];
+      slab_load(c, 0, v);
+      slab_store(c, 0, v);
+    }
     __syncthreads();
   }
   // one step: uses cur, prefetches the next step's operands into nxt
@@ -458,19 +487,21 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
         if constexpr (PF) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
       }
     }
-    T gnext = (T)0;
-    if constexpr (LDS_G) gnext = Gp[(size_t)min(alpha + 1, D.r0 - 1) * F + slab_elem(min(kq, NCH - 1))];
-    T c2s[PF ? MT : 1][PF ? MT : 1][4];
-    if constexpr (PF) {
+    T gnext[EPT];
+    if constexpr (LDS_G) slab_load(min(kq, NCH - 1), min(alpha + 1, D.r0 - 1), gnext);
+    T c2s[C2S ? MT : 1][C2S ? MT : 1][4];
+    if constexpr (C2S) {
       if (k < D.K) {
-      const T *C2k = tb.C2chain + (size_t)k * MT * MT * 256 + lane;
+        const T *C2k = tb.C2chain + (size_t)k * MT * MT * 256 + lane;
 #pragma unroll
-      for (int mtp = 0; mtp < MT; ++mtp)
+        for (int mtp = 0; mtp < MT; ++mtp)
 #pragma unroll
-        for (int mg = 0; mg < MT; ++mg)
+          for (int mg = 0; mg < MT; ++mg)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) c2s[mtp][mg][v] = C2k[((mtp * MT + mg) * 4 + v) * 64];
+            for (int v = 0; v < 4; ++v) c2s[mtp][mg][v] = C2k[((mtp * MT + mg) * 4 + v) * 64];
       }
+    }
+    if constexpr (PF) {
       const bool wrap = kq + 1 == nkq;
       if (step + 1 < nsteps) load_terms(wrap ? alpha + 1 : alpha, wrap ? 0 : kq + 1, nxt);
     }
@@ -498,10 +529,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
           W[mg] = M::mma(g, cur.cb[kt], W[mg]);
         }
       }
-      // all gamma' tiles; rows outside this workgroup's range are not stored.
-      // With prefetched f32 term matrices the tiles' chains are interleaved
-      // (short MFMA latency, cheap accumulators); otherwise one tile at a
-      // time, loading that tile's Chat2 fragments (keeps registers for Phi)
+      // Z rows outside this workgroup's gamma' range are not stored.  With
+      // Chat2 loaded whole (small ranks, FP32) the tiles' chains are
+      // interleaved (short MFMA latency, cheap accumulators); otherwise one
+      // tile at a time, skipping tiles outside the range and loading each
+      // tile's Chat2 fragments in turn (keeps registers for Phi)
       auto store_z = [&](int mtp, const acc &Zt) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -509,7 +541,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
           if (gp >= g_lo && gp < g_hi) Zw[(gp - g_lo) * 16 + lr] = Zt[v];
         }
       };
-      if constexpr (sizeof(T) == 4 && PF) {
+      if constexpr (F32 && C2S) {
         acc Z[MT];
 #pragma unroll
         for (int mtp = 0; mtp < MT; ++mtp) Z[mtp] = zero4<acc>();
@@ -525,8 +557,13 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
         const T *C2k = tb.C2chain + (size_t)k * MT * MT * 256 + lane;
 #pragma unroll
         for (int mtp = 0; mtp < MT; ++mtp) {
+          // only the gamma' tiles that meet this workgroup's rows (uniform);
+          // at five FP32 tiles the branch costs registers (spills) and more
+          // time than the skipped tiles save
+          if constexpr (!(F32 && MT == 5))
+            if (16 * mtp >= g_hi || 16 * mtp + 16 <= g_lo) continue;
           T c2[MT][4];
-          if constexpr (PF) {
+          if constexpr (C2S) {
 #pragma unroll
             for (int mg = 0; mg < MT; ++mg)
 #pragma unroll
@@ -553,7 +590,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
       if (alpha + 1 < D.r0) {
         if (kq < NCH) slab_store(kq, (alpha + 1) & 1, gnext);
         if (kq + 1 == nkq)  // fewer steps than chunks: the rest now
-          for (int c = nkq; c < NCH; ++c) slab_store(c, (alpha + 1) & 1, Gp[(size_t)(alpha + 1) * F + slab_elem(c)]);
+          for (int c = nkq; c < NCH; ++c) {
+            T v[EPT];
+            slab_load(c, alpha + 1, v);
+            slab_store(c, (alpha + 1) & 1, v);
+          }
       }
     }
     __syncthreads();
@@ -653,8 +694,9 @@ __global__ __launch_bounds__(256, 1) void k_core_bf(const float *__restrict__ G,
 
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gs = blockIdx.x % NGS;
-  const int tt = blockIdx.x / NGS;
+  const int bid = xcd_order(blockIdx.x, gridDim.x);
+  const int gs = bid % NGS;
+  const int tt = bid / NGS;
   const int bt = tt % MT;
   const int p = tt / MT;
   if (p >= P) return;
@@ -976,7 +1018,7 @@ hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_
   const int gper = (a.D.r2 + a.NGS - 1) / a.NGS;
   if ((gper + NW - 1) / NW > NGW) return hipErrorInvalidValue;  // the plan gives every wavefront <= NGW rows
   constexpr int RP = 16 * MT;
-  constexpr bool lds_g = NW == 8 && sizeof(T) == 4 && MT == 3;  // the slab-in-LDS form of k_core
+  constexpr bool lds_g = sizeof(T) == 4 && MT >= 3;  // the slab-in-LDS forms of k_core
   constexpr size_t slab = lds_g ? (size_t)RP * (RP % 32 == 0 ? RP + 16 : RP) : 0;
   const size_t lds = (2 * slab + 2 * NW * (size_t)gper * 16) * sizeof(T);
   const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);

@@ -110,15 +110,17 @@ def test_f64_cfg1(ctx):
 
 def test_f64_rank_tiles(ctx):
     """Ranks spanning 2..5 tiles of 16 (every core-kernel variant)."""
-    for r in (20, 40, 48, 70):
+    for r in (20, 40, 48, 60, 70):
         s = W.small_system(n=(max(24, r) + 3) // 4 * 4, L=6.0, N=2, r=r, K=10, seed=35)
         check_f64(ctx, s, label=f"r={r}")
 
 
 def test_f32_rank_tiles_against_f64(ctx):
     """Every FP32 core-kernel variant (2..5 rank tiles) against the GPU FP64 path."""
-    for r in (20, 40, 48, 70):
-        s = W.small_system(n=(max(24, r) + 3) // 4 * 4, L=6.0, N=2, r=r, K=10, seed=35)
+    # K = 10 gives fewer steps per slab than LDS slab chunks at 3..5 tiles;
+    # K = 24 at 4 tiles gives more
+    for r, K in ((20, 10), (40, 10), (48, 10), (60, 10), (60, 24), (70, 10)):
+        s = W.small_system(n=(max(24, r) + 3) // 4 * 4, L=6.0, N=2, r=r, K=K, seed=35)
         v64, e64, p64 = run_gpu(ctx, s, "f64")
         v32, e32, p32 = run_gpu(ctx, s, "f32")
         verr = rel_vx_err(v32, v64, s.grid.q)
@@ -133,7 +135,7 @@ def test_bf16_split_against_f64(ctx, form, tol):
     GPU FP64 path, every rank-tile variant.  The three-product form keeps
     ~16 bits per operand (2^-16 relative per product), the six-product form
     ~24 (FP32 level)."""
-    for r in (20, 40, 48, 70):
+    for r in (20, 40, 48, 60, 70):
         s = W.small_system(n=(max(24, r) + 3) // 4 * 4, L=6.0, N=2, r=r, K=10, seed=35)
         v64, e64, p64 = run_gpu(ctx, s, "f64")
         vb, eb, pb = run_gpu(ctx, s, form)
