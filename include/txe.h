@@ -219,12 +219,14 @@ txe_status txe_graph_destroy(txe_graph *graph);
  * registers; knobs[1] gamma tiles per wavefront of the projection kernel
  * (1..3); knobs[2] c tiles per wavefront of the back-projection kernel (1, 2;
  * 0 = chosen by size); knobs[3] workgroups of the persistent projection and
- * back-projection kernels.  Results do not depend on knobs[1..3]; knobs[0]
- * changes the summation order of the pair energies only.
+ * back-projection kernels; knobs[4] form of the back-projection kernel (1
+ * streaming, 2 batched loads; 0 = by precision).  Results do not depend on
+ * knobs[1..4]; knobs[0] changes the summation order of the pair energies
+ * only.
  *
  * txe_tune times txe_apply with these args (each candidate: one warm-up and
  * `reps` timed applies, HIP events on the context stream; the host waits) in
- * coordinate descent from the defaults {1, 2, 0, 2048}, at most two sweeps,
+ * coordinate descent from the defaults {1, 2, 0, 2048, 0}, at most two sweeps,
  * and keeps the fastest in the context under a key made of the device
  * architecture, grid, ranks, K, N, Ni, compute, mode and whether Vx psi is
  * wanted.  Later applies, batches and graphs with the same key use it.  The
@@ -232,12 +234,13 @@ txe_status txe_graph_destroy(txe_graph *graph);
  * time of the chosen shape.  Not allowed during capture (TXE_ERR_STATE). */
 txe_status txe_tune(txe_context *ctx, const txe_system *sys, const txe_apply_args *args, int32_t reps,
                     double *best_ms);
-/* The launch shape an apply with these args would use (host knobs[4]);
+/* The launch shape an apply with these args would use (host knobs[5]);
  * *tuned (host, may be NULL) = 1 if it came from the tuner or a cache. */
-txe_status txe_plan_get(txe_context *ctx, const txe_system *sys, const txe_apply_args *args, int32_t knobs[4],
+txe_status txe_plan_get(txe_context *ctx, const txe_system *sys, const txe_apply_args *args, int32_t knobs[5],
                         int32_t *tuned);
 /* The context's tuned shapes as a JSON object {key: {"ngs_mul", "proj_gt",
- * "back_ncg", "grid_cap"}}, one entry per line (overwrites `path`). */
+ * "back_ncg", "grid_cap", "back_form"}}, one entry per line (overwrites
+ * `path`).  On load a missing "back_form" means 0. */
 txe_status txe_tune_save(txe_context *ctx, const char *path);
 /* Merges a file written by txe_tune_save into the context; *loaded (host,
  * may be NULL) = entries read.  A malformed entry or an out-of-range shape

@@ -43,6 +43,7 @@ struct Knobs {
   int proj_gt = 2;     // gamma tiles per wavefront in proj12 (1, 2, 3)
   int back_ncg = 0;    // c tiles per wavefront in back (1, 2; 0 = by size)
   int grid_cap = 2048; // workgroups of the persistent proj12 / back kernels
+  int back_form = 0;   // back kernel form (1 streaming, 2 batched; 0 = by precision)
 };
 
 struct txe_context {
@@ -659,7 +660,8 @@ static Knobs knobs_for(const txe_context *ctx, const txe_system *sys, const txe_
 
 static bool knobs_valid(const Knobs &k) {
   return (k.ngs_mul == 1 || k.ngs_mul == 2 || k.ngs_mul == 4) && k.proj_gt >= 1 && k.proj_gt <= 3 &&
-         k.back_ncg >= 0 && k.back_ncg <= 2 && k.grid_cap >= 256 && k.grid_cap <= 16384;
+         k.back_ncg >= 0 && k.back_ncg <= 2 && k.grid_cap >= 256 && k.grid_cap <= 16384 && k.back_form >= 0 &&
+         k.back_form <= 2;
 }
 
 static txe_status validate_args(const txe_context *ctx, const txe_system *sys, const txe_apply_args *a) {
@@ -717,6 +719,7 @@ static ChunkArgs<T> chunk_args(const txe_system *sys, const txe_apply_args *a, c
   c.proj_gt = pl.kn.proj_gt;
   c.back_ncg = pl.kn.back_ncg;
   c.grid_cap = pl.kn.grid_cap;
+  c.back_form = pl.kn.back_form;
   c.psi = a->psi;
   c.vx = a->vxpsi;
   c.out_scale = a->out_scale;
@@ -1030,14 +1033,18 @@ extern "C" txe_status txe_tune(txe_context *ctx, const txe_system *sys, const tx
   Knobs best{};
   double best_t = 0.0;
   txe_status st = time_apply(ctx, sys, args, best, reps, &best_t);
-  const std::vector<int> ngs = {1, 2, 4}, gt = {1, 2, 3}, ncg = {1, 2}, cap = {1024, 2048, 4096};
+  const std::vector<int> ngs = {1, 2, 4}, gt = {1, 2, 3}, ncg = {1, 2}, cap = {1024, 2048, 4096}, form = {1, 2};
   for (int sweep = 0; sweep < 2 && st == TXE_OK; ++sweep) {
     const Knobs start = best;
-    for (int knob = 0; knob < 4 && st == TXE_OK; ++knob) {
-      const std::vector<int> &vals = knob == 0 ? ngs : knob == 1 ? gt : knob == 2 ? ncg : cap;
+    for (int knob = 0; knob < 5 && st == TXE_OK; ++knob) {
+      const std::vector<int> &vals = knob == 0 ? ngs : knob == 1 ? gt : knob == 2 ? ncg : knob == 3 ? cap : form;
       for (int v : vals) {
         Knobs k = best;
-        int &field = knob == 0 ? k.ngs_mul : knob == 1 ? k.proj_gt : knob == 2 ? k.back_ncg : k.grid_cap;
+        int &field = knob == 0 ? k.ngs_mul
+                     : knob == 1 ? k.proj_gt
+                     : knob == 2 ? k.back_ncg
+                     : knob == 3 ? k.grid_cap
+                                 : k.back_form;
         if (field == v) continue;
         field = v;
         double t = 0.0;
@@ -1049,7 +1056,7 @@ extern "C" txe_status txe_tune(txe_context *ctx, const txe_system *sys, const tx
       }
     }
     if (start.ngs_mul == best.ngs_mul && start.proj_gt == best.proj_gt && start.back_ncg == best.back_ncg &&
-        start.grid_cap == best.grid_cap)
+        start.grid_cap == best.grid_cap && start.back_form == best.back_form)
       break;
   }
   ctx->prof.on = prof_on;
@@ -1060,14 +1067,14 @@ extern "C" txe_status txe_tune(txe_context *ctx, const txe_system *sys, const tx
 }
 
 extern "C" txe_status txe_plan_get(txe_context *ctx, const txe_system *sys, const txe_apply_args *args,
-                                   int32_t knobs[4], int32_t *tuned) {
+                                   int32_t knobs[5], int32_t *tuned) {
   if (!ctx || !sys || !args || !knobs) return fail(TXE_ERR_ARG, "null argument");
   txe_status st = validate_args(ctx, sys, args);
   if (st != TXE_OK) return st;
   const std::string key = plan_key(ctx, sys, args);
   auto it = ctx->plans.find(key);
   const Knobs k = it == ctx->plans.end() ? Knobs{} : it->second;
-  knobs[0] = k.ngs_mul; knobs[1] = k.proj_gt; knobs[2] = k.back_ncg; knobs[3] = k.grid_cap;
+  knobs[0] = k.ngs_mul; knobs[1] = k.proj_gt; knobs[2] = k.back_ncg; knobs[3] = k.grid_cap; knobs[4] = k.back_form;
   if (tuned) *tuned = it != ctx->plans.end();
   return ok();
 }
@@ -1075,9 +1082,10 @@ extern "C" txe_status txe_plan_get(txe_context *ctx, const txe_system *sys, cons
 // Cache file: a JSON object mapping each problem key to its launch shape,
 // one entry per line:
 //   {
-//    "gfx950|n=64,64,64|...": {"ngs_mul": 1, "proj_gt": 2, "back_ncg": 0, "grid_cap": 2048},
+//    "gfx950|n=64,64,64|...": {"ngs_mul": 1, "proj_gt": 2, "back_ncg": 0, "grid_cap": 2048, "back_form": 0},
 //    ...
 //   }
+// ("back_form" may be absent: 0.)
 extern "C" txe_status txe_tune_save(txe_context *ctx, const char *path) {
   if (!ctx || !path) return fail(TXE_ERR_ARG, "null argument");
   FILE *f = fopen(path, "w");
@@ -1086,8 +1094,9 @@ extern "C" txe_status txe_tune_save(txe_context *ctx, const char *path) {
   size_t i = 0;
   for (const auto &kv : ctx->plans) {
     const Knobs &k = kv.second;
-    fprintf(f, " \"%s\": {\"ngs_mul\": %d, \"proj_gt\": %d, \"back_ncg\": %d, \"grid_cap\": %d}%s\n",
-            kv.first.c_str(), k.ngs_mul, k.proj_gt, k.back_ncg, k.grid_cap, ++i < ctx->plans.size() ? "," : "");
+    fprintf(f, " \"%s\": {\"ngs_mul\": %d, \"proj_gt\": %d, \"back_ncg\": %d, \"grid_cap\": %d, \"back_form\": %d}%s\n",
+            kv.first.c_str(), k.ngs_mul, k.proj_gt, k.back_ncg, k.grid_cap, k.back_form,
+            ++i < ctx->plans.size() ? "," : "");
   }
   fprintf(f, "}\n");
   const bool bad = ferror(f) != 0;
@@ -1123,7 +1132,9 @@ extern "C" txe_status txe_tune_load(txe_context *ctx, const char *path, int32_t 
     Knobs k;
     if (q1 == std::string::npos || !read_int_field(line, "ngs_mul", &k.ngs_mul) ||
         !read_int_field(line, "proj_gt", &k.proj_gt) || !read_int_field(line, "back_ncg", &k.back_ncg) ||
-        !read_int_field(line, "grid_cap", &k.grid_cap) || !knobs_valid(k)) {
+        !read_int_field(line, "grid_cap", &k.grid_cap) ||
+        (line.find("\"back_form\":") != std::string::npos && !read_int_field(line, "back_form", &k.back_form)) ||
+        !knobs_valid(k)) {
       st = fail(TXE_ERR_ARG, "%s:%d: not a valid cache entry", path, lineno);
       break;
     }

@@ -375,10 +375,10 @@ def tune(ctx: Context, sysm: System, psi, compute="f32", symmetric=True, i0=0, N
 def plan(ctx: Context, sysm: System, psi, compute="f32", symmetric=True, i0=0, Ni=None, want_vx=True):
     """(knobs dict, tuned flag) an apply with these arguments would use."""
     a, vx, ex, ep = _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, False)
-    k = (ctypes.c_int32 * 4)()
+    k = (ctypes.c_int32 * 5)()
     tuned = ctypes.c_int32()
     _check(lib().txe_plan_get(ctx.h, sysm.h, ctypes.byref(a), k, ctypes.byref(tuned)))
-    return dict(ngs_mul=k[0], proj_gt=k[1], back_ncg=k[2], grid_cap=k[3]), bool(tuned.value)
+    return dict(ngs_mul=k[0], proj_gt=k[1], back_ncg=k[2], grid_cap=k[3], back_form=k[4]), bool(tuned.value)
 
 
 def tune_save(ctx: Context, path):
