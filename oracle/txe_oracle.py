@@ -29,9 +29,11 @@ time, in the order the paper gives the steps:
         the functional S with the mixing fraction set to 1).
   * O6  Gradient dE_x/dpsi_i = 2 w (Vx psi_i) with w the 3-D grid weights.
 
-Readings where the paper is silent (grid, boundary, element order, bases,
-where the convolution is evaluated) are listed in the design doc; they are the
-same for the oracle and the GPU path.  Parity of the Tucker-truncated
+Where the paper is silent the oracle takes these readings, the same ones
+the GPU path takes: uniform 1-D nodes, every node carrying a full linear hat
+(a ghost node beyond each end), weights q = h; bases shared by all pairs and
+q-orthonormal; the kernel sum evaluated in the Tucker core and then
+back-projected (phi = P C P rho).  Parity of the Tucker-truncated
 (r < n) result against anything but this oracle is unpinned (no closed form
 exists for it); the full-rank case is pinned to a dense 3-D kernel apply.
 """

@@ -35,7 +35,7 @@ def short(name):
 def ktrace(stats_csv, out_md, cmd):
     rows = list(csv.DictReader(open(stats_csv)))
     lines = ["# Kernel trace: 64^3 exchange apply (2080 unique pairs, r = 40, K = 40)", "",
-             "Command (from the repository root on the GPU box):", "", "```", cmd, "```", "",
+             "Command (from the repository root, on the machine with the GPU):", "", "```", cmd, "```", "",
              "| Kernel | Calls | Average (ms) | Min (ms) | Max (ms) | Share |", "|---|---|---|---|---|---|"]
     for r in rows:
         lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} | "
