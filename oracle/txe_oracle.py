@@ -28,6 +28,10 @@ time, in the order the paper gives the steps:
   * O5  Exchange energy E_x = -1/2 sum_{i,j} e_ij (the exact-exchange term of
         the functional S with the mixing fraction set to 1).
   * O6  Gradient dE_x/dpsi_i = 2 w (Vx psi_i) with w the 3-D grid weights.
+  * O7  Adaptively compressed exchange (section "ACE implementation"): from
+        W_i = Vx psi_i, the matrix M_ij = <psi_i, W_j>_W, its Cholesky factor
+        M = -L L^T, the projection vectors xi_k = sum_i W_i (L^-1)_ki (eq.
+        `eta`) and the operator V_ACE = -sum_k xi_k <xi_k, .>_W.
 
 Where the paper is silent the oracle takes these readings, the same ones
 the GPU path takes: uniform 1-D nodes, every node carrying a full linear hat
@@ -250,6 +254,39 @@ def energy_change_one_orbital(psi, st: Setup, m, delta):
         return tot
 
     return contrib(new) - contrib(psi[m])
+
+
+# ---------------------------------------------------------------------------------------
+# O7: adaptively compressed exchange (section "ACE implementation")
+# ---------------------------------------------------------------------------------------
+def ace_build(psi, W, q):
+    """The ACE projection vectors from the orbitals psi_i and their exchange
+    actions W_i = Vx psi_i (arrays N x n0 x n1 x n2):
+
+        M_ij = <psi_i, W_j>_W            (the paper's integral, on the grid)
+        M = -L L^T                       (Cholesky factor of -M)
+        xi_k = sum_i W_i (L^{-1})_{ki}
+
+    Returns (M, L, xi)."""
+    N = psi.shape[0]
+    w3 = weights3d(q).reshape(-1)
+    P = psi.reshape(N, -1)
+    Wm = W.reshape(N, -1)
+    M = P @ (Wm * w3[None, :]).T
+    L = np.linalg.cholesky(-M)
+    Linv = np.linalg.inv(L)
+    xi = (Linv @ Wm).reshape(W.shape)
+    return M, L, xi
+
+
+def ace_apply(xi, q, phi):
+    """V_ACE phi_j = - sum_k xi_k <xi_k, phi_j>_W for trial functions phi
+    (Nphi x n0 x n1 x n2)."""
+    w3 = weights3d(q).reshape(-1)
+    X = xi.reshape(xi.shape[0], -1)
+    F = phi.reshape(phi.shape[0], -1)
+    C = X @ (F * w3[None, :]).T          # C[k, j] = <xi_k, phi_j>_W
+    return (-(C.T @ X)).reshape(phi.shape)
 
 
 # ---------------------------------------------------------------------------------------

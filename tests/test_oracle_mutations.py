@@ -86,3 +86,48 @@ _orig = {"core_sum": O.core_sum, "conv_matrix_1d": O.conv_matrix_1d, "pair": O.p
 def test_planted_mistake_is_caught(monkeypatch, name, fn):
     monkeypatch.setattr(O, name, fn)
     assert _pins_fail(), f"a planted mistake in oracle step {name} ({fn.__name__}) went unnoticed"
+
+
+def _ace_pins_fail():
+    s = W.small_system(n=10, L=5.0, N=3, r=6, K=6, seed=21)
+    st = O.Setup.from_system(s)
+    psi = s.psi.numpy()
+    vx, _ = O.apply(psi, st)
+    M, L, xi = O.ace_build(psi, vx, st.q)
+    fixture = (s, st, psi, vx, M, L, xi)
+    for c in (P.test_ace_exact_on_the_orbitals, P.test_ace_factor_and_matrix,
+              P.test_ace_operator_symmetric_nsd_and_rank):
+        try:
+            c(fixture)
+        except (AssertionError, ValueError, np.linalg.LinAlgError):
+            return True
+    return False
+
+
+def test_unmutated_ace_passes():
+    assert not _ace_pins_fail()
+
+
+@pytest.mark.parametrize("mistake", ["transposed_inverse", "dropped_weights", "sign"])
+def test_ace_mistakes_are_caught(monkeypatch, mistake):
+    orig_build, orig_apply = O.ace_build, O.ace_apply
+
+    def bad_build(psi, Wv, q):
+        N = psi.shape[0]
+        w3 = O.weights3d(q).reshape(-1)
+        P_, Wm = psi.reshape(N, -1), Wv.reshape(N, -1)
+        M = P_ @ (Wm * (np.ones_like(w3) if mistake == "dropped_weights" else w3)[None, :]).T
+        L = np.linalg.cholesky(-M)
+        Li = np.linalg.inv(L)
+        if mistake == "transposed_inverse":
+            Li = Li.T
+        xi = (Li @ Wm).reshape(Wv.shape)
+        return M, L, xi
+
+    def bad_apply(xi, q, phi):
+        out = orig_apply(xi, q, phi)
+        return -out if mistake == "sign" else out
+
+    monkeypatch.setattr(O, "ace_build", bad_build if mistake != "sign" else orig_build)
+    monkeypatch.setattr(O, "ace_apply", bad_apply)
+    assert _ace_pins_fail()

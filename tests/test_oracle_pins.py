@@ -311,3 +311,60 @@ def test_fcc_and_rutile_geometry():
     assert len(f40) == 40 and np.sqrt((f40 ** 2).sum(1)).max() < 4.9
     r = W.rutile_sites(310)
     assert r.shape == (310, 3) and np.sqrt((r ** 2).sum(1)).max() <= 12.0 + 1e-9
+
+
+# ---------------------------------------------------------------------------------------
+# O7: adaptively compressed exchange, against the properties the paper builds
+# it to have (section "ACE implementation")
+# ---------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def ace_small(sys_small):
+    s, st = sys_small
+    psi = s.psi.numpy()
+    vx, _ = O.apply(psi, st)
+    M, L, xi = O.ace_build(psi, vx, st.q)
+    return s, st, psi, vx, M, L, xi
+
+
+def test_ace_exact_on_the_orbitals(ace_small):
+    """V_ACE psi_j = Vx psi_j for every orbital it was built from (the exchange
+    action from O4, computed independently of O7)."""
+    s, st, psi, vx, M, L, xi = ace_small
+    out = O.ace_apply(xi, st.q, psi)
+    rel = np.abs(out - vx).max() / np.abs(vx).max()
+    assert rel <= 1e-12
+
+
+def test_ace_factor_and_matrix(ace_small):
+    """M is the Galerkin matrix of the exchange operator on the orbitals:
+    symmetric, negative definite, and -L L^T with L lower triangular with a
+    positive diagonal."""
+    s, st, psi, vx, M, L, xi = ace_small
+    w3 = O.weights3d(st.q)
+    ref = np.einsum("iabc,jabc,abc->ij", psi, vx, w3)  # brute-force grid integral
+    assert np.abs(M - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(M - M.T).max() <= 1e-13 * np.abs(M).max()
+    assert np.linalg.eigvalsh(M).max() < 0
+    assert np.allclose(np.triu(L, 1), 0) and (np.diag(L) > 0).all()
+    assert np.abs(-L @ L.T - M).max() <= 1e-13 * np.abs(M).max()
+
+
+def test_ace_operator_symmetric_nsd_and_rank(ace_small):
+    """On random trial functions: <a, V b>_W = <b, V a>_W, <a, V a>_W <= 0,
+    and V annihilates what is W-orthogonal to every xi_k (rank N)."""
+    s, st, psi, vx, M, L, xi = ace_small
+    w3 = O.weights3d(st.q)
+    rng = np.random.default_rng(5)
+    phi = rng.standard_normal((6,) + psi.shape[1:])
+    V = O.ace_apply(xi, st.q, phi)
+    G = np.einsum("iabc,jabc,abc->ij", phi, V, w3)
+    assert np.abs(G - G.T).max() <= 1e-12 * np.abs(G).max()
+    assert np.linalg.eigvalsh(0.5 * (G + G.T)).max() <= 1e-12 * np.abs(G).max()
+    # W-orthogonal complement of span(xi)
+    X = xi.reshape(xi.shape[0], -1)
+    D = w3.reshape(-1)
+    Q, _ = np.linalg.qr((X * np.sqrt(D)[None]).T)
+    f = phi.reshape(phi.shape[0], -1) * np.sqrt(D)[None]
+    f = f - (f @ Q) @ Q.T
+    perp = (f / np.sqrt(D)[None]).reshape(phi.shape)
+    assert np.abs(O.ace_apply(xi, st.q, perp)).max() <= 1e-12 * np.abs(V).max()
