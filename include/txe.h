@@ -247,6 +247,27 @@ txe_status txe_tune_save(txe_context *ctx, const char *path);
  * fails the whole load (TXE_ERR_ARG) and changes nothing. */
 txe_status txe_tune_load(txe_context *ctx, const char *path, int32_t *loaded);
 
+/* Adaptively compressed exchange (section "ACE implementation"), the
+ * consumer of the exchange action.  From N orbitals psi and their actions
+ * W = Vx psi (device, N x n0 x n1 x n2, dtype; e.g. the vxpsi of a symmetric
+ * txe_apply over the same orbitals):
+ *     M_ij = <psi_i, W_j>_W,  M = -L L^T (Cholesky),  xi_k = sum_i W_i (L^-1)_ki
+ * (eq. `eta`).  xi: device, N x n0 x n1 x n2 FP64, overwritten.  M_out,
+ * L_out: optional device N x N FP64 (row-major; L lower triangular with
+ * zeros above).  info: optional device int32, set to 0, or to j + 1 when the
+ * pivot of column j is not positive (M not negative definite); the outputs
+ * are then undefined.  All arithmetic FP64 (MFMA for the grid contractions,
+ * one workgroup for the Cholesky factor and its inverse).  Asynchronous on
+ * the context stream; uses the context workspace.  1 <= N <= 2048. */
+txe_status txe_ace_build(txe_context *ctx, const txe_system *sys, int32_t N, int32_t dtype, const void *psi,
+                         const void *W, double *xi, double *M_out, double *L_out, int32_t *info);
+/* V_ACE applied to Nphi trial functions: out_j = -sum_k xi_k <xi_k, phi_j>_W
+ * (the operator equals Vx on the orbitals it was built from).  xi: device
+ * FP64 from txe_ace_build; phi, out: device Nphi x n0 x n1 x n2 in dtype
+ * (out overwritten, must not overlap an input).  1 <= Nphi <= 65536. */
+txe_status txe_ace_apply(txe_context *ctx, const txe_system *sys, int32_t N, const double *xi, int32_t Nphi,
+                         int32_t dtype, const void *phi, void *out);
+
 /* Measured ceilings of this device (the denominators a roofline can use
  * next to the published peaks): kind 0 = FP64 MFMA 16x16x4, 1 = FP32 MFMA
  * 16x16x4, 2 = bf16 MFMA 16x16x32 (TFLOP/s, 8 independent accumulator

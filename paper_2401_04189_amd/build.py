@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtxe.so")
 
-SOURCES = ["txe_kernels.hip", "txe_ceiling.hip", "txe_api.cpp", "txe_setup.cpp"]
+SOURCES = ["txe_kernels.hip", "txe_ace.hip", "txe_ceiling.hip", "txe_api.cpp", "txe_setup.cpp"]
 ARCH = "gfx950"
 
 

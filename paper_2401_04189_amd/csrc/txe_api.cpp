@@ -1165,3 +1165,82 @@ extern "C" txe_status txe_measure_ceiling(txe_context *ctx, int32_t kind, double
   if (e != hipSuccess) return device_failed(ctx, e);
   return ok();
 }
+
+// ------------------------------------------------------------------------------------
+// adaptively compressed exchange
+// ------------------------------------------------------------------------------------
+static bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+  const char *a0 = (const char *)a, *b0 = (const char *)b;
+  return a && b && a0 < b0 + nb && b0 < a0 + na;
+}
+
+extern "C" txe_status txe_ace_build(txe_context *ctx, const txe_system *sys, int32_t N, int32_t dtype,
+                                    const void *psi, const void *W, double *xi, double *M_out, double *L_out,
+                                    int32_t *info) {
+  if (!ctx || !sys || !psi || !W || !xi) return fail(TXE_ERR_ARG, "null argument");
+  if (sys->device != ctx->device) return fail(TXE_ERR_ARG, "system and context are on different devices");
+  if (N < 1 || N > 2048) return fail(TXE_ERR_SHAPE, "N = %d not in [1, 2048]", N);
+  if (dtype != TXE_DTYPE_F64 && dtype != TXE_DTYPE_F32) return fail(TXE_ERR_ARG, "unknown dtype %d", dtype);
+  if (ctx->sticky) return fail(TXE_ERR_DEVICE, "context has a previous device error: %s", ctx->sticky_msg.c_str());
+  const size_t elt = dtype == TXE_DTYPE_F64 ? 8 : 4;
+  const long long ng = (long long)sys->n[0] * sys->n[1] * sys->n[2];
+  const size_t nin = (size_t)N * ng * elt, nxi = (size_t)N * ng * 8, nmat = (size_t)N * N * 8;
+  if (((uintptr_t)psi % elt) || ((uintptr_t)W % elt) || ((uintptr_t)xi % 8) || ((uintptr_t)M_out % 8) ||
+      ((uintptr_t)L_out % 8) || ((uintptr_t)info % 4))
+    return fail(TXE_ERR_ARG, "misaligned pointer");
+  if (overlaps(xi, nxi, psi, nin) || overlaps(xi, nxi, W, nin) || overlaps(M_out, nmat, psi, nin) ||
+      overlaps(M_out, nmat, W, nin) || overlaps(L_out, nmat, psi, nin) || overlaps(L_out, nmat, W, nin) ||
+      overlaps(M_out, nmat, xi, nxi) || overlaps(L_out, nmat, xi, nxi) || overlaps(M_out, nmat, L_out, nmat))
+    return fail(TXE_ERR_ARG, "outputs overlap inputs or each other");
+  const int nch = gram_nchunks(N, N, ng);
+  size_t off = 0;
+  const size_t o_part = off; off = align256(off + (size_t)nch * N * N * 8);
+  const size_t o_M = off; off = align256(off + nmat);
+  const size_t o_L = off; off = align256(off + nmat);
+  const size_t o_T = off; off = align256(off + nmat);
+  const size_t o_info = off; off = align256(off + 4);
+  txe_status st = ensure_workspace(ctx, off);
+  if (st != TXE_OK) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  char *ws = (char *)ctx->ws;
+  double *M = M_out ? M_out : (double *)(ws + o_M);
+  double *L = L_out ? L_out : (double *)(ws + o_L);
+  int *inf = info ? (int *)info : (int *)(ws + o_info);
+  const bool f64 = dtype == TXE_DTYPE_F64;
+  hipError_t e = ace_gram(f64, f64, psi, N, W, N, sys->D, sys->qdev, (double *)(ws + o_part), M, ctx->stream);
+  if (e == hipSuccess) e = ace_chol_inv(M, N, L, (double *)(ws + o_T), inf, ctx->stream);
+  if (e == hipSuccess) e = ace_comb(f64, true, (const double *)(ws + o_T), N, N, W, ng, 1.0, 1, xi, ctx->stream);
+  if (e != hipSuccess) return device_failed(ctx, e);
+  return ok();
+}
+
+extern "C" txe_status txe_ace_apply(txe_context *ctx, const txe_system *sys, int32_t N, const double *xi,
+                                    int32_t Nphi, int32_t dtype, const void *phi, void *out) {
+  if (!ctx || !sys || !xi || !phi || !out) return fail(TXE_ERR_ARG, "null argument");
+  if (sys->device != ctx->device) return fail(TXE_ERR_ARG, "system and context are on different devices");
+  if (N < 1 || N > 2048) return fail(TXE_ERR_SHAPE, "N = %d not in [1, 2048]", N);
+  if (Nphi < 1 || Nphi > 65536) return fail(TXE_ERR_SHAPE, "Nphi = %d not in [1, 65536]", Nphi);
+  if (dtype != TXE_DTYPE_F64 && dtype != TXE_DTYPE_F32) return fail(TXE_ERR_ARG, "unknown dtype %d", dtype);
+  if (ctx->sticky) return fail(TXE_ERR_DEVICE, "context has a previous device error: %s", ctx->sticky_msg.c_str());
+  const size_t elt = dtype == TXE_DTYPE_F64 ? 8 : 4;
+  const long long ng = (long long)sys->n[0] * sys->n[1] * sys->n[2];
+  if (((uintptr_t)xi % 8) || ((uintptr_t)phi % elt) || ((uintptr_t)out % elt))
+    return fail(TXE_ERR_ARG, "misaligned pointer");
+  const size_t nphi = (size_t)Nphi * ng * elt;
+  if (overlaps(out, nphi, phi, nphi) || overlaps(out, nphi, xi, (size_t)N * ng * 8))
+    return fail(TXE_ERR_ARG, "out overlaps an input");
+  const int nch = gram_nchunks(Nphi, N, ng);
+  size_t off = 0;
+  const size_t o_part = off; off = align256(off + (size_t)nch * Nphi * N * 8);
+  const size_t o_C = off; off = align256(off + (size_t)Nphi * N * 8);
+  txe_status st = ensure_workspace(ctx, off);
+  if (st != TXE_OK) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  char *ws = (char *)ctx->ws;
+  const bool f64 = dtype == TXE_DTYPE_F64;
+  double *Ct = (double *)(ws + o_C);  // Ct[j][k] = <phi_j, xi_k>_W
+  hipError_t e = ace_gram(f64, true, phi, Nphi, xi, N, sys->D, sys->qdev, (double *)(ws + o_part), Ct, ctx->stream);
+  if (e == hipSuccess) e = ace_comb(true, f64, Ct, Nphi, N, xi, ng, -1.0, 0, out, ctx->stream);
+  if (e != hipSuccess) return device_failed(ctx, e);
+  return ok();
+}

@@ -172,6 +172,17 @@ hipError_t run_chunk_bf16(const Tables<float> &tb, const BfTables &bt, int nspli
 hipError_t run_energy(const double *epair, long long npairs, int symmetric, int N, double *ex, double *e_out,
                       hipStream_t s, Prof *prof);
 
+// Adaptively compressed exchange (txe_ace.hip).  ace_gram: G[i][j] =
+// sum_g w(g) X_i(g) Y_j(g) (part: gram_nchunks(NX, NY, ng) * NX * NY
+// doubles of scratch); ace_chol_inv: L = chol(-M), T = L^-1, info;
+// ace_comb: out[m][g] = scale * sum_i A[m][i] X_i(g).
+int gram_nchunks(int NX, int NY, long long ng);
+hipError_t ace_gram(bool x64, bool y64, const void *X, int NX, const void *Y, int NY, const Dims &D,
+                    const double *const qdev[3], double *part, double *G, hipStream_t s);
+hipError_t ace_chol_inv(const double *M, int N, double *L, double *T, int *info, hipStream_t s);
+hipError_t ace_comb(bool x64, bool o64, const double *A, int MR, int K, const void *X, long long ng, double scale,
+                    int lower, void *out, hipStream_t s);
+
 // Ceiling microbenchmarks (txe_ceiling.hip): kind 0 f64, 1 f32, 2 bf16 MFMA
 // in TFLOP/s; 3 HBM stream in GB/s.  Allocates, synchronises the stream.
 hipError_t measure_ceiling(int kind, hipStream_t s, double *value);

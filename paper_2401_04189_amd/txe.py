@@ -86,6 +86,10 @@ SIGNATURES = {
     "txe_tune_save": (_c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "txe_tune_load": (_c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
     "txe_measure_ceiling": (_c_int, [ctypes.c_void_p, _c_int, ctypes.POINTER(ctypes.c_double)]),
+    "txe_ace_build": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_int, _c_int, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "txe_ace_apply": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_int, ctypes.c_void_p, _c_int, _c_int,
+                               ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 KERNELS = ("proj12", "proj3", "core", "epair", "back", "energy")
@@ -405,3 +409,44 @@ def workspace_bytes(ctx, sysm, psi, compute="f64", symmetric=True, i0=0, Ni=None
     nb = ctypes.c_size_t()
     _check(lib().txe_workspace_query(ctx.h, sysm.h, ctypes.byref(a), ctypes.byref(nb)))
     return nb.value
+
+
+def ace_build(ctx: Context, sysm: System, psi, W, want_factors=False):
+    """ACE projection vectors xi (FP64, like psi's shape) from orbitals psi and
+    W = Vx psi.  Returns (xi, info) or (xi, info, M, L) with want_factors;
+    info is a 0-d int32 CUDA tensor (0 = success)."""
+    import torch
+
+    for t, name in ((psi, "psi"), (W, "W")):
+        if not t.is_cuda or not t.is_contiguous() or tuple(t.shape[1:]) != sysm.n:
+            raise ValueError(f"{name} must be a contiguous CUDA tensor N x {sysm.n}")
+    if psi.shape != W.shape or psi.dtype != W.dtype:
+        raise ValueError("psi and W must have the same shape and dtype")
+    N = psi.shape[0]
+    xi = torch.empty(psi.shape, dtype=torch.float64, device=psi.device)
+    info = torch.empty((), dtype=torch.int32, device=psi.device)
+    M = L = None
+    if want_factors:
+        M = torch.empty((N, N), dtype=torch.float64, device=psi.device)
+        L = torch.empty((N, N), dtype=torch.float64, device=psi.device)
+    ctx.set_stream(torch.cuda.current_stream(psi.device))
+    _check(lib().txe_ace_build(ctx.h, sysm.h, N, DTYPE["f64" if psi.dtype == torch.float64 else "f32"],
+                               psi.data_ptr(), W.data_ptr(), xi.data_ptr(), M.data_ptr() if M is not None else None,
+                               L.data_ptr() if L is not None else None, info.data_ptr()))
+    return (xi, info, M, L) if want_factors else (xi, info)
+
+
+def ace_apply(ctx: Context, sysm: System, xi, phi):
+    """V_ACE phi for trial functions phi (CUDA tensor Nphi x grid, f32 or f64)."""
+    import torch
+
+    if not phi.is_cuda or not phi.is_contiguous() or tuple(phi.shape[1:]) != sysm.n:
+        raise ValueError(f"phi must be a contiguous CUDA tensor Nphi x {sysm.n}")
+    if xi.dtype != torch.float64 or not xi.is_contiguous() or tuple(xi.shape[1:]) != sysm.n:
+        raise ValueError("xi must be the FP64 tensor from ace_build")
+    out = torch.empty_like(phi)
+    ctx.set_stream(torch.cuda.current_stream(phi.device))
+    _check(lib().txe_ace_apply(ctx.h, sysm.h, xi.shape[0], xi.data_ptr(), phi.shape[0],
+                               DTYPE["f64" if phi.dtype == torch.float64 else "f32"], phi.data_ptr(),
+                               out.data_ptr()))
+    return out
