@@ -259,6 +259,35 @@ def bench_batched(args, txe, torch, W):
     print(json.dumps(out), flush=True)
 
 
+def bench_ace(txe, torch, ctx, sysm, psi, vx, args):
+    """Adaptively compressed exchange from the FP32 exchange action already
+    in vx: build time (Gram matrix, Cholesky factor and inverse, projection
+    vectors) and the time of one V_ACE apply to N trial functions, with the
+    FP64 flops of the two grid contractions of each."""
+    txe.apply(ctx, sysm, psi, compute="f32", vx_out=vx)
+    xi, info = txe.ace_build(ctx, sysm, psi, vx)
+    out = txe.ace_apply(ctx, sysm, xi, psi)
+    torch.cuda.synchronize()
+    exact = float((out - vx).abs().max() / vx.abs().max())
+    steps = max(args.steps, 3)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(steps):
+        txe.ace_build(ctx, sysm, psi, vx)
+    ev[1].record()
+    for _ in range(steps):
+        txe.ace_apply(ctx, sysm, xi, psi)
+    ev[2].record()
+    torch.cuda.synchronize()
+    b_ms, a_ms = ev[0].elapsed_time(ev[1]) / steps, ev[1].elapsed_time(ev[2]) / steps
+    N, ng = psi.shape[0], psi[0].numel()
+    # build: M (N^2 ng MACs) and xi = L^-1 W (lower triangle: N(N+1)/2 ng); apply: 2 N^2 ng
+    b_fl, a_fl = 2.0 * (N * N + N * (N + 1) / 2) * ng, 2.0 * 2 * N * N * ng
+    return {"info": int(info), "exact_rel": exact, "build_ms": round(b_ms, 4), "apply_ms": round(a_ms, 4),
+            "build_tflops_f64": round(b_fl / (b_ms * 1e-3) / 1e12, 2),
+            "apply_tflops_f64": round(a_fl / (a_ms * 1e-3) / 1e12, 2), "peak_f64": PEAK_TFLOPS["f64"]}
+
+
 def cpu_baseline(s, seconds):
     """The CPU FP64 oracle, as it stands, on the first unique pairs of the same
     workload until `seconds` of work are done."""
@@ -405,6 +434,7 @@ def main():
                               "bf16_mfma_tflops": round(ctx.ceiling("bf16"), 1),
                               "hbm_stream_gbs": round(ctx.ceiling("hbm"), 1)},
     }
+    out["ace"] = bench_ace(txe, torch, ctx, sysm, psi, vx, args)
     if args.retune:
         txe.tune_save(ctx, TUNE_CACHE)
     sysm.close()
