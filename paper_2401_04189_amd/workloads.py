@@ -99,8 +99,12 @@ def exp_sum(K, s_lo=-8.0, s_hi=4.0):
     its coefficients are not printed, so these stand in for them.
     """
     K = int(K)
-    hs = (s_hi - s_lo) / (K - 1)
-    s = s_lo + hs * np.arange(K)
+    if K == 1:  # one node at the middle of the interval, carrying all of it
+        hs = s_hi - s_lo
+        s = np.array([0.5 * (s_lo + s_hi)])
+    else:
+        hs = (s_hi - s_lo) / (K - 1)
+        s = s_lo + hs * np.arange(K)
     w = 2.0 / math.sqrt(math.pi) * hs * np.exp(s)
     alpha = np.exp(2.0 * s)
     return w, alpha
