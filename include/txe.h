@@ -217,7 +217,8 @@ txe_status txe_graph_destroy(txe_graph *graph);
 /* Tuner.  Launch shapes of one problem: knobs[0] gamma' splits of the core
  * kernel as a multiple (1, 2, 4) of the fewest that fit its accumulator
  * registers; knobs[1] gamma tiles per wavefront of the projection kernel
- * (1..3); knobs[2] c tiles per wavefront of the back-projection kernel (1, 2;
+ * (1..3; 4 = all of them, in a form compiled for the rank tile count);
+ * knobs[2] c tiles per wavefront of the back-projection kernel (1, 2;
  * 0 = chosen by size); knobs[3] workgroups of the persistent projection and
  * back-projection kernels; knobs[4] form of the back-projection kernel (1
  * streaming, 2 batched loads; 0 = by precision).  Results do not depend on
@@ -226,7 +227,7 @@ txe_status txe_graph_destroy(txe_graph *graph);
  *
  * txe_tune times txe_apply with these args (each candidate: one warm-up and
  * `reps` timed applies, HIP events on the context stream; the host waits) in
- * coordinate descent from the defaults {1, 2, 0, 2048, 0}, at most two sweeps,
+ * coordinate descent from the defaults {1, 4, 0, 2048, 0}, at most two sweeps,
  * and keeps the fastest in the context under a key made of the device
  * architecture, grid, ranks, K, N, Ni, compute, mode and whether Vx psi is
  * wanted.  Later applies, batches and graphs with the same key use it.  The

@@ -40,7 +40,7 @@ static txe_status ok() {
 // Launch-shape choices of one apply (the tuner's search space).
 struct Knobs {
   int ngs_mul = 1;     // gamma' splits of the core kernel, as a multiple of the fewest that fit the registers
-  int proj_gt = 2;     // gamma tiles per wavefront in proj12 (1, 2, 3)
+  int proj_gt = 4;     // gamma tiles per wavefront in proj12 (1, 2, 3; 4 = all, compile-time form)
   int back_ncg = 0;    // c tiles per wavefront in back (1, 2; 0 = by size)
   int grid_cap = 2048; // workgroups of the persistent proj12 / back kernels
   int back_form = 0;   // back kernel form (1 streaming, 2 batched; 0 = by precision)
@@ -659,7 +659,7 @@ static Knobs knobs_for(const txe_context *ctx, const txe_system *sys, const txe_
 }
 
 static bool knobs_valid(const Knobs &k) {
-  return (k.ngs_mul == 1 || k.ngs_mul == 2 || k.ngs_mul == 4) && k.proj_gt >= 1 && k.proj_gt <= 3 &&
+  return (k.ngs_mul == 1 || k.ngs_mul == 2 || k.ngs_mul == 4) && k.proj_gt >= 1 && k.proj_gt <= 4 &&
          k.back_ncg >= 0 && k.back_ncg <= 2 && k.grid_cap >= 256 && k.grid_cap <= 16384 && k.back_form >= 0 &&
          k.back_form <= 2;
 }
@@ -1033,7 +1033,7 @@ extern "C" txe_status txe_tune(txe_context *ctx, const txe_system *sys, const tx
   Knobs best{};
   double best_t = 0.0;
   txe_status st = time_apply(ctx, sys, args, best, reps, &best_t);
-  const std::vector<int> ngs = {1, 2, 4}, gt = {1, 2, 3}, ncg = {1, 2}, cap = {1024, 2048, 4096}, form = {1, 2};
+  const std::vector<int> ngs = {1, 2, 4}, gt = {1, 2, 3, 4}, ncg = {1, 2}, cap = {1024, 2048, 4096}, form = {1, 2};
   for (int sweep = 0; sweep < 2 && st == TXE_OK; ++sweep) {
     const Knobs start = best;
     for (int knob = 0; knob < 5 && st == TXE_OK; ++knob) {
@@ -1082,7 +1082,7 @@ extern "C" txe_status txe_plan_get(txe_context *ctx, const txe_system *sys, cons
 // Cache file: a JSON object mapping each problem key to its launch shape,
 // one entry per line:
 //   {
-//    "gfx950|n=64,64,64|...": {"ngs_mul": 1, "proj_gt": 2, "back_ncg": 0, "grid_cap": 2048, "back_form": 0},
+//    "gfx950|n=64,64,64|...": {"ngs_mul": 1, "proj_gt": 4, "back_ncg": 0, "grid_cap": 2048, "back_form": 0},
 //    ...
 //   }
 // ("back_form" may be absent: 0.)

@@ -201,6 +201,86 @@ __global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dim
   }
 }
 
+// proj12, compile-time form: all MT gamma tiles per wavefront (MT = rank
+// tiles of every mode), so no per-MFMA guard; the psi loads use clamped
+// addresses and a select instead of a branch.
+template <typename T, typename Tin, int MT, bool LDS_TAB>
+__global__ __launch_bounds__(256) void k_proj12m(const Tin *__restrict__ psi, Dims D, PairMap pm, int P,
+                                                 Tables<T> tb, T *__restrict__ T2) {
+  using M = MF<T>;
+  using acc = typename M::acc;
+  constexpr int RP = 16 * MT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
+  const int nbt = D.nb1 >> 4, nct = D.nc2 >> 4;
+  const T *V2 = tb.V2B, *V1c = tb.V1chain;
+  if constexpr (LDS_TAB) {
+    T *s2 = reinterpret_cast<T *>(smem_raw);
+    T *s1 = s2 + (size_t)D.nc2 * RP;
+    const int m2 = D.nc2 * RP, m1 = MT * nbt * 256;
+    for (int idx = threadIdx.x; idx < m2; idx += 256) s2[idx] = tb.V2B[idx];
+    for (int idx = threadIdx.x; idx < m1; idx += 256) s1[idx] = tb.V1chain[idx];
+    __syncthreads();
+    V2 = s2;
+    V1c = s1;
+  }
+  const size_t plane = (size_t)D.n1 * D.n2;
+  const long long total = (long long)P * D.n0;
+  for (long long item = (long long)blockIdx.x * 4 + wave; item < total; item += (long long)gridDim.x * 4) {
+    const int a = (int)(item % D.n0);
+    const int p = (int)(item / D.n0);
+    int i, j;
+    pair_ij(pm, pm.p0 + p, i, j);
+    const Tin *pi = psi + ((size_t)i * D.n0 + a) * plane;
+    const Tin *pj = psi + ((size_t)j * D.n0 + a) * plane;
+    acc T2a[MT][MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int gt = 0; gt < MT; ++gt) T2a[mt][gt] = zero4<acc>();
+    for (int mb = 0; mb < nbt; ++mb) {
+      acc T1[MT];
+#pragma unroll
+      for (int gt = 0; gt < MT; ++gt) T1[gt] = zero4<acc>();
+      const int b = 16 * mb + lr;
+      const size_t rowoff = (size_t)min(b, D.n1 - 1) * D.n2;
+      for (int J = 0; J < nct; ++J) {
+        const int c = 16 * J + 4 * lg;
+        const bool in = b < D.n1 && c < D.n2;
+        const size_t off = rowoff + min(c, D.n2 - 4);
+        double x[4], y[4];
+        load4(pi + off, x);
+        load4(pj + off, y);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = in ? x[q] * y[q] : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const T *vrow = V2 + (size_t)(c + jj) * RP + lr;
+          const T rho = (T)x[jj];
+#pragma unroll
+          for (int gt = 0; gt < MT; ++gt) T1[gt] = M::mma(rho, vrow[16 * gt], T1[gt]);
+        }
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const T af = V1c[(((size_t)mt * nbt + mb) * 4 + v) * 64 + lane];
+#pragma unroll
+          for (int gt = 0; gt < MT; ++gt) T2a[mt][gt] = M::mma(af, T1[gt][v], T2a[mt][gt]);
+        }
+    }
+    T *out = T2 + ((size_t)p * D.n0 + a) * RP * RP;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int gt = 0; gt < MT; ++gt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[(size_t)(16 * mt + drow<T>(lg, v)) * RP + 16 * gt + lr] = T2a[mt][gt][v];
+  }
+}
+
 // -------------------------------------------------------------------------------------
 // proj3: G[p][alpha][f] = sum_a V0[a][alpha] T2[p][a][f], f = (beta, gamma)
 // one wavefront per (pair, group of FT f-tiles)
@@ -1345,6 +1425,29 @@ hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s
   return ncg == 2 ? launch_back_s_ncg<T, Tin, 2>(tb, a, s) : launch_back_s_ncg<T, Tin, 1>(tb, a, s);
 }
 
+template <typename T, typename Tin, int MT>
+void launch_proj12m_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  const unsigned nb = blocks_for((long long)a.P * a.D.n0);
+  const size_t tab = ((size_t)a.D.nc2 * 16 * MT + (size_t)MT * (a.D.nb1 >> 4) * 256) * sizeof(T);
+  if (tab <= 64 * 1024)
+    hipLaunchKernelGGL((k_proj12m<T, Tin, MT, true>), dim3(std::min(nb, (unsigned)a.grid_cap)), dim3(256), tab, s,
+                       (const Tin *)a.psi, a.D, a.pm, a.P, tb, a.T2);
+  else
+    hipLaunchKernelGGL((k_proj12m<T, Tin, MT, false>), dim3(nb), dim3(256), 0, s, (const Tin *)a.psi, a.D, a.pm,
+                       a.P, tb, a.T2);
+}
+
+template <typename T, typename Tin>
+void launch_proj12m(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  switch (a.D.MT1) {
+    case 1: launch_proj12m_mt<T, Tin, 1>(tb, a, s); break;
+    case 2: launch_proj12m_mt<T, Tin, 2>(tb, a, s); break;
+    case 3: launch_proj12m_mt<T, Tin, 3>(tb, a, s); break;
+    case 4: launch_proj12m_mt<T, Tin, 4>(tb, a, s); break;
+    default: launch_proj12m_mt<T, Tin, 5>(tb, a, s); break;
+  }
+}
+
 template <typename T, typename Tin, int GT>
 void launch_proj12(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
   const int ngg = (a.D.MT2 + GT - 1) / GT;
@@ -1364,7 +1467,8 @@ hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx,
   constexpr int FT = 4;
   hipError_t e;
   prof->begin(K_PROJ12, s);
-  if (a.proj_gt == 1) launch_proj12<T, Tin, 1>(tb, a, s);
+  if (a.proj_gt == 4) launch_proj12m<T, Tin>(tb, a, s);
+  else if (a.proj_gt == 1) launch_proj12<T, Tin, 1>(tb, a, s);
   else if (a.proj_gt == 3) launch_proj12<T, Tin, 3>(tb, a, s);
   else launch_proj12<T, Tin, 2>(tb, a, s);
   prof->end(s);
