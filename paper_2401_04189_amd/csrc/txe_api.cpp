@@ -43,7 +43,7 @@ struct Knobs {
   int proj_gt = 4;     // gamma tiles per wavefront in proj12 (1, 2, 3; 4 = all, compile-time form)
   int back_ncg = 0;    // c tiles per wavefront in back (1, 2; 0 = by size)
   int grid_cap = 2048; // workgroups of the persistent proj12 / back kernels
-  int back_form = 0;   // back kernel form (1 streaming, 2 batched; 0 = by precision)
+  int back_form = 0;   // back kernel form (1 streaming, 2 batched; 0 = default, batched)
 };
 
 struct txe_context {

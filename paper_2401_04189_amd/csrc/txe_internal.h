@@ -82,7 +82,7 @@ struct ChunkArgs {
   int NGS;                    // gamma' splits in the core kernel
   int proj_gt;                // gamma tiles per wavefront in proj12 (1, 2 or 3)
   int back_ncg;               // c tiles per wavefront in back (1 or 2; 0 = by size)
-  int back_form;              // back kernel form (1 streaming, 2 batched; 0 = by precision)
+  int back_form;              // back kernel form (1 streaming, 2 batched; 0 = default, batched)
   int grid_cap;               // workgroups of the persistent kernels
   const void *psi;
   void *vx;

@@ -1055,7 +1055,7 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
                                                 Tin *__restrict__ vx, const double *__restrict__ out_scale,
                                                 int weighted, const double *__restrict__ q0,
                                                 const double *__restrict__ q1, const double *__restrict__ q2,
-                                                int lds_tab) {
+                                                int lds_tab, int mb0) {
   using M = MF<T>;
   using acc = typename M::acc;
   constexpr int RP = 16 * MT;
@@ -1106,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
 #pragma unroll
     for (int mbb = 0; mbb < NBT; ++mbb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) poff[mbb][v] = min(16 * mbb + drow<T>(lg, v), D.n1 - 1) * D.n2;
+      for (int v = 0; v < 4; ++v) poff[mbb][v] = min(16 * (mb0 + mbb) + drow<T>(lg, v), D.n1 - 1) * D.n2;
     int pc[NCG];
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) pc[cg] = min(16 * ct[cg] + lr, D.n2 - 1);
@@ -1161,7 +1161,7 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
       // phi[b][c] = sum_beta' U1[b][beta'] X[beta'][c] (chained), then Acc += psi_j phi
 #pragma unroll
       for (int mbb = 0; mbb < NBT; ++mbb) {
-        if (mbb >= nbt) break;  // uniform
+        if (mb0 + mbb >= nbt) break;  // uniform
         // one b tile at a time: keeps the U1 fragments and psi values of the
         // other tiles out of registers
         __builtin_amdgcn_sched_barrier(0);
@@ -1178,7 +1178,7 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
         for (int mbe = 0; mbe < MT; ++mbe)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const T af = u1[(((size_t)mbb * MT + mbe) * 4 + v) * 64 + lane];
+            const T af = u1[(((size_t)(mb0 + mbb) * MT + mbe) * 4 + v) * 64 + lane];
 #pragma unroll
             for (int cg = 0; cg < NCG; ++cg) ph[cg] = M::mma(af, X[mbe][cg][v], ph[cg]);
           }
@@ -1192,14 +1192,14 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
     Tin *out = vx + (size_t)t * D.n0 * plane + (size_t)a * plane;
 #pragma unroll
     for (int mbb = 0; mbb < NBT; ++mbb) {
-      if (mbb >= nbt) break;
+      if (mb0 + mbb >= nbt) break;
 #pragma unroll
       for (int cg = 0; cg < NCG; ++cg) {
         const int c = 16 * (cgi * NCG + cg) + lr;
         if (cgi * NCG + cg < nct && c < D.n2) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int b = 16 * mbb + drow<T>(lg, v);
+            const int b = 16 * (mb0 + mbb) + drow<T>(lg, v);
             if (b < D.n1) {
               double val = -scale * (double)Acc[mbb][cg][v];
               if (weighted) val *= q0[a] * q1[b] * q2[c];
@@ -1386,15 +1386,24 @@ hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStrea
   const int lds_tab = tab <= 64 * 1024 ? 1 : 0;
   const unsigned nbl = lds_tab ? std::min(nb, (unsigned)a.grid_cap) : nb;
   const size_t lds = lds_tab ? tab : 0;
-#define TXE_BACK(NBTV)                                                                                    \
+  // FP64: all b tiles in one launch.  FP32: at most four b tiles per launch
+  // (registers); more take several launches over disjoint b ranges, each
+  // recomputing X for its sources (measured faster at 80^3)
+  if (nbt > 8) return hipErrorInvalidValue;
+#define TXE_BACK(NBTV, MB0)                                                                                 \
   hipLaunchKernelGGL((k_back_b<T, Tin, MT, NBTV, NCG>), dim3(nbl), dim3(256), lds, s, a.S1, psi, a.D, a.pm, \
                      a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1],      \
-                     a.qdev[2], lds_tab)
-  if (nbt <= 2) TXE_BACK(2);
-  else if (nbt <= 4) TXE_BACK(4);
-  else if (nbt <= 6) TXE_BACK(6);
-  else if (nbt <= 8) TXE_BACK(8);
-  else return hipErrorInvalidValue;
+                     a.qdev[2], lds_tab, MB0)
+  if (nbt <= 2) {
+    TXE_BACK(2, 0);
+  } else if (nbt <= 4) {
+    TXE_BACK(4, 0);
+  } else if constexpr (sizeof(T) == 8) {
+    if (nbt <= 6) TXE_BACK(6, 0);
+    else TXE_BACK(8, 0);
+  } else {
+    for (int mb0 = 0; mb0 < nbt; mb0 += 4) TXE_BACK(4, mb0);
+  }
 #undef TXE_BACK
   return hipGetLastError();
 }
@@ -1415,10 +1424,9 @@ template <typename T, typename Tin>
 hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
   // form: streaming (k_back_s, runtime rank loops, high occupancy) or
   // batched (k_back_b, compile-time rank tiles, loads issued per source in
-  // batches).  Default: batched for FP64, and for FP32 while its b-tile
-  // accumulators are few (up to 64 grid points along mode 1); what measured
-  // fastest on the 64^3 and 80^3 workloads
-  const bool batched = a.back_form ? a.back_form == 2 : (sizeof(T) == 8 || (a.D.nb1 >> 4) <= 4);
+  // batches).  Default: batched, which measured fastest on the 64^3 and
+  // 80^3 workloads in both precisions
+  const bool batched = a.back_form ? a.back_form == 2 : true;
   // two c-tiles per wavefront while the b-tile accumulators are few
   const int ncg = a.back_ncg ? a.back_ncg : ((a.D.nb1 >> 4) <= 4 ? 2 : 1);
   if (batched) return ncg == 2 ? launch_back_b_ncg<T, Tin, 2>(tb, a, s) : launch_back_b_ncg<T, Tin, 1>(tb, a, s);
