@@ -613,7 +613,8 @@ static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, cons
   pl.elt = pl.f64 ? sizeof(double) : sizeof(float);
   pl.npairs = pl.symmetric ? (long long)a->N * (a->N + 1) / 2 : (long long)a->Ni * a->N;
   const int mt = std::max(D.MT0, std::max(D.MT1, D.MT2));
-  const int rows = core_rows(pl.f64, a->compute == TXE_COMPUTE_BF16X3 || a->compute == TXE_COMPUTE_BF16X6, mt);
+  const int nsplit = a->compute == TXE_COMPUTE_BF16X3 ? 2 : a->compute == TXE_COMPUTE_BF16X6 ? 3 : 0;
+  const int rows = core_rows(pl.f64, nsplit, mt);
   // fewest gamma' splits whose rows fit the accumulator registers, times the
   // tuned multiplier; then trimmed so that no split is empty
   int ngs = (D.r2 + rows - 1) / rows * std::max(1, kn.ngs_mul);

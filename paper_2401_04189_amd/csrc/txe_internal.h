@@ -188,6 +188,6 @@ hipError_t ace_comb(bool x64, bool o64, const double *A, int MR, int K, const vo
 hipError_t measure_ceiling(int kind, hipStream_t s, double *value);
 
 // Core-kernel variant choice (register budget per precision).
-int core_rows(bool f64, bool split_bf16, int mt);  // gamma' rows one core workgroup covers
+int core_rows(bool f64, int nsplit, int mt);  // gamma' rows one core workgroup covers (nsplit: bf16 parts, 0 = none)
 
 }  // namespace txe

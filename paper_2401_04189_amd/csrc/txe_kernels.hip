@@ -720,11 +720,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
 }
 
 // -------------------------------------------------------------------------------------
-// core, split-bf16 form: the same loop as k_core<float>, with the two chained
-// contractions of phase A (over beta, then gamma) done on bf16 MFMA (16x16x32)
-// with split operands and FP32 accumulation: every operand x is taken as
-// p0 + p1 (+ p2) in bf16 and each product keeps the terms p_i q_j with
-// i + j < NS.  The accumulation of phase B stays FP32 MFMA.
+// split-bf16 helpers: every operand x of the two chained contractions of
+// phase A is taken as p0 + p1 (+ p2) in bf16 and a product keeps the terms
+// p_i q_j with i + j < NS (bf16 MFMA 16x16x32, FP32 accumulation)
 // -------------------------------------------------------------------------------------
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
@@ -761,15 +759,27 @@ __device__ __forceinline__ bf8 ld_bf8(const unsigned short *p) {
   return r;
 }
 
-template <int MT, int NGW, int NS, bool WRITE_S1>
-__global__ __launch_bounds__(256, 1) void k_core_bf(const float *__restrict__ G, Dims D, int P, int NGS,
-                                                    Tables<float> tb, BfTables bft, float *__restrict__ S1,
-                                                    double *__restrict__ epart) {
+
+// -------------------------------------------------------------------------------------
+// core, split-bf16 form with the slab in LDS: the same loop as k_core<float>
+// (NW wavefronts, one term each per step, Z double-buffered in LDS, phase B
+// in FP32 MFMA), with the two chained contractions of phase A on bf16 MFMA
+// 16x16x32 over split operands.  The slab is split once per slab by the
+// workgroup while it arrives (chunked over the steps) and kept in LDS as
+// bf16 A fragments [part][gamma tile][beta chunk][lane][8]; each step reads
+// its fragments with 16-byte LDS loads.  Chat1 fragments and the phase-B
+// Ahat columns of the next step are prefetched.
+// -------------------------------------------------------------------------------------
+template <int MT, int NGW, int NS, int NW, bool WRITE_S1>
+__global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict__ G, Dims D, int P, int NGS,
+                                                         Tables<float> tb, BfTables bft, float *__restrict__ S1,
+                                                         double *__restrict__ epart) {
   using M = MF<float>;
   using acc = f4;
   constexpr int RP = 16 * MT;
   constexpr size_t F = (size_t)RP * RP;
   constexpr int NC = (RP + 31) / 32;              // K = 32 chunks of the core size
+  constexpr int FRAG = NS * MT * NC * 64 * 8;      // bf16 values of one split slab
   extern __shared__ __align__(16) unsigned char smem_raw[];
 
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
@@ -784,12 +794,16 @@ __global__ __launch_bounds__(256, 1) void k_core_bf(const float *__restrict__ G,
   const int gper = (D.r2 + NGS - 1) / NGS;
   const int g_lo = gs * gper;
   const int g_hi = min(D.r2, g_lo + gper);
-  const int gw = (gper + 3) >> 2;
+  const int gw = (gper + NW - 1) / NW;
   const int wg_lo = g_lo + wave * gw;
   const int wg_hi = min(g_hi, wg_lo + gw);
   const float *Gp = G + (size_t)p * RP * F;
-  float *Zs = reinterpret_cast<float *>(smem_raw);
-  const int zsz = 4 * gper * 16;
+  unsigned short *Gs = reinterpret_cast<unsigned short *>(smem_raw);   // [2][FRAG]
+  float *Zs = reinterpret_cast<float *>(smem_raw + 2 * FRAG * sizeof(unsigned short));
+  const int zsz = NW * gper * 16;
+  constexpr int NTG = NW / 4;
+  const int nkq = (D.K + NW - 1) / NW;
+  const int nsteps = D.r0 * nkq;
 
   acc Phi[MT][NGW];
 #pragma unroll
@@ -797,60 +811,97 @@ __global__ __launch_bounds__(256, 1) void k_core_bf(const float *__restrict__ G,
 #pragma unroll
     for (int ng = 0; ng < NGW; ++ng) Phi[mt][ng] = zero4<acc>();
 
-  constexpr bool HOLD_G = MT <= 3;
-  bf8 gsp[HOLD_G ? MT : 1][HOLD_G ? NC : 1][NS];
-  const float *Ga = Gp + lr;
-  // A fragment (m = gamma = 16 mg + lr, k = beta = 32 c + 8 lg + i) of the slab, split
-  auto load_g = [&](int mg, int c, bf8 (&o)[NS]) {
-    float x[8];
+  // slab chunks: EPT elements per thread, about four chunks per slab
+  constexpr int CHT = 64 * NW;
+  constexpr int EPT = (int)((F + 4 * CHT - 1) / (4 * CHT));
+  constexpr int CH = EPT * CHT;
+  constexpr int NCH = (int)((F + CH - 1) / CH);
+  const int tid = threadIdx.x;
+  auto slab_load = [&](int c, int a_, float (&v)[EPT]) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int beta = 32 * c + 8 * lg + i;
-      x[i] = (beta < RP) ? Ga[beta * RP + 16 * mg] : 0.f;
+    for (int j = 0; j < EPT; ++j) v[j] = Gp[(size_t)a_ * F + min(c * CH + j * CHT + tid, (int)F - 1)];
+  };
+  // element (beta, gamma) -> split parts at A fragment (gamma tile, beta chunk, lane, i)
+  auto slab_store = [&](int c, int buf, const float (&v)[EPT]) {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = c * CH + j * CHT + tid;
+      if (e < (int)F) {
+        const int beta = e / RP, gamma = e % RP;
+        const int ln = ((beta >> 3) & 3) * 16 + (gamma & 15);
+        const int base = ((((gamma >> 4) * NC + (beta >> 5)) * 64 + ln) * 8) + (beta & 7);
+        float r = v[j];
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) {
+          const __bf16 h = (__bf16)r;
+          Gs[buf * FRAG + sp * (MT * NC * 512) + base] = __builtin_bit_cast(unsigned short, h);
+          if (sp + 1 < NS) r -= (float)h;
+        }
+      }
     }
-    split8<NS>(x, o);
+  };
+  // zero both buffers (beta rows past RP inside the last chunk stay zero),
+  // then slab 0
+  for (int idx = tid; idx < FRAG; idx += CHT) {
+    Gs[idx] = 0;
+    Gs[FRAG + idx] = 0;
+  }
+  __syncthreads();
+  for (int c = 0; c < NCH; ++c) {
+    float v[EPT];
+    slab_load(c, 0, v);
+    slab_store(c, 0, v);
+  }
+  __syncthreads();
+
+  struct CF {
+    bf8 cb[NC][NS];
+    float af[NTG][MT];
+  };
+  auto load_terms = [&](int alpha_, int kq_, CF &f) {
+#pragma unroll
+    for (int tg = 0; tg < NTG; ++tg) {
+      const float *ah = tb.Ahat + ((size_t)alpha_ * D.Kp + NW * kq_ + 4 * tg + lg) * RP + lr;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) f.af[tg][mt] = ah[16 * mt];
+    }
+    const int k_ = NW * kq_ + wave;
+    if (k_ >= D.K) return;
+    const unsigned short *c1 = bft.C1 + (((size_t)k_ * MT + bt) * 3) * NC * 512 + lane * 8;
+#pragma unroll
+    for (int sp = 0; sp < NS; ++sp)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) f.cb[c][sp] = ld_bf8(c1 + ((size_t)sp * NC + c) * 512);
   };
 
-  const int nkq = (D.K + 3) >> 2;
-  const int nsteps = D.r0 * nkq;
-  for (int step = 0; step < nsteps; ++step) {
+  CF ca, cb2;
+  load_terms(0, 0, ca);
+  auto step_body = [&](const int step, CF &cur, CF &nxt) __attribute__((always_inline)) {
     const int alpha = step / nkq;
     const int kq = step - alpha * nkq;
-    const int k = 4 * kq + wave;
-    if (kq == 0) {
-      Ga = Gp + (size_t)alpha * F + lr;
-      if constexpr (HOLD_G) {
-#pragma unroll
-        for (int mg = 0; mg < MT; ++mg)
-#pragma unroll
-          for (int c = 0; c < NC; ++c) load_g(mg, c, gsp[mg][c]);
-      }
+    const int k = NW * kq + wave;
+    float gnext[EPT];
+    slab_load(min(kq, NCH - 1), min(alpha + 1, D.r0 - 1), gnext);
+    {
+      const bool wrap = kq + 1 == nkq;
+      if (step + 1 < nsteps) load_terms(wrap ? alpha + 1 : alpha, wrap ? 0 : kq + 1, nxt);
     }
     float *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * gper * 16;
     if (k < D.K) {
       // ---- W[gamma][beta'] = sum_beta G[alpha][beta][gamma] Chat1_k[beta'][beta]
-      bf8 cb[NC][NS];
-      const unsigned short *c1 = bft.C1 + (((size_t)k * MT + bt) * 3) * NC * 512 + lane * 8;
-#pragma unroll
-      for (int sp = 0; sp < NS; ++sp)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) cb[c][sp] = ld_bf8(c1 + ((size_t)sp * NC + c) * 512);
+      const unsigned short *gl = Gs + (alpha & 1) * FRAG + lane * 8;
       acc W[MT];
 #pragma unroll
       for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int mg = 0; mg < MT; ++mg) {
-          if constexpr (HOLD_G) {
-            W[mg] = mma_split<NS>(gsp[mg][c], cb[c], W[mg]);
-          } else {
-            bf8 g[NS];
-            load_g(mg, c, g);
-            W[mg] = mma_split<NS>(g, cb[c], W[mg]);
-          }
+          bf8 g[NS];
+#pragma unroll
+          for (int sp = 0; sp < NS; ++sp) g[sp] = ld_bf8(gl + ((sp * MT + mg) * NC + c) * 512);
+          W[mg] = mma_split<NS>(g, cur.cb[c], W[mg]);
         }
-      }
       // ---- Z[gamma'][beta'] = sum_gamma Chat2_k[gamma'][gamma] W[gamma][beta'], two W tiles per K = 32
       bf8 wsp[NC][NS];
 #pragma unroll
@@ -866,6 +917,7 @@ __global__ __launch_bounds__(256, 1) void k_core_bf(const float *__restrict__ G,
       const unsigned short *c2 = bft.C2 + (size_t)k * 3 * MT * NC * 512 + lane * 8;
 #pragma unroll
       for (int mtp = 0; mtp < MT; ++mtp) {
+        if (16 * mtp >= g_hi || 16 * mtp + 16 <= g_lo) continue;  // uniform: tile outside the split
         acc Z = zero4<acc>();
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -883,27 +935,41 @@ __global__ __launch_bounds__(256, 1) void k_core_bf(const float *__restrict__ G,
     } else {
       for (int idx = lane; idx < gper * 16; idx += 64) Zw[idx] = 0.f;
     }
+    // the next slab's chunk (split) before the barrier
+    if (alpha + 1 < D.r0) {
+      if (kq < NCH) slab_store(kq, (alpha + 1) & 1, gnext);
+      if (kq + 1 == nkq)
+        for (int c = nkq; c < NCH; ++c) {
+          float v[EPT];
+          slab_load(c, alpha + 1, v);
+          slab_store(c, (alpha + 1) & 1, v);
+        }
+    }
     __syncthreads();
     // ---- phase B (FP32 MFMA): Phi += sum_{k in step} w_k Chat0_k[alpha'][alpha] Z_k
-    {
-      const int kk = 4 * kq + lg;
-      float af[MT];
-      const float *ah = tb.Ahat + ((size_t)alpha * D.Kp + kk) * RP + lr;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) af[mt] = ah[16 * mt];
-      const float *zrow = Zs + (size_t)(step & 1) * zsz + (size_t)lg * gper * 16 + lr;
+    for (int tg = 0; tg < NTG; ++tg) {
+      const float *zrow = Zs + (size_t)(step & 1) * zsz + (size_t)(4 * tg + lg) * gper * 16 + lr;
 #pragma unroll
       for (int ng = 0; ng < NGW; ++ng) {
+        if (NW == 8 && ng >= gw) break;
         const int row = min(wg_lo - g_lo + ng, gper - 1);
         const float bz = zrow[row * 16];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(af[mt], bz, Phi[mt][ng]);
+        for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(cur.af[tg][mt], bz, Phi[mt][ng]);
       }
     }
+  };
+  int step = 0;
+  for (; step + 1 < nsteps; step += 2) {
+    step_body(step, ca, cb2);
+    step_body(step + 1, cb2, ca);
   }
-  core_epilogue<float, MT, NGW, 4, WRITE_S1>(Phi, Gp, D, p, bt, gs, NGS, wg_lo, wg_hi, lane, lr, lg, wave, tb, S1,
-                                           epart);
+  for (; step < nsteps; ++step) step_body(step, ca, cb2);
+  core_epilogue<float, MT, NGW, NW, WRITE_S1>(Phi, Gp, D, p, bt, gs, NGS, wg_lo, wg_hi, lane, lr, lg, wave, tb, S1,
+                                              epart);
 }
+
 
 // -------------------------------------------------------------------------------------
 // back: for target t, slab a and a group of NCG c-tiles, over all sources s:
@@ -1315,18 +1381,27 @@ hipError_t launch_core(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx,
   return hipErrorInvalidValue;
 }
 
-template <int MT, int NGW, int NS>
-hipError_t launch_core_bf_mt(const Tables<float> &tb, const BfTables &bft, const ChunkArgs<float> &a, bool want_vx,
-                             hipStream_t s) {
+template <int MT, int NGW, int NS, int NW>
+hipError_t launch_core_bf2_mt(const Tables<float> &tb, const BfTables &bft, const ChunkArgs<float> &a, bool want_vx,
+                              hipStream_t s) {
   const int gper = (a.D.r2 + a.NGS - 1) / a.NGS;
-  const size_t lds = (2 * 4 * (size_t)gper * 16) * sizeof(float);
+  if ((gper + NW - 1) / NW > NGW) return hipErrorInvalidValue;
+  constexpr int RP = 16 * MT, NC = (RP + 31) / 32;
+  constexpr size_t frag = (size_t)NS * MT * NC * 512;
+  const size_t lds = 2 * frag * sizeof(unsigned short) + (2 * NW * (size_t)gper * 16) * sizeof(float);
   const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
+  if (lds > 64 * 1024) {
+    const void *fn = want_vx ? (const void *)k_core_bf2<MT, NGW, NS, NW, true>
+                             : (const void *)k_core_bf2<MT, NGW, NS, NW, false>;
+    const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (ea != hipSuccess) return ea;
+  }
   if (want_vx)
-    hipLaunchKernelGGL((k_core_bf<MT, NGW, NS, true>), dim3(nb), dim3(256), lds, s, (const float *)a.G, a.D, a.P,
-                       a.NGS, tb, bft, a.S1, a.epart);
+    hipLaunchKernelGGL((k_core_bf2<MT, NGW, NS, NW, true>), dim3(nb), dim3(64 * NW), lds, s, (const float *)a.G, a.D,
+                       a.P, a.NGS, tb, bft, a.S1, a.epart);
   else
-    hipLaunchKernelGGL((k_core_bf<MT, NGW, NS, false>), dim3(nb), dim3(256), lds, s, (const float *)a.G, a.D, a.P,
-                       a.NGS, tb, bft, a.S1, a.epart);
+    hipLaunchKernelGGL((k_core_bf2<MT, NGW, NS, NW, false>), dim3(nb), dim3(64 * NW), lds, s, (const float *)a.G,
+                       a.D, a.P, a.NGS, tb, bft, a.S1, a.epart);
   return hipGetLastError();
 }
 
@@ -1334,11 +1409,18 @@ template <int NS>
 hipError_t launch_core_bf(const Tables<float> &tb, const BfTables &bft, const ChunkArgs<float> &a, bool want_vx,
                           hipStream_t s) {
   switch (a.D.MT0) {
-    case 1: return launch_core_bf_mt<1, NGW32[1], NS>(tb, bft, a, want_vx, s);
-    case 2: return launch_core_bf_mt<2, NGW32[2], NS>(tb, bft, a, want_vx, s);
-    case 3: return launch_core_bf_mt<3, NGW32[3], NS>(tb, bft, a, want_vx, s);
-    case 4: return launch_core_bf_mt<4, NGW32[4], NS>(tb, bft, a, want_vx, s);
-    case 5: return launch_core_bf_mt<5, NGW32[5], NS>(tb, bft, a, want_vx, s);
+    // two-part splits at small ranks: eight wavefronts; otherwise four
+    case 1:
+      if constexpr (NS == 2) return launch_core_bf2_mt<1, NGW32x8[1], NS, 8>(tb, bft, a, want_vx, s);
+      else return launch_core_bf2_mt<1, NGW32[1], NS, 4>(tb, bft, a, want_vx, s);
+    case 2:
+      if constexpr (NS == 2) return launch_core_bf2_mt<2, NGW32x8[2], NS, 8>(tb, bft, a, want_vx, s);
+      else return launch_core_bf2_mt<2, NGW32[2], NS, 4>(tb, bft, a, want_vx, s);
+    case 3:
+      if constexpr (NS == 2) return launch_core_bf2_mt<3, NGW32x8[3], NS, 8>(tb, bft, a, want_vx, s);
+      else return launch_core_bf2_mt<3, NGW32[3], NS, 4>(tb, bft, a, want_vx, s);
+    case 4: return launch_core_bf2_mt<4, NGW32[4], NS, 4>(tb, bft, a, want_vx, s);
+    case 5: return launch_core_bf2_mt<5, NGW32[5], NS, 4>(tb, bft, a, want_vx, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1518,10 +1600,10 @@ hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx,
 
 }  // namespace
 
-int core_rows(bool f64, bool split_bf16, int mt) {
+int core_rows(bool f64, int nsplit, int mt) {
   if (f64) return 4 * NGW64[mt];
-  if (split_bf16 || NW32[mt] == 4) return 4 * NGW32[mt];
-  return 8 * NGW32x8[mt];
+  if (nsplit == 3 || NW32[mt] == 4) return 4 * NGW32[mt];
+  return 8 * NGW32x8[mt];  // FP32 and two-part bf16 at up to three tiles
 }
 
 hipError_t run_chunk_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s,
