@@ -469,9 +469,13 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   constexpr bool C2S = F32 ? MT <= 3 : MT <= 2;
   constexpr bool HOLD_G = C2S && (NW == 4 || MT <= 2);
   constexpr bool LDS_G = F32 && !HOLD_G;
-  constexpr int SROW = RP % 32 == 0 ? RP + 16 : RP;
+  // LDS slab row beta: for each of the 16 lanes of a fragment its MT gamma
+  // values (gamma = 16 mg + lane) side by side, padded to LPL, so a lane
+  // reads all of its A fragments of one beta row with 16-byte loads
+  constexpr int LPL = MT <= 4 ? 4 : 8;
+  constexpr int SROW = 16 * LPL;
   constexpr int SLAB = LDS_G ? RP * SROW : 0;
-  T *Gs = reinterpret_cast<T *>(smem_raw);        // [2][RP][SROW] (LDS_G)
+  T *Gs = reinterpret_cast<T *>(smem_raw);        // [2][RP][16][LPL] (LDS_G)
   T *Zs = Gs + 2 * SLAB;                          // [2][NW][gper][16]
   const int zsz = NW * gper * 16;
 
@@ -541,7 +545,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
       const int e = c * CH + j * CHT + tid;
-      if (e < (int)F) Gs[buf * SLAB + (e / RP) * SROW + (e % RP)] = v[j];
+      if (e < (int)F) {
+        const int gamma = e % RP;
+        Gs[buf * SLAB + (e / RP) * SROW + (gamma & 15) * LPL + (gamma >> 4)] = v[j];
+      }
     }
   };
   if constexpr (LDS_G) {
@@ -600,11 +607,24 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
       for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
 #pragma unroll
       for (int kt = 0; kt < 4 * MT; ++kt) {
+        T gl[LDS_G ? LPL : 1];
+        if constexpr (LDS_G) {
+          const float4 *src =
+              reinterpret_cast<const float4 *>(Gs + (alpha & 1) * SLAB + (4 * kt + lg) * SROW + lr * LPL);
+#pragma unroll
+          for (int q = 0; q < LPL / 4; ++q) {
+            const float4 f = src[q];
+            gl[4 * q] = f.x;
+            gl[4 * q + 1] = f.y;
+            gl[4 * q + 2] = f.z;
+            gl[4 * q + 3] = f.w;
+          }
+        }
 #pragma unroll
         for (int mg = 0; mg < MT; ++mg) {
           T g;
           if constexpr (HOLD_G) g = gf[kt][mg];
-          else if constexpr (LDS_G) g = Gs[(alpha & 1) * SLAB + (4 * kt + lg) * SROW + 16 * mg + lr];
+          else if constexpr (LDS_G) g = gl[mg];
           else g = Ga[(4 * kt + lg) * RP + 16 * mg];
           W[mg] = M::mma(g, cur.cb[kt], W[mg]);
         }
@@ -1335,7 +1355,7 @@ hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_
   if ((gper + NW - 1) / NW > NGW) return hipErrorInvalidValue;  // the plan gives every wavefront <= NGW rows
   constexpr int RP = 16 * MT;
   constexpr bool lds_g = sizeof(T) == 4 && MT >= 3;  // the slab-in-LDS forms of k_core
-  constexpr size_t slab = lds_g ? (size_t)RP * (RP % 32 == 0 ? RP + 16 : RP) : 0;
+  constexpr size_t slab = lds_g ? (size_t)RP * 16 * (MT <= 4 ? 4 : 8) : 0;
   const size_t lds = (2 * slab + 2 * NW * (size_t)gper * 16) * sizeof(T);
   const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
   if (lds > 64 * 1024) {  // opt in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
