@@ -300,14 +300,17 @@ static void build_tables(const txe_system &S, HostTables &H, bool f64) {
   for (int k = 0; k < D.K; ++k)
     for (int be = 0; be < D.r1; ++be)
       for (int bp = 0; bp < D.r1; ++bp) H.C1B[((size_t)k * D.rp1 + be) * D.rp1 + bp] = Ch(1, k, bp, be);
-  // C2chain[k][mt'][mg][v][lane] = Chat2_k[gamma' = 16mt'+lr][gamma = 16mg+4lg+v]
+  // C2chain[k][mt'][mg][v][lane] = Chat2_k[gamma' = 16mt'+lr][gamma = 16mg+4v+lg]
+  // for both precisions: chunk v of tile mg holds gamma rows 16mg+4v..+3, so
+  // chunks past the rank are all zero and the core skips them (the FP32 core
+  // orders the slab's gamma rows inside a tile to match)
   H.C2chain.assign((size_t)D.Kp * D.MT2 * D.MT2 * 256, 0.0);
   for (int k = 0; k < D.K; ++k)
     for (int mtp = 0; mtp < D.MT2; ++mtp)
       for (int mg = 0; mg < D.MT2; ++mg)
         for (int v = 0; v < 4; ++v)
           for (int l = 0; l < 64; ++l) {
-            const int gp = 16 * mtp + (l & 15), g = 16 * mg + drow(l >> 4, v);
+            const int gp = 16 * mtp + (l & 15), g = 16 * mg + 4 * v + (l >> 4);
             if (gp < D.r2 && g < D.r2)
               H.C2chain[((((size_t)k * D.MT2 + mtp) * D.MT2 + mg) * 4 + v) * 64 + l] = Ch(2, k, gp, g);
           }

@@ -428,8 +428,17 @@ __device__ __forceinline__ void core_epilogue(typename MF<T>::acc (&Phi)[MT][NGW
 // term matrices are shared by every workgroup and come from L2; Z is
 // double-buffered in LDS so each step needs one barrier; Phi stays in
 // registers for the whole pair.
+// Padding: in the last 16-row tile of beta and gamma only the first TL
+// four-row chunks are live (TL = 4: all of them); the beta contraction of W
+// runs over 4 (MT - 1) + TL K = 4 steps and the gamma contraction of Z skips
+// the dead chunks.  A chunk is one accumulator entry v of W across the four
+// lane groups;
+// FP64 accumulators hold rows 4v + lg, i.e. contiguous chunks already, while
+// the FP32 core permutes the slab's gamma rows inside each 16-row tile (row m
+// of the A operand is gamma 4(m mod 4) + m / 4) so that its entry v holds
+// gamma 4v + lg too.
 // -------------------------------------------------------------------------------------
-template <typename T, int MT, int NGW, int NW, bool WRITE_S1>
+template <typename T, int MT, int NGW, int NW, bool WRITE_S1, int TL>
 __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Dims D, int P, int NGS, Tables<T> tb,
                                                  T *__restrict__ S1, double *__restrict__ epart) {
   using M = MF<T>;
@@ -469,6 +478,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   constexpr bool C2S = F32 ? MT <= 3 : MT <= 2;
   constexpr bool HOLD_G = C2S && (NW == 4 || MT <= 2);
   constexpr bool LDS_G = F32 && !HOLD_G;
+  // slab gamma row (inside its tile) that this lane feeds to the W chain
+  const int lrg = F32 ? ((lr & 3) << 2 | (lr >> 2)) : lr;
+  constexpr int NKT = 4 * (MT - 1) + TL;  // K = 4 steps of the beta contraction
   // LDS slab row beta: for each of the 16 lanes of a fragment its MT gamma
   // values (gamma = 16 mg + lane) side by side, padded to LPL, so a lane
   // reads all of its A fragments of one beta row with 16-byte loads
@@ -517,7 +529,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   };
   // A fragments of slab alpha: G[alpha][beta = 4kt+lg][gamma = 16mg+lr]
   auto load_slab = [&](int alpha_, T (&g)[GK][GM]) {
-    const T *Ga_ = Gp + (size_t)alpha_ * F + lr;
+    const T *Ga_ = Gp + (size_t)alpha_ * F + lrg;
 #pragma unroll
     for (int kt = 0; kt < GK; ++kt)
 #pragma unroll
@@ -527,7 +539,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   CF ca, cb2;
   T gf[GK][GM];  // held slab fragments
   if constexpr (PF) load_terms(0, 0, ca);
-  const T *Ga = Gp + lr;
+  const T *Ga = Gp + lrg;
   // LDS slab: the next slab arrives in (about) four chunks of EPT elements
   // per thread, chunk kq during step kq (loaded at the start of the step,
   // stored before the step's barrier); the loads are unconditional (clamped
@@ -547,7 +559,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
       const int e = c * CH + j * CHT + tid;
       if (e < (int)F) {
         const int gamma = e % RP;
-        Gs[buf * SLAB + (e / RP) * SROW + (gamma & 15) * LPL + (gamma >> 4)] = v[j];
+        const int gl16 = gamma & 15, ln = (gl16 & 3) << 2 | (gl16 >> 2);  // lane that reads it
+        Gs[buf * SLAB + (e / RP) * SROW + ln * LPL + (gamma >> 4)] = v[j];
       }
     }
   };
@@ -565,7 +578,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
     const int kq = step - alpha * nkq;
     const int k = NW * kq + wave;
     if (kq == 0) {
-      Ga = Gp + (size_t)alpha * F + lr;
+      Ga = Gp + (size_t)alpha * F + lrg;
       if constexpr (HOLD_G) {
         load_slab(alpha, gf);
         // settle the slab (and this step's prefetched terms) here, once per
@@ -607,6 +620,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
       for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
 #pragma unroll
       for (int kt = 0; kt < 4 * MT; ++kt) {
+        if (kt >= NKT) break;
         T gl[LDS_G ? LPL : 1];
         if constexpr (LDS_G) {
           const float4 *src =
@@ -648,9 +662,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
 #pragma unroll
         for (int mg = 0; mg < MT; ++mg)
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
+          for (int v = 0; v < 4; ++v) {
+            if (mg == MT - 1 && v >= TL) break;
 #pragma unroll
             for (int mtp = 0; mtp < MT; ++mtp) Z[mtp] = M::mma(c2s[mtp][mg][v], W[mg][v], Z[mtp]);
+          }
 #pragma unroll
         for (int mtp = 0; mtp < MT; ++mtp) store_z(mtp, Z[mtp]);
       } else {
@@ -678,7 +694,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
 #pragma unroll
           for (int mg = 0; mg < MT; ++mg)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Z = M::mma(c2[mg][v], W[mg][v], Z);
+            for (int v = 0; v < 4; ++v) {
+              if (mg == MT - 1 && v >= TL) break;
+              Z = M::mma(c2[mg][v], W[mg][v], Z);
+            }
           store_z(mtp, Z);
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -1349,7 +1368,7 @@ namespace {
 
 inline unsigned blocks_for(long long waves) { return (unsigned)((waves + 3) / 4); }
 
-template <typename T, int MT, int NGW, int NW>
+template <typename T, int MT, int NGW, int NW, int TL>
 hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
   const int gper = (a.D.r2 + a.NGS - 1) / a.NGS;
   if ((gper + NW - 1) / NW > NGW) return hipErrorInvalidValue;  // the plan gives every wavefront <= NGW rows
@@ -1360,15 +1379,15 @@ hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_
   const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
   if (lds > 64 * 1024) {  // opt in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
     const void *fn =
-        want_vx ? (const void *)k_core<T, MT, NGW, NW, true> : (const void *)k_core<T, MT, NGW, NW, false>;
+        want_vx ? (const void *)k_core<T, MT, NGW, NW, true, TL> : (const void *)k_core<T, MT, NGW, NW, false, TL>;
     const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
   }
   if (want_vx)
-    hipLaunchKernelGGL((k_core<T, MT, NGW, NW, true>), dim3(nb), dim3(64 * NW), lds, s, a.G, a.D, a.P, a.NGS, tb,
+    hipLaunchKernelGGL((k_core<T, MT, NGW, NW, true, TL>), dim3(nb), dim3(64 * NW), lds, s, a.G, a.D, a.P, a.NGS, tb,
                        a.S1, a.epart);
   else
-    hipLaunchKernelGGL((k_core<T, MT, NGW, NW, false>), dim3(nb), dim3(64 * NW), lds, s, a.G, a.D, a.P, a.NGS, tb,
+    hipLaunchKernelGGL((k_core<T, MT, NGW, NW, false, TL>), dim3(nb), dim3(64 * NW), lds, s, a.G, a.D, a.P, a.NGS, tb,
                        a.S1, a.epart);
   return hipGetLastError();
 }
@@ -1381,22 +1400,37 @@ constexpr int NGW32[MAX_MT + 1] = {0, 4, 8, 10, 12, 10};
 constexpr int NW32[MAX_MT + 1] = {0, 8, 8, 8, 4, 4};
 constexpr int NGW32x8[MAX_MT + 1] = {0, 2, 4, 6, 0, 0};
 
+// FP32: one core per count of live chunks in the last tile of modes 1 and 2
+template <int MT, int NGW, int NW>
+hipError_t launch_core_f32_tl(const Tables<float> &tb, const ChunkArgs<float> &a, bool want_vx, hipStream_t s) {
+  const int rt = max(a.D.r1, a.D.r2) - 16 * (MT - 1);
+  switch (min(4, max(1, (rt + 3) / 4))) {
+    case 1: return launch_core_mt<float, MT, NGW, NW, 1>(tb, a, want_vx, s);
+    case 2: return launch_core_mt<float, MT, NGW, NW, 2>(tb, a, want_vx, s);
+    case 3: return launch_core_mt<float, MT, NGW, NW, 3>(tb, a, want_vx, s);
+    default: return launch_core_mt<float, MT, NGW, NW, 4>(tb, a, want_vx, s);
+  }
+}
+
 template <typename T>
 hipError_t launch_core(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
   const int mt = max(a.D.MT0, max(a.D.MT1, a.D.MT2));
-  constexpr bool f64 = sizeof(T) == 8;
-  switch (mt) {
-    case 1:
-      if constexpr (f64) return launch_core_mt<T, 1, NGW64[1], 4>(tb, a, want_vx, s);
-      else return launch_core_mt<T, 1, NGW32x8[1], 8>(tb, a, want_vx, s);
-    case 2:
-      if constexpr (f64) return launch_core_mt<T, 2, NGW64[2], 4>(tb, a, want_vx, s);
-      else return launch_core_mt<T, 2, NGW32x8[2], 8>(tb, a, want_vx, s);
-    case 3:
-      if constexpr (f64) return launch_core_mt<T, 3, NGW64[3], 4>(tb, a, want_vx, s);
-      else return launch_core_mt<T, 3, NGW32x8[3], 8>(tb, a, want_vx, s);
-    case 4: return launch_core_mt<T, 4, (f64 ? NGW64[4] : NGW32[4]), 4>(tb, a, want_vx, s);
-    case 5: return launch_core_mt<T, 5, (f64 ? NGW64[5] : NGW32[5]), 4>(tb, a, want_vx, s);
+  if constexpr (sizeof(T) == 8) {
+    switch (mt) {
+      case 1: return launch_core_mt<T, 1, NGW64[1], 4, 4>(tb, a, want_vx, s);
+      case 2: return launch_core_mt<T, 2, NGW64[2], 4, 4>(tb, a, want_vx, s);
+      case 3: return launch_core_mt<T, 3, NGW64[3], 4, 4>(tb, a, want_vx, s);
+      case 4: return launch_core_mt<T, 4, NGW64[4], 4, 4>(tb, a, want_vx, s);
+      case 5: return launch_core_mt<T, 5, NGW64[5], 4, 4>(tb, a, want_vx, s);
+    }
+  } else {
+    switch (mt) {
+      case 1: return launch_core_f32_tl<1, NGW32x8[1], 8>(tb, a, want_vx, s);
+      case 2: return launch_core_f32_tl<2, NGW32x8[2], 8>(tb, a, want_vx, s);
+      case 3: return launch_core_f32_tl<3, NGW32x8[3], 8>(tb, a, want_vx, s);
+      case 4: return launch_core_f32_tl<4, NGW32[4], 4>(tb, a, want_vx, s);
+      case 5: return launch_core_f32_tl<5, NGW32[5], 4>(tb, a, want_vx, s);
+    }
   }
   return hipErrorInvalidValue;
 }

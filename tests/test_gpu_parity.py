@@ -129,6 +129,28 @@ def test_f32_rank_tiles_against_f64(ctx):
         assert abs(e32 - e64) <= 1e-5 and perr <= 1e-5 and verr <= 1e-5
 
 
+# per-mode ranks: the tile count follows the largest rank, the live chunks
+# of the last tile follow modes 1 and 2 (one, three and four of four live)
+ANISO = ((40, 20, 20), (20, 36, 44), (44, 44, 18), (18, 30, 48))
+
+
+def test_f64_anisotropic_ranks(ctx):
+    for r in ANISO:
+        s = W.small_system(n=48, L=6.0, N=2, r=r, K=10, seed=41)
+        check_f64(ctx, s, label=f"r={r}")
+
+
+def test_f32_anisotropic_ranks_against_f64(ctx):
+    for r in ANISO:
+        s = W.small_system(n=48, L=6.0, N=2, r=r, K=10, seed=41)
+        v64, e64, p64 = run_gpu(ctx, s, "f64")
+        v32, e32, p32 = run_gpu(ctx, s, "f32")
+        verr = rel_vx_err(v32, v64, s.grid.q)
+        perr = np.abs(p32 - p64).max() / np.abs(p64).max()
+        print(f"[f32 r={r}] |dE_x| {abs(e32 - e64):.3e} Ha  e_ij rel {perr:.3e}  Vx rel {verr:.3e}", flush=True)
+        assert abs(e32 - e64) <= 1e-5 and perr <= 1e-5 and verr <= 1e-5
+
+
 @pytest.mark.parametrize("form,tol", [("bf16x6", 1e-5), ("bf16x3", 2e-4)])
 def test_bf16_split_against_f64(ctx, form, tol):
     """Split-bf16 core kernel sums (three- or two-part operands) against the
