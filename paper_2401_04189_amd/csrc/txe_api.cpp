@@ -266,7 +266,7 @@ static txe_status upload(DevTables<T> &dt, const std::vector<double> &src, T **d
 
 // Build every table in FP64 with the layouts Tables<T> documents.
 struct HostTables {
-  std::vector<double> V2B, V1chain, V0K, C1B, C2chain, Ahat, U0chain, U2T, U1chain;
+  std::vector<double> V2B, V1chain, V0K, C1f, C2chain, Ahat, U0chain, U2T, U1chain;
 };
 
 // Accumulator row of entry v in lane group lg of a 16x16x4 MFMA: 4*lg + v
@@ -295,15 +295,31 @@ static void build_tables(const txe_system &S, HostTables &H, bool f64) {
   H.V0K.assign((size_t)D.n0 * D.rp0, 0.0);
   for (int a = 0; a < D.n0; ++a)
     for (int al = 0; al < D.r0; ++al) H.V0K[(size_t)a * D.rp0 + al] = V(0, a, al);
-  // C1B[k][beta][beta'] = Chat1_k[beta'][beta]
-  H.C1B.assign((size_t)D.Kp * D.rp1 * D.rp1, 0.0);
-  for (int k = 0; k < D.K; ++k)
-    for (int be = 0; be < D.r1; ++be)
-      for (int bp = 0; bp < D.r1; ++bp) H.C1B[((size_t)k * D.rp1 + be) * D.rp1 + bp] = Ch(1, k, bp, be);
-  // C2chain[k][mt'][mg][v][lane] = Chat2_k[gamma' = 16mt'+lr][gamma = 16mg+4v+lg]
-  // for both precisions: chunk v of tile mg holds gamma rows 16mg+4v..+3, so
-  // chunks past the rank are all zero and the core skips them (the FP32 core
-  // orders the slab's gamma rows inside a tile to match)
+  // FP32: C1f[k][bt][kq][lane][j] = Chat1_k[beta' = 16bt+lr][beta = 16kq+4j+lg],
+  // the B fragments of K = 4 steps kt = 4kq+j of the core's W chain side by
+  // side; FP64: C1f[k][beta][beta'] = Chat1_k[beta'][beta]
+  if (f64) {
+    H.C1f.assign((size_t)D.Kp * D.rp1 * D.rp1, 0.0);
+    for (int k = 0; k < D.K; ++k)
+      for (int be = 0; be < D.r1; ++be)
+        for (int bp = 0; bp < D.r1; ++bp) H.C1f[((size_t)k * D.rp1 + be) * D.rp1 + bp] = Ch(1, k, bp, be);
+  } else {
+    H.C1f.assign((size_t)D.Kp * D.MT1 * D.MT1 * 256, 0.0);
+    for (int k = 0; k < D.K; ++k)
+      for (int bt = 0; bt < D.MT1; ++bt)
+        for (int kq = 0; kq < D.MT1; ++kq)
+          for (int l = 0; l < 64; ++l)
+            for (int j = 0; j < 4; ++j) {
+              const int bp = 16 * bt + (l & 15), be = 16 * kq + 4 * j + (l >> 4);
+              if (bp < D.r1 && be < D.r1)
+                H.C1f[((((size_t)k * D.MT1 + bt) * D.MT1 + kq) * 64 + l) * 4 + j] = Ch(1, k, bp, be);
+            }
+  }
+  // C2chain: Chat2_k[gamma' = 16mt'+lr][gamma = 16mg+4v+lg] at [k][mt'][mg][lane][v]
+  // (FP32) or [k][mt'][mg][v][lane] (FP64).  In both precisions chunk v of
+  // tile mg holds gamma rows 16mg+4v..+3, so chunks past the rank are all
+  // zero and the core skips them (the FP32 core orders the slab's gamma rows
+  // inside a tile to match)
   H.C2chain.assign((size_t)D.Kp * D.MT2 * D.MT2 * 256, 0.0);
   for (int k = 0; k < D.K; ++k)
     for (int mtp = 0; mtp < D.MT2; ++mtp)
@@ -311,8 +327,8 @@ static void build_tables(const txe_system &S, HostTables &H, bool f64) {
         for (int v = 0; v < 4; ++v)
           for (int l = 0; l < 64; ++l) {
             const int gp = 16 * mtp + (l & 15), g = 16 * mg + 4 * v + (l >> 4);
-            if (gp < D.r2 && g < D.r2)
-              H.C2chain[((((size_t)k * D.MT2 + mtp) * D.MT2 + mg) * 4 + v) * 64 + l] = Ch(2, k, gp, g);
+            const size_t base = (((size_t)k * D.MT2 + mtp) * D.MT2 + mg) * 256;
+            if (gp < D.r2 && g < D.r2) H.C2chain[base + (f64 ? v * 64 + l : l * 4 + v)] = Ch(2, k, gp, g);
           }
   // Ahat[alpha][k][alpha'] = w_k Chat0_k[alpha'][alpha]
   H.Ahat.assign((size_t)D.r0 * D.Kp * D.rp0, 0.0);
@@ -411,7 +427,7 @@ static txe_status upload_tables(DevTables<T> &dt, const HostTables &H, hipStream
   if ((st = upload(dt, H.V2B, &dt.t.V2B, s)) != TXE_OK) return st;
   if ((st = upload(dt, H.V1chain, &dt.t.V1chain, s)) != TXE_OK) return st;
   if ((st = upload(dt, H.V0K, &dt.t.V0K, s)) != TXE_OK) return st;
-  if ((st = upload(dt, H.C1B, &dt.t.C1B, s)) != TXE_OK) return st;
+  if ((st = upload(dt, H.C1f, &dt.t.C1f, s)) != TXE_OK) return st;
   if ((st = upload(dt, H.C2chain, &dt.t.C2chain, s)) != TXE_OK) return st;
   if ((st = upload(dt, H.Ahat, &dt.t.Ahat, s)) != TXE_OK) return st;
   if ((st = upload(dt, H.U0chain, &dt.t.U0chain, s)) != TXE_OK) return st;

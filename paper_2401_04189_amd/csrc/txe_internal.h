@@ -43,14 +43,20 @@ struct PairMap {
 // is zero beyond the true sizes, so padded rows and columns contribute zero.
 // "chain" tables hold the A operand of an MFMA whose B operand is the
 // accumulator of the previous MFMA, permuted to the accumulator's row order:
-// entry [..][v][lane] is M[16*m + lane%16][16*kt + 4*(lane/16) + v].
+// entry [..][v][lane] is M[16*m + lane%16][16*kt + drow(lane/16, v)].  In
+// FP32 the core's term tables (C1f, C2chain) keep a lane's four K = 4 steps
+// side by side, [..][lane][4], for 16-byte loads.
 template <typename T>
 struct Tables {
   T *V2B;       // [nc2][rp2]            V2[c][gamma]                    (q2 U2)
   T *V1chain;   // [MT1][nb1/16][4][64]  V1[b][beta] as A[beta][b]
   T *V0K;       // [n0][rp0]             V0[a][alpha]
-  T *C1B;       // [Kp][rp1][rp1]        Chat1_k[beta'][beta] at [k][beta][beta']
-  T *C2chain;   // [Kp][MT2][MT2][4][64] Chat2_k[gamma'][gamma]
+  // FP32: [Kp][MT1][MT1][64][4] Chat1_k[16bt + l%16][16kq + 4j + l/16] at [k][bt][kq][l][j]
+  // FP64: [Kp][rp1][rp1]        Chat1_k[beta'][beta] at [k][beta][beta']
+  T *C1f;
+  // FP32: [Kp][MT2][MT2][64][4] Chat2_k[16mt' + l%16][16mg + 4v + l/16] at [k][mt'][mg][l][v]
+  // FP64: [Kp][MT2][MT2][4][64] the same element at [k][mt'][mg][v][l]
+  T *C2chain;
   T *Ahat;      // [r0][Kp][rp0]         w_k Chat0_k[alpha'][alpha] at [alpha][k][alpha']
   T *U0chain;   // [na0/16][MT0][4][64]  U0[a][alpha']
   T *U2T;       // [rp2][nc2]            U2[c][gamma] at [gamma][c]

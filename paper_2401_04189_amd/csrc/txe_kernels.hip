@@ -68,6 +68,25 @@ __device__ __forceinline__ void load4(const float *p, double (&o)[4]) {
   const f4 v = *reinterpret_cast<const f4 *>(p);
   o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
 }
+// the first NL of four consecutive floats (16-byte aligned); the rest are zero
+template <int NL>
+__device__ __forceinline__ void loadn(const float *p, float (&o)[4]) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef float f3 __attribute__((ext_vector_type(3)));
+  o[0] = o[1] = o[2] = o[3] = 0.f;
+  if constexpr (NL == 1) {
+    o[0] = *p;
+  } else if constexpr (NL == 2) {
+    const f2 v = *reinterpret_cast<const f2 *>(p);
+    o[0] = v[0]; o[1] = v[1];
+  } else if constexpr (NL == 3) {
+    const f3 v = *reinterpret_cast<const f3 *>(p);
+    o[0] = v[0]; o[1] = v[1]; o[2] = v[2];
+  } else {
+    const f4 v = *reinterpret_cast<const f4 *>(p);
+    o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+  }
+}
 
 __device__ __forceinline__ long long sym_start(long long i, long long N) { return i * N - i * (i - 1) / 2; }
 
@@ -514,6 +533,35 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
     T cb[4 * MT];
     T af[NTG][MT];
   };
+  // Chat1_k B fragments of every K = 4 step of the W chain (FP32: a lane's
+  // four steps of one 16-row group with one load, the live ones only)
+  auto load_c1 = [&](int k_, T (&cb)[4 * MT]) {
+    if constexpr (F32) {
+      const float *C1k = tb.C1f + ((size_t)k_ * MT + bt) * MT * 256 + lane * 4;
+#pragma unroll
+      for (int kq4 = 0; kq4 < MT; ++kq4) {
+        float(&o)[4] = *reinterpret_cast<float(*)[4]>(&cb[4 * kq4]);
+        if (kq4 < MT - 1) loadn<4>(C1k + kq4 * 256, o);
+        else loadn<TL>(C1k + kq4 * 256, o);
+      }
+    } else {
+      const T *C1k = tb.C1f + (size_t)k_ * F + 16 * bt + lr;
+#pragma unroll
+      for (int kt = 0; kt < 4 * MT; ++kt) cb[kt] = C1k[(4 * kt + lg) * RP];
+    }
+  };
+  // Chat2_k A fragments [v] of gamma' tile mtp and gamma tile mg
+  auto load_c2 = [&](int k_, int mtp, int mg, T (&o)[4]) {
+    if constexpr (F32) {
+      const float *p_ = tb.C2chain + ((size_t)k_ * MT * MT + mtp * MT + mg) * 256 + lane * 4;
+      if (mg < MT - 1) loadn<4>(p_, o);
+      else loadn<TL>(p_, o);
+    } else {
+      const T *p_ = tb.C2chain + ((size_t)k_ * MT * MT + mtp * MT + mg) * 256 + lane;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[v] = p_[v * 64];
+    }
+  };
   auto load_terms = [&](int alpha_, int kq_, CF &f) {
 #pragma unroll
     for (int tg = 0; tg < NTG; ++tg) {
@@ -523,9 +571,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
     }
     const int k_ = NW * kq_ + wave;
     if (k_ >= D.K) return;
-    const T *C1k = tb.C1B + (size_t)k_ * F + 16 * bt + lr;
-#pragma unroll
-    for (int kt = 0; kt < 4 * MT; ++kt) f.cb[kt] = C1k[(4 * kt + lg) * RP];
+    load_c1(k_, f.cb);
   };
   // A fragments of slab alpha: G[alpha][beta = 4kt+lg][gamma = 16mg+lr]
   auto load_slab = [&](int alpha_, T (&g)[GK][GM]) {
@@ -592,13 +638,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
     T c2s[C2S ? MT : 1][C2S ? MT : 1][4];
     if constexpr (C2S) {
       if (k < D.K) {
-        const T *C2k = tb.C2chain + (size_t)k * MT * MT * 256 + lane;
 #pragma unroll
         for (int mtp = 0; mtp < MT; ++mtp)
 #pragma unroll
-          for (int mg = 0; mg < MT; ++mg)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) c2s[mtp][mg][v] = C2k[((mtp * MT + mg) * 4 + v) * 64];
+          for (int mg = 0; mg < MT; ++mg) load_c2(k, mtp, mg, c2s[mtp][mg]);
       }
     }
     if constexpr (PF) {
@@ -606,11 +649,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
       if (step + 1 < nsteps) load_terms(wrap ? alpha + 1 : alpha, wrap ? 0 : kq + 1, nxt);
     }
     if constexpr (!PF) {
-      if (k < D.K) {
-        const T *C1k = tb.C1B + (size_t)k * F + 16 * bt + lr;
-#pragma unroll
-        for (int kt = 0; kt < 4 * MT; ++kt) cur.cb[kt] = C1k[(4 * kt + lg) * RP];
-      }
+      if (k < D.K) load_c1(k, cur.cb);
     }
     T *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * gper * 16;
     // ---- phase A
@@ -670,7 +709,6 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
 #pragma unroll
         for (int mtp = 0; mtp < MT; ++mtp) store_z(mtp, Z[mtp]);
       } else {
-        const T *C2k = tb.C2chain + (size_t)k * MT * MT * 256 + lane;
 #pragma unroll
         for (int mtp = 0; mtp < MT; ++mtp) {
           // only the gamma' tiles that meet this workgroup's rows (uniform);
@@ -686,9 +724,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
               for (int v = 0; v < 4; ++v) c2[mg][v] = c2s[mtp][mg][v];
           } else {
 #pragma unroll
-            for (int mg = 0; mg < MT; ++mg)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) c2[mg][v] = C2k[((mtp * MT + mg) * 4 + v) * 64];
+            for (int mg = 0; mg < MT; ++mg) load_c2(k, mtp, mg, c2[mg]);
           }
           acc Z = zero4<acc>();
 #pragma unroll
