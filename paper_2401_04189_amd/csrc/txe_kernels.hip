@@ -507,8 +507,15 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   constexpr int SROW = 16 * LPL;
   constexpr int SLAB = LDS_G ? RP * SROW : 0;
   T *Gs = reinterpret_cast<T *>(smem_raw);        // [2][RP][16][LPL] (LDS_G)
-  T *Zs = Gs + 2 * SLAB;                          // [2][NW][gper][16]
-  const int zsz = NW * gper * 16;
+  // Z slots: [2][NW][ZSS].  FP32: row gamma' of slot w at gamma' * ZRS, every
+  // padded row has room, so stores need no range test; the 80-byte row
+  // stride spreads a store's four lane groups (rows 4 apart) over the banks
+  // and the slot stride does the same for phase B's four terms.  FP64 (the
+  // faster form there): only the workgroup's gper rows, at (gamma' - g_lo) * 16
+  constexpr int ZRS = F32 ? 20 : 16;
+  const int ZSS = F32 ? RP * ZRS + 16 : gper * 16;
+  T *Zs = Gs + 2 * SLAB;
+  const int zsz = NW * ZSS;
 
   acc Phi[MT][NGW];
 #pragma unroll
@@ -651,7 +658,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
     if constexpr (!PF) {
       if (k < D.K) load_c1(k, cur.cb);
     }
-    T *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * gper * 16;
+    T *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * ZSS;
     // ---- phase A
     if (k < D.K) {
       acc W[MT];
@@ -682,16 +689,17 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
           W[mg] = M::mma(g, cur.cb[kt], W[mg]);
         }
       }
-      // Z rows outside this workgroup's gamma' range are not stored.  With
-      // Chat2 loaded whole (small ranks, FP32) the tiles' chains are
+      // With Chat2 loaded whole (small ranks, FP32) the tiles' chains are
       // interleaved (short MFMA latency, cheap accumulators); otherwise one
-      // tile at a time, skipping tiles outside the range and loading each
-      // tile's Chat2 fragments in turn (keeps registers for Phi)
+      // tile at a time, skipping tiles outside this workgroup's gamma' rows
+      // and loading each tile's Chat2 fragments in turn (keeps registers
+      // for Phi).  Rows outside the range are stored and never read.
       auto store_z = [&](int mtp, const acc &Zt) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int gp = 16 * mtp + drow<T>(lg, v);
-          if (gp >= g_lo && gp < g_hi) Zw[(gp - g_lo) * 16 + lr] = Zt[v];
+          if constexpr (F32) Zw[gp * ZRS + lr] = Zt[v];
+          else if (gp >= g_lo && gp < g_hi) Zw[(gp - g_lo) * 16 + lr] = Zt[v];
         }
       };
       if constexpr (F32 && C2S) {
@@ -739,7 +747,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
         }
       }
     } else {
-      for (int idx = lane; idx < gper * 16; idx += 64) Zw[idx] = (T)0;
+      if constexpr (F32)
+        for (int idx = lane; idx < (g_hi - g_lo) * 16; idx += 64) Zw[(g_lo + (idx >> 4)) * ZRS + (idx & 15)] = (T)0;
+      else
+        for (int idx = lane; idx < gper * 16; idx += 64) Zw[idx] = (T)0;
     }
     if constexpr (LDS_G) {
       if (alpha + 1 < D.r0) {
@@ -754,28 +765,47 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
     }
     __syncthreads();
     // ---- phase B: reduction over the step's terms, four at a time (slot lg
-    // of group tg)
+    // of group tg); rows past this wavefront's range read a valid LDS row
+    // and are never stored, and with eight wavefronts a uniform bound skips
+    // the spare rows' MFMAs
+    const T *zb = Zs + (size_t)(step & 1) * zsz + lr;
+    if constexpr (F32) {
+      // all Z rows read before the first MFMA
+      T bz[NTG][NGW];
 #pragma unroll
-    for (int tg = 0; tg < NTG; ++tg) {
-      T af[MT];
-      if constexpr (PF) {
+      for (int tg = 0; tg < NTG; ++tg)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) af[mt] = cur.af[tg][mt];
-      } else {
-        const T *ah = tb.Ahat + ((size_t)alpha * D.Kp + NW * kq + 4 * tg + lg) * RP + lr;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) af[mt] = ah[16 * mt];
-      }
-      const T *zrow = Zs + (size_t)(step & 1) * zsz + (size_t)(4 * tg + lg) * gper * 16 + lr;
-      // rows past this wavefront's range read a valid LDS row and are never
-      // stored; with eight wavefronts a uniform bound skips the spare rows
+        for (int ng = 0; ng < NGW; ++ng) bz[tg][ng] = zb[(4 * tg + lg) * ZSS + min(wg_lo + ng, RP - 1) * ZRS];
 #pragma unroll
       for (int ng = 0; ng < NGW; ++ng) {
         if (NW == 8 && ng >= gw) break;
-        const int row = min(wg_lo - g_lo + ng, gper - 1);
-        const T bz = zrow[row * 16];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(af[mt], bz, Phi[mt][ng]);
+        for (int tg = 0; tg < NTG; ++tg)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(cur.af[tg][mt], bz[tg][ng], Phi[mt][ng]);
+      }
+    } else {
+      // FP64 (four wavefronts, up to ten rows): each row's read next to its
+      // MFMAs keeps the register file for the Phi accumulators
+#pragma unroll
+      for (int tg = 0; tg < NTG; ++tg) {
+        T af[MT];
+        if constexpr (PF) {
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) af[mt] = cur.af[tg][mt];
+        } else {
+          const T *ah = tb.Ahat + ((size_t)alpha * D.Kp + NW * kq + 4 * tg + lg) * RP + lr;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) af[mt] = ah[16 * mt];
+        }
+        const T *zrow = zb + (size_t)(4 * tg + lg) * ZSS;
+#pragma unroll
+        for (int ng = 0; ng < NGW; ++ng) {
+          if (NW == 8 && ng >= gw) break;
+          const T bz = zrow[min(wg_lo - g_lo + ng, gper - 1) * 16];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(af[mt], bz, Phi[mt][ng]);
+        }
       }
     }
   };
@@ -1411,7 +1441,8 @@ hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_
   constexpr int RP = 16 * MT;
   constexpr bool lds_g = sizeof(T) == 4 && MT >= 3;  // the slab-in-LDS forms of k_core
   constexpr size_t slab = lds_g ? (size_t)RP * 16 * (MT <= 4 ? 4 : 8) : 0;
-  const size_t lds = (2 * slab + 2 * NW * (size_t)gper * 16) * sizeof(T);
+  const size_t zslot = sizeof(T) == 4 ? (size_t)RP * 20 + 16 : (size_t)gper * 16;  // k_core's Z slot
+  const size_t lds = (2 * slab + 2 * NW * zslot) * sizeof(T);
   const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
   if (lds > 64 * 1024) {  // opt in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
     const void *fn =
