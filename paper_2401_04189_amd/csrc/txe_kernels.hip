@@ -90,6 +90,17 @@ __device__ __forceinline__ void loadn(const float *p, float (&o)[4]) {
 
 __device__ __forceinline__ long long sym_start(long long i, long long N) { return i * N - i * (i - 1) / 2; }
 
+// a global-memory pointer the caller knows to be the same in every lane,
+// moved to scalar registers (loads then take a scalar base and a 32-bit lane
+// offset)
+template <typename P>
+__device__ __forceinline__ const __attribute__((address_space(1))) P *wave_uniform(const P *p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (const __attribute__((address_space(1))) P *)(((unsigned long long)hi << 32) | lo);
+}
+
 // Workgroups are handed to the eight XCDs round-robin (block b runs on XCD
 // b mod 8), and each XCD has its own L2.  This bijection renumbers the grid
 // so that each XCD receives one contiguous range of logical block indices:
@@ -1220,13 +1231,13 @@ __global__ __launch_bounds__(256) void k_back_s(const T *__restrict__ S1, const 
   }
 }
 
-template <typename T, typename Tin, int MT, int NBT, int NCG>
+template <typename T, typename Tin, int MT, int NBT, int NCG, bool LDS_TAB>
 __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const Tin *__restrict__ psi, Dims D,
                                                 PairMap pm, int N, int t_begin, int t_count, Tables<T> tb,
                                                 Tin *__restrict__ vx, const double *__restrict__ out_scale,
                                                 int weighted, const double *__restrict__ q0,
                                                 const double *__restrict__ q1, const double *__restrict__ q2,
-                                                int lds_tab, int mb0) {
+                                                int mb0) {
   using M = MF<T>;
   using acc = typename M::acc;
   constexpr int RP = 16 * MT;
@@ -1238,22 +1249,24 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
   const int nct = D.nc2 >> 4, nbt = D.nb1 >> 4;
   const int ncg = (nct + NCG - 1) / NCG;
   const int nkt = (D.r2 + 3) >> 2;  // gamma' rows in use, in fours
-  // shared operands (U2^T and the chained U1 fragments) staged once per
-  // workgroup when they fit in LDS
-  const T *U2t = tb.U2T, *U1c = tb.U1chain;
-  if (lds_tab) {
-    T *s2 = reinterpret_cast<T *>(smem_raw);
-    T *s1 = s2 + (size_t)RP * D.nc2;
+  // shared operands (U2^T and the chained U1 fragments), staged once per
+  // workgroup in LDS when they fit (the choice is compile-time, so the
+  // reads are LDS or global loads, never generic ones)
+  T *s2 = reinterpret_cast<T *>(smem_raw);
+  T *s1 = s2 + (size_t)RP * D.nc2;
+  if constexpr (LDS_TAB) {
     const int m2 = RP * D.nc2, m1 = nbt * MT * 256;
     for (int idx = threadIdx.x; idx < m2; idx += 256) s2[idx] = tb.U2T[idx];
     for (int idx = threadIdx.x; idx < m1; idx += 256) s1[idx] = tb.U1chain[idx];
     __syncthreads();
-    U2t = s2;
-    U1c = s1;
   }
+  const T *U2t = LDS_TAB ? s2 : tb.U2T;
+  const T *U1c = LDS_TAB ? s1 : tb.U1chain;
   const size_t plane = (size_t)D.n1 * D.n2;
   const size_t S1pair = (size_t)D.n0 * RP * RP;
   const long long total = (long long)t_count * D.n0 * ncg;
+  // per-lane offsets are 32-bit and unsigned, added to wave-uniform bases
+  const unsigned soff = (unsigned)(lg * RP + lr);  // S1 fragment element of this lane
   for (long long item = (long long)blockIdx.x * 4 + wave; item < total; item += (long long)gridDim.x * 4) {
     const int cgi = (int)(item % ncg);
     const long long rest = item / ncg;
@@ -1270,17 +1283,17 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
 #pragma unroll
     for (int kt = 0; kt < 4 * MT; ++kt)
 #pragma unroll
-      for (int cg = 0; cg < NCG; ++cg) bu[kt][cg] = U2t[(size_t)(4 * kt + lg) * D.nc2 + 16 * ct[cg] + lr];
+      for (int cg = 0; cg < NCG; ++cg) bu[kt][cg] = U2t[(unsigned)((4 * kt + lg) * D.nc2 + 16 * ct[cg] + lr)];
     // psi_j values of this wavefront's output points, clamped into the grid
     // (points past the edge are computed and never stored)
-    int poff[NBT][4];  // within one plane (n1 n2 < 2^31)
+    unsigned poff[NBT][4];  // within one plane (n1 n2 < 2^31)
 #pragma unroll
     for (int mbb = 0; mbb < NBT; ++mbb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) poff[mbb][v] = min(16 * (mb0 + mbb) + drow<T>(lg, v), D.n1 - 1) * D.n2;
-    int pc[NCG];
+      for (int v = 0; v < 4; ++v) poff[mbb][v] = (unsigned)(min(16 * (mb0 + mbb) + drow<T>(lg, v), D.n1 - 1) * D.n2);
+    unsigned pc[NCG];
 #pragma unroll
-    for (int cg = 0; cg < NCG; ++cg) pc[cg] = min(16 * ct[cg] + lr, D.n2 - 1);
+    for (int cg = 0; cg < NCG; ++cg) pc[cg] = (unsigned)min(16 * ct[cg] + lr, D.n2 - 1);
 
     acc Acc[NBT][NCG];
 #pragma unroll
@@ -1296,13 +1309,13 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
       } else {
         pg = (long long)t * pm.N + s;
       }
-      const T *S = S1 + (size_t)(pg - pm.p0) * S1pair + (size_t)a * RP * RP + lr;
-      const Tin *ps = psi + (size_t)s * D.n0 * plane + (size_t)a * plane;
+      const auto *S = wave_uniform(S1 + (size_t)(pg - pm.p0) * S1pair + (size_t)a * RP * RP);
+      const auto *ps = wave_uniform(psi + (size_t)s * D.n0 * plane + (size_t)a * plane);
       // the U1 fragments do not depend on the source, but holding all of
-      // them across the source loop costs NBT * MT * 4 registers: an empty
-      // asm makes the table pointer opaque per source so they are reloaded
-      const T *u1 = U1c;
-      asm volatile("" : "+v"(u1));
+      // them across the source loop costs NBT * MT * 4 registers: an offset
+      // made opaque per source by an empty asm makes them reload
+      unsigned u1o = (unsigned)(mb0 * MT * 256 + lane);
+      asm volatile("" : "+v"(u1o));
       // X[beta'][c] = sum_gamma' S1[gamma'][beta'] U2[c][gamma']
       acc X[MT][NCG];
 #pragma unroll
@@ -1318,7 +1331,7 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
           const int gam = 4 * (kb + k) + lg;
 #pragma unroll
           for (int mb = 0; mb < MT; ++mb) {
-            const T x = S[(size_t)gam * RP + 16 * mb];
+            const T x = S[soff + (unsigned)(4 * (kb + k) * RP + 16 * mb)];
             sf[k][mb] = gam < D.r2 ? x : (T)0;  // rows past r2 are not written by the core kernel
           }
         }
@@ -1349,7 +1362,7 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
         for (int mbe = 0; mbe < MT; ++mbe)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const T af = u1[(((size_t)(mb0 + mbb) * MT + mbe) * 4 + v) * 64 + lane];
+            const T af = U1c[u1o + (unsigned)(((mbb * MT + mbe) * 4 + v) * 64)];
 #pragma unroll
             for (int cg = 0; cg < NCG; ++cg) ph[cg] = M::mma(af, X[mbe][cg][v], ph[cg]);
           }
@@ -1593,10 +1606,17 @@ hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStrea
   // (registers); more take several launches over disjoint b ranges, each
   // recomputing X for its sources (measured faster at 80^3)
   if (nbt > 8) return hipErrorInvalidValue;
-#define TXE_BACK(NBTV, MB0)                                                                                 \
-  hipLaunchKernelGGL((k_back_b<T, Tin, MT, NBTV, NCG>), dim3(nbl), dim3(256), lds, s, a.S1, psi, a.D, a.pm, \
-                     a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1],      \
-                     a.qdev[2], lds_tab, MB0)
+#define TXE_BACK(NBTV, MB0)                                                                                      \
+  do {                                                                                                           \
+    if (lds_tab)                                                                                                 \
+      hipLaunchKernelGGL((k_back_b<T, Tin, MT, NBTV, NCG, true>), dim3(nbl), dim3(256), lds, s, a.S1, psi, a.D,  \
+                         a.pm, a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0],           \
+                         a.qdev[1], a.qdev[2], MB0);                                                             \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_back_b<T, Tin, MT, NBTV, NCG, false>), dim3(nbl), dim3(256), 0, s, a.S1, psi, a.D,   \
+                         a.pm, a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0],           \
+                         a.qdev[1], a.qdev[2], MB0);                                                             \
+  } while (0)
   if (nbt <= 2) {
     TXE_BACK(2, 0);
   } else if (nbt <= 4) {
