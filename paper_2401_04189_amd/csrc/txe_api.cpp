@@ -604,7 +604,8 @@ struct Plan {
   int tchunk;          // targets per chunk (block mode)
   long long Pmax;      // pairs per chunk
   size_t elt;
-  size_t off_T2, off_G, off_S1, off_epart, off_epair, total;
+  size_t psi32_elems;  // FP32 copy of FP64 orbitals for the projection (0: none)
+  size_t off_T2, off_G, off_S1, off_epart, off_epair, off_psi32, total;
 };
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -620,6 +621,7 @@ static void plan_sizes(const Dims &D, Plan &pl) {
   pl.off_S1 = off; off = align256(off + P * perS1 * pl.elt);
   pl.off_epart = off; off = align256(off + P * D.MT1 * pl.NGS * sizeof(double));
   pl.off_epair = off; off = align256(off + (size_t)pl.npairs * sizeof(double));
+  pl.off_psi32 = off; off = align256(off + pl.psi32_elems * sizeof(float));
   pl.total = off;
 }
 
@@ -630,6 +632,9 @@ static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, cons
   pl.symmetric = a->symmetric != 0;
   pl.want_vx = a->vxpsi != nullptr;
   pl.elt = pl.f64 ? sizeof(double) : sizeof(float);
+  // the reduced-precision forms project FP64 orbitals from an FP32 copy
+  // (half the bytes of the projection's orbital reads)
+  pl.psi32_elems = (!pl.f64 && a->dtype == TXE_DTYPE_F64) ? (size_t)a->N * D.n0 * D.n1 * D.n2 : 0;
   pl.npairs = pl.symmetric ? (long long)a->N * (a->N + 1) / 2 : (long long)a->Ni * a->N;
   const int mt = std::max(D.MT0, std::max(D.MT1, D.MT2));
   const int nsplit = a->compute == TXE_COMPUTE_BF16X3 ? 2 : a->compute == TXE_COMPUTE_BF16X6 ? 3 : 0;
@@ -771,6 +776,11 @@ static hipError_t run_plan(const txe_system *sys, const txe_apply_args *args, co
     } else {
       ChunkArgs<float> c = chunk_args<float>(sys, args, pl, ws);
       c.pm.p0 = p0; c.P = P; c.t_begin = tb; c.t_count = tcnt;
+      if (pl.psi32_elems) {
+        c.psi32 = (const float *)(ws + pl.off_psi32);
+        c.psi32_fill = ci == 0 ? 1 : 0;
+        c.psi_elems = pl.psi32_elems;
+      }
       if (args->compute == TXE_COMPUTE_F32)
         e = run_chunk_f32(sys->t32.t, c, psi64, pl.want_vx, s, prof);
       else

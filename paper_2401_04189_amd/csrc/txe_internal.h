@@ -91,6 +91,11 @@ struct ChunkArgs {
   int back_form;              // back kernel form (1 streaming, 2 batched; 0 = default, batched)
   int grid_cap;               // workgroups of the persistent kernels
   const void *psi;
+  // FP32 copy of FP64 orbitals for the projection of the reduced-precision
+  // forms (null: the projection reads psi); psi32_fill: this chunk writes it
+  const float *psi32;
+  int psi32_fill;
+  size_t psi_elems;           // N * n0 * n1 * n2
   void *vx;
   const double *out_scale;
   int weighted;

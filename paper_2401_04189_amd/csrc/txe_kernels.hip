@@ -21,6 +21,7 @@
 // so an accumulator whose rows are the next contraction index feeds the next
 // MFMA as its B operand directly, one entry v at a time ("chained").
 #include <algorithm>
+#include <type_traits>
 
 #include "txe_internal.h"
 
@@ -1231,8 +1232,8 @@ __global__ __launch_bounds__(256) void k_back_s(const T *__restrict__ S1, const 
   }
 }
 
-template <typename T, typename Tin, int MT, int NBT, int NCG, bool LDS_TAB>
-__global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const Tin *__restrict__ psi, Dims D,
+template <typename T, typename Tin, typename Tps, int MT, int NBT, int NCG, bool LDS_TAB>
+__global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const Tps *__restrict__ psi, Dims D,
                                                 PairMap pm, int N, int t_begin, int t_count, Tables<T> tb,
                                                 Tin *__restrict__ vx, const double *__restrict__ out_scale,
                                                 int weighted, const double *__restrict__ q0,
@@ -1350,7 +1351,7 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
         // other tiles out of registers
         __builtin_amdgcn_sched_barrier(0);
         // psi_j at this b tile's points, loaded ahead of the chain that needs them
-        Tin pv[NCG][4];
+        Tps pv[NCG][4];
 #pragma unroll
         for (int cg = 0; cg < NCG; ++cg)
 #pragma unroll
@@ -1589,12 +1590,14 @@ hipError_t launch_back_s_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStre
   return hipGetLastError();
 }
 
-template <typename T, typename Tin, int MT, int NCG>
+template <typename T, typename Tin, typename Tps, int MT, int NCG>
 hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
   const int nct = a.D.nc2 >> 4, nbt = a.D.nb1 >> 4;
   const long long waves = (long long)a.t_count * a.D.n0 * ((nct + NCG - 1) / NCG);
   const unsigned nb = blocks_for(waves);
-  const Tin *psi = (const Tin *)a.psi;
+  // psi_j as read: the orbitals, or their FP32 copy (the values the FP32
+  // kernel rounds them to anyway)
+  const Tps *psi = std::is_same<Tps, Tin>::value ? (const Tps *)a.psi : (const Tps *)a.psi32;
   Tin *vx = (Tin *)a.vx;
   // shared operands in LDS when they fit in 64 KiB; the grid is then capped
   // and each workgroup walks several items
@@ -1609,11 +1612,11 @@ hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStrea
 #define TXE_BACK(NBTV, MB0)                                                                                      \
   do {                                                                                                           \
     if (lds_tab)                                                                                                 \
-      hipLaunchKernelGGL((k_back_b<T, Tin, MT, NBTV, NCG, true>), dim3(nbl), dim3(256), lds, s, a.S1, psi, a.D,  \
+      hipLaunchKernelGGL((k_back_b<T, Tin, Tps, MT, NBTV, NCG, true>), dim3(nbl), dim3(256), lds, s, a.S1, psi, a.D,  \
                          a.pm, a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0],           \
                          a.qdev[1], a.qdev[2], MB0);                                                             \
     else                                                                                                         \
-      hipLaunchKernelGGL((k_back_b<T, Tin, MT, NBTV, NCG, false>), dim3(nbl), dim3(256), 0, s, a.S1, psi, a.D,   \
+      hipLaunchKernelGGL((k_back_b<T, Tin, Tps, MT, NBTV, NCG, false>), dim3(nbl), dim3(256), 0, s, a.S1, psi, a.D,   \
                          a.pm, a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0],           \
                          a.qdev[1], a.qdev[2], MB0);                                                             \
   } while (0)
@@ -1631,16 +1634,23 @@ hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStrea
   return hipGetLastError();
 }
 
-template <typename T, typename Tin, int NCG>
-hipError_t launch_back_b_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+template <typename T, typename Tin, typename Tps, int NCG>
+hipError_t launch_back_b_tps(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
   switch (a.D.MT1) {
-    case 1: return launch_back_b_mt<T, Tin, 1, NCG>(tb, a, s);
-    case 2: return launch_back_b_mt<T, Tin, 2, NCG>(tb, a, s);
-    case 3: return launch_back_b_mt<T, Tin, 3, NCG>(tb, a, s);
-    case 4: return launch_back_b_mt<T, Tin, 4, NCG>(tb, a, s);
-    case 5: return launch_back_b_mt<T, Tin, 5, NCG>(tb, a, s);
+    case 1: return launch_back_b_mt<T, Tin, Tps, 1, NCG>(tb, a, s);
+    case 2: return launch_back_b_mt<T, Tin, Tps, 2, NCG>(tb, a, s);
+    case 3: return launch_back_b_mt<T, Tin, Tps, 3, NCG>(tb, a, s);
+    case 4: return launch_back_b_mt<T, Tin, Tps, 4, NCG>(tb, a, s);
+    case 5: return launch_back_b_mt<T, Tin, Tps, 5, NCG>(tb, a, s);
   }
   return hipErrorInvalidValue;
+}
+
+template <typename T, typename Tin, int NCG>
+hipError_t launch_back_b_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  if constexpr (sizeof(T) == 4 && sizeof(Tin) == 8)
+    if (a.psi32) return launch_back_b_tps<T, Tin, float, NCG>(tb, a, s);
+  return launch_back_b_tps<T, Tin, Tin, NCG>(tb, a, s);
 }
 
 template <typename T, typename Tin>
@@ -1692,16 +1702,51 @@ void launch_proj12(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
                        a.P, tb, a.T2);
 }
 
+// FP64 orbitals rounded to FP32 (two per thread and step)
+__global__ __launch_bounds__(256) void k_psi_f32(const double *__restrict__ in, float *__restrict__ out, size_t n) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const size_t n2 = n / 2;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (size_t)gridDim.x * 256) {
+    const d2 v = reinterpret_cast<const d2 *>(in)[i];
+    f2 o;
+    o[0] = (float)v[0];
+    o[1] = (float)v[1];
+    reinterpret_cast<f2 *>(out)[i] = o;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) out[n - 1] = (float)in[n - 1];
+}
+
+template <typename T, typename TinP>
+void launch_proj(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  if (a.proj_gt == 4) launch_proj12m<T, TinP>(tb, a, s);
+  else if (a.proj_gt == 1) launch_proj12<T, TinP, 1>(tb, a, s);
+  else if (a.proj_gt == 3) launch_proj12<T, TinP, 3>(tb, a, s);
+  else launch_proj12<T, TinP, 2>(tb, a, s);
+}
+
 template <typename T, typename Tin>
 hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s, Prof *prof,
                        const BfTables *bft = nullptr, int nsplit = 0) {
   constexpr int FT = 4;
   hipError_t e;
   prof->begin(K_PROJ12, s);
-  if (a.proj_gt == 4) launch_proj12m<T, Tin>(tb, a, s);
-  else if (a.proj_gt == 1) launch_proj12<T, Tin, 1>(tb, a, s);
-  else if (a.proj_gt == 3) launch_proj12<T, Tin, 3>(tb, a, s);
-  else launch_proj12<T, Tin, 2>(tb, a, s);
+  if constexpr (sizeof(T) == 4 && sizeof(Tin) == 8) {
+    if (a.psi32) {
+      // the projection reads the FP32 copy (written once per apply, by the
+      // first chunk, and counted with its projection)
+      if (a.psi32_fill)
+        hipLaunchKernelGGL(k_psi_f32, dim3((unsigned)std::min<size_t>((a.psi_elems / 2 + 255) / 256 + 1, 8192)),
+                           dim3(256), 0, s, (const double *)a.psi, const_cast<float *>(a.psi32), a.psi_elems);
+      ChunkArgs<T> a32 = a;
+      a32.psi = a.psi32;
+      launch_proj<T, float>(tb, a32, s);
+    } else {
+      launch_proj<T, Tin>(tb, a, s);
+    }
+  } else {
+    launch_proj<T, Tin>(tb, a, s);
+  }
   prof->end(s);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   {
