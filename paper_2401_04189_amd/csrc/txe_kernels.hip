@@ -916,8 +916,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
   const int wg_hi = min(g_hi, wg_lo + gw);
   const float *Gp = G + (size_t)p * RP * F;
   unsigned short *Gs = reinterpret_cast<unsigned short *>(smem_raw);   // [2][FRAG]
+  // Z slots with room for every padded row (as in k_core<float>)
+  constexpr int ZRS = 20, ZSS = RP * ZRS + 16;
   float *Zs = reinterpret_cast<float *>(smem_raw + 2 * FRAG * sizeof(unsigned short));
-  const int zsz = NW * gper * 16;
+  constexpr int zsz = NW * ZSS;
   constexpr int NTG = NW / 4;
   const int nkq = (D.K + NW - 1) / NW;
   const int nsteps = D.r0 * nkq;
@@ -1003,7 +1005,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
       const bool wrap = kq + 1 == nkq;
       if (step + 1 < nsteps) load_terms(wrap ? alpha + 1 : alpha, wrap ? 0 : kq + 1, nxt);
     }
-    float *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * gper * 16;
+    float *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * ZSS;
     if (k < D.K) {
       // ---- W[gamma][beta'] = sum_beta G[alpha][beta][gamma] Chat1_k[beta'][beta]
       const unsigned short *gl = Gs + (alpha & 1) * FRAG + lane * 8;
@@ -1046,11 +1048,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int gp = 16 * mtp + 4 * lg + v;
-          if (gp >= g_lo && gp < g_hi) Zw[(gp - g_lo) * 16 + lr] = Z[v];
+          Zw[gp * ZRS + lr] = Z[v];
         }
       }
     } else {
-      for (int idx = lane; idx < gper * 16; idx += 64) Zw[idx] = 0.f;
+      for (int idx = lane; idx < (g_hi - g_lo) * 16; idx += 64) Zw[(g_lo + (idx >> 4)) * ZRS + (idx & 15)] = 0.f;
     }
     // the next slab's chunk (split) before the barrier
     if (alpha + 1 < D.r0) {
@@ -1063,17 +1065,22 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
         }
     }
     __syncthreads();
-    // ---- phase B (FP32 MFMA): Phi += sum_{k in step} w_k Chat0_k[alpha'][alpha] Z_k
+    // ---- phase B (FP32 MFMA): Phi += sum_{k in step} w_k Chat0_k[alpha'][alpha] Z_k,
+    // all Z rows read before the first MFMA
+    {
+      const float *zb = Zs + (size_t)(step & 1) * zsz + lr;
+      float bz[NTG][NGW];
 #pragma unroll
-    for (int tg = 0; tg < NTG; ++tg) {
-      const float *zrow = Zs + (size_t)(step & 1) * zsz + (size_t)(4 * tg + lg) * gper * 16 + lr;
+      for (int tg = 0; tg < NTG; ++tg)
+#pragma unroll
+        for (int ng = 0; ng < NGW; ++ng) bz[tg][ng] = zb[(4 * tg + lg) * ZSS + min(wg_lo + ng, RP - 1) * ZRS];
 #pragma unroll
       for (int ng = 0; ng < NGW; ++ng) {
         if (NW == 8 && ng >= gw) break;
-        const int row = min(wg_lo - g_lo + ng, gper - 1);
-        const float bz = zrow[row * 16];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(cur.af[tg][mt], bz, Phi[mt][ng]);
+        for (int tg = 0; tg < NTG; ++tg)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(cur.af[tg][mt], bz[tg][ng], Phi[mt][ng]);
       }
     }
   };
@@ -1523,7 +1530,7 @@ hipError_t launch_core_bf2_mt(const Tables<float> &tb, const BfTables &bft, cons
   if ((gper + NW - 1) / NW > NGW) return hipErrorInvalidValue;
   constexpr int RP = 16 * MT, NC = (RP + 31) / 32;
   constexpr size_t frag = (size_t)NS * MT * NC * 512;
-  const size_t lds = 2 * frag * sizeof(unsigned short) + (2 * NW * (size_t)gper * 16) * sizeof(float);
+  const size_t lds = 2 * frag * sizeof(unsigned short) + (2 * NW * ((size_t)RP * 20 + 16)) * sizeof(float);
   const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
   if (lds > 64 * 1024) {
     const void *fn = want_vx ? (const void *)k_core_bf2<MT, NGW, NS, NW, true>
