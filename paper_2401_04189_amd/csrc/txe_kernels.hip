@@ -509,6 +509,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   constexpr bool C2S = F32 ? MT <= 3 : MT <= 2;
   constexpr bool HOLD_G = C2S && (NW == 4 || MT <= 2);
   constexpr bool LDS_G = F32 && !HOLD_G;
+  //   KM     term-major order (FP32 with Chat2 held): see below
+  constexpr bool KM = F32 && LDS_G && C2S;
   // slab gamma row (inside its tile) that this lane feeds to the W chain
   const int lrg = F32 ? ((lr & 3) << 2 | (lr >> 2)) : lr;
   constexpr int NKT = 4 * (MT - 1) + TL;  // K = 4 steps of the beta contraction
@@ -603,7 +605,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
 
   CF ca, cb2;
   T gf[GK][GM];  // held slab fragments
-  if constexpr (PF) load_terms(0, 0, ca);
+  if constexpr (PF && !KM) load_terms(0, 0, ca);
   const T *Ga = Gp + lrg;
   // LDS slab: the next slab arrives in (about) four chunks of EPT elements
   // per thread, chunk kq during step kq (loaded at the start of the step,
@@ -637,6 +639,126 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
     }
     __syncthreads();
   }
+  if constexpr (KM) {
+    // Term-major order: the outer loop walks the groups of NW terms, the
+    // inner loop the slabs alpha.  Each wavefront holds its term's Chat1 and
+    // Chat2 fragments in registers for all r0 slabs, and one whole slab
+    // streams through the LDS double buffer per step, so the term tables are
+    // read once per term group instead of once per (slab, term group).  The
+    // sums are the same as in slab-major order (phase B adds the same
+    // products to the same Phi accumulators, in another order).
+    constexpr int EPS = (int)((F + CHT - 1) / CHT);  // slab elements per thread and step
+    typedef T AF[NTG][MT];
+    auto load_af = [&](int alpha_, int kq_, AF &af) {
+#pragma unroll
+      for (int tg = 0; tg < NTG; ++tg) {
+        const T *ah = tb.Ahat + ((size_t)alpha_ * D.Kp + NW * kq_ + 4 * tg + lg) * RP + lr;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) af[tg][mt] = ah[16 * mt];
+      }
+    };
+    auto kslab_load = [&](int a_, T (&v)[EPS]) {
+#pragma unroll
+      for (int j = 0; j < EPS; ++j) v[j] = Gp[(size_t)a_ * F + min(j * CHT + tid, (int)F - 1)];
+    };
+    auto kslab_store = [&](int buf, const T (&v)[EPS]) {
+#pragma unroll
+      for (int j = 0; j < EPS; ++j) {
+        const int e = j * CHT + tid;
+        if (e < (int)F) {
+          const int gamma = e % RP;
+          const int gl16 = gamma & 15, ln = (gl16 & 3) << 2 | (gl16 >> 2);
+          Gs[buf * SLAB + (e / RP) * SROW + ln * LPL + (gamma >> 4)] = v[j];
+        }
+      }
+    };
+    T tcb[4 * MT];
+    T c2s[MT][MT][4];
+    AF afa, afb;
+    load_af(0, 0, afa);
+    auto kstep = [&](const int kq, const int alpha, const int step, AF &cur, AF &nxt) __attribute__((always_inline)) {
+      const int k = NW * kq + wave;
+      // the next step's slab (alpha + 1, or alpha 0 of the next term group)
+      // and phase-B columns, issued before this step's work
+      const bool last_a = alpha + 1 == D.r0;
+      const bool more = !last_a || kq + 1 < nkq;  // uniform
+      T gnext[EPS];
+      kslab_load(last_a ? 0 : alpha + 1, gnext);
+      if (more) load_af(last_a ? 0 : alpha + 1, last_a ? kq + 1 : kq, nxt);
+      T *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * ZSS;
+      if (k < D.K) {
+        acc W[MT];
+#pragma unroll
+        for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
+#pragma unroll
+        for (int kt = 0; kt < 4 * MT; ++kt) {
+          if (kt >= NKT) break;
+          const float4 f =
+              *reinterpret_cast<const float4 *>(Gs + (step & 1) * SLAB + (4 * kt + lg) * SROW + lr * LPL);
+          const T gl[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+          for (int mg = 0; mg < MT; ++mg) W[mg] = M::mma(gl[mg], tcb[kt], W[mg]);
+        }
+        acc Z[MT];
+#pragma unroll
+        for (int mtp = 0; mtp < MT; ++mtp) Z[mtp] = zero4<acc>();
+#pragma unroll
+        for (int mg = 0; mg < MT; ++mg)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            if (mg == MT - 1 && v >= TL) break;
+#pragma unroll
+            for (int mtp = 0; mtp < MT; ++mtp) Z[mtp] = M::mma(c2s[mtp][mg][v], W[mg][v], Z[mtp]);
+          }
+#pragma unroll
+        for (int mtp = 0; mtp < MT; ++mtp)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Zw[(16 * mtp + drow<T>(lg, v)) * ZRS + lr] = Z[mtp][v];
+      } else {
+        for (int idx = lane; idx < (g_hi - g_lo) * 16; idx += 64) Zw[(g_lo + (idx >> 4)) * ZRS + (idx & 15)] = (T)0;
+      }
+      if (more) kslab_store((step + 1) & 1, gnext);
+      __syncthreads();
+      const T *zb = Zs + (size_t)(step & 1) * zsz + lr;
+      T bz[NTG][NGW];
+#pragma unroll
+      for (int tg = 0; tg < NTG; ++tg)
+#pragma unroll
+        for (int ng = 0; ng < NGW; ++ng) bz[tg][ng] = zb[(4 * tg + lg) * ZSS + min(wg_lo + ng, RP - 1) * ZRS];
+#pragma unroll
+      for (int ng = 0; ng < NGW; ++ng) {
+        if (NW == 8 && ng >= gw) break;
+#pragma unroll
+        for (int tg = 0; tg < NTG; ++tg)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(cur[tg][mt], bz[tg][ng], Phi[mt][ng]);
+      }
+    };
+    int step = 0;
+    for (int kq = 0; kq < nkq; ++kq) {
+      const int k = NW * kq + wave;
+      if (k < D.K) {
+        load_c1(k, tcb);
+#pragma unroll
+        for (int mtp = 0; mtp < MT; ++mtp)
+#pragma unroll
+          for (int mg = 0; mg < MT; ++mg) load_c2(k, mtp, mg, c2s[mtp][mg]);
+      }
+      int alpha = 0;
+      for (; alpha + 1 < D.r0; alpha += 2, step += 2) {
+        kstep(kq, alpha, step, afa, afb);
+        kstep(kq, alpha + 1, step + 1, afb, afa);
+      }
+      if (alpha < D.r0) {  // odd r0: the tail step leaves the next columns in afb
+        kstep(kq, alpha, step, afa, afb);
+        ++step;
+#pragma unroll
+        for (int tg = 0; tg < NTG; ++tg)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) afa[tg][mt] = afb[tg][mt];
+      }
+    }
+  } else {
   // one step: uses cur, prefetches the next step's operands into nxt
   auto step_body = [&](const int step, CF &cur, CF &nxt) __attribute__((always_inline)) {
     const int alpha = step / nkq;
@@ -831,6 +953,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
     }
   }
   for (; step < nsteps; ++step) step_body(step, ca, cb2);
+  }
 
   core_epilogue<T, MT, NGW, NW, WRITE_S1>(Phi, Gp, D, p, bt, gs, NGS, wg_lo, wg_hi, lane, lr, lg, wave, tb, S1,
                                           epart);
