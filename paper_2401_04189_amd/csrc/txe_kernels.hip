@@ -1116,6 +1116,138 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
       for (int c = 0; c < NC; ++c) f.cb[c][sp] = ld_bf8(c1 + ((size_t)sp * NC + c) * 512);
   };
 
+  // eight wavefronts (two-part splits): term-major order as in the FP32 core,
+  // the term's split Chat1/Chat2 fragments held for all slabs
+  constexpr bool KM = NW == 8;
+  if constexpr (KM) {
+    constexpr int EPS = (int)((F + CHT - 1) / CHT);  // slab elements per thread and step
+    typedef float AF[NTG][MT];
+    auto load_af = [&](int alpha_, int kq_, AF &af) {
+#pragma unroll
+      for (int tg = 0; tg < NTG; ++tg) {
+        const float *ah = tb.Ahat + ((size_t)alpha_ * D.Kp + NW * kq_ + 4 * tg + lg) * RP + lr;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) af[tg][mt] = ah[16 * mt];
+      }
+    };
+    auto kslab_load = [&](int a_, float (&v)[EPS]) {
+#pragma unroll
+      for (int j = 0; j < EPS; ++j) v[j] = Gp[(size_t)a_ * F + min(j * CHT + tid, (int)F - 1)];
+    };
+    auto kslab_store = [&](int buf, const float (&v)[EPS]) {
+#pragma unroll
+      for (int j = 0; j < EPS; ++j) {
+        const int e = j * CHT + tid;
+        if (e < (int)F) {
+          const int beta = e / RP, gamma = e % RP;
+          const int ln = ((beta >> 3) & 3) * 16 + (gamma & 15);
+          const int base = ((((gamma >> 4) * NC + (beta >> 5)) * 64 + ln) * 8) + (beta & 7);
+          float r = v[j];
+#pragma unroll
+          for (int sp = 0; sp < NS; ++sp) {
+            const __bf16 h = (__bf16)r;
+            Gs[buf * FRAG + sp * (MT * NC * 512) + base] = __builtin_bit_cast(unsigned short, h);
+            if (sp + 1 < NS) r -= (float)h;
+          }
+        }
+      }
+    };
+    bf8 hcb[NC][NS];
+    bf8 hc2[MT][NC][NS];
+    AF afa, afb;
+    load_af(0, 0, afa);
+    auto kstep = [&](const int kq, const int alpha, const int step, AF &cur, AF &nxt) __attribute__((always_inline)) {
+      const int k = NW * kq + wave;
+      const bool last_a = alpha + 1 == D.r0;
+      const bool more = !last_a || kq + 1 < nkq;  // uniform
+      float gnext[EPS];
+      kslab_load(last_a ? 0 : alpha + 1, gnext);
+      if (more) load_af(last_a ? 0 : alpha + 1, last_a ? kq + 1 : kq, nxt);
+      float *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * ZSS;
+      if (k < D.K) {
+        const unsigned short *gl = Gs + (step & 1) * FRAG + lane * 8;
+        acc W[MT];
+#pragma unroll
+        for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int mg = 0; mg < MT; ++mg) {
+            bf8 g[NS];
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) g[sp] = ld_bf8(gl + ((sp * MT + mg) * NC + c) * 512);
+            W[mg] = mma_split<NS>(g, hcb[c], W[mg]);
+          }
+        bf8 wsp[NC][NS];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          float x[8];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            x[i] = W[2 * c][i];
+            x[4 + i] = (2 * c + 1 < MT) ? W[(2 * c + 1 < MT) ? 2 * c + 1 : 0][i] : 0.f;
+          }
+          split8<NS>(x, wsp[c]);
+        }
+#pragma unroll
+        for (int mtp = 0; mtp < MT; ++mtp) {
+          if (16 * mtp >= g_hi || 16 * mtp + 16 <= g_lo) continue;  // uniform: tile outside the split
+          acc Z = zero4<acc>();
+#pragma unroll
+          for (int c = 0; c < NC; ++c) Z = mma_split<NS>(hc2[mtp][c], wsp[c], Z);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Zw[(16 * mtp + 4 * lg + v) * ZRS + lr] = Z[v];
+        }
+      } else {
+        for (int idx = lane; idx < (g_hi - g_lo) * 16; idx += 64) Zw[(g_lo + (idx >> 4)) * ZRS + (idx & 15)] = 0.f;
+      }
+      if (more) kslab_store((step + 1) & 1, gnext);
+      __syncthreads();
+      const float *zb = Zs + (size_t)(step & 1) * zsz + lr;
+      float bz[NTG][NGW];
+#pragma unroll
+      for (int tg = 0; tg < NTG; ++tg)
+#pragma unroll
+        for (int ng = 0; ng < NGW; ++ng) bz[tg][ng] = zb[(4 * tg + lg) * ZSS + min(wg_lo + ng, RP - 1) * ZRS];
+#pragma unroll
+      for (int ng = 0; ng < NGW; ++ng) {
+        if (ng >= gw) break;
+#pragma unroll
+        for (int tg = 0; tg < NTG; ++tg)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(cur[tg][mt], bz[tg][ng], Phi[mt][ng]);
+      }
+    };
+    int step = 0;
+    for (int kq = 0; kq < nkq; ++kq) {
+      const int k = NW * kq + wave;
+      if (k < D.K) {
+        const unsigned short *c1 = bft.C1 + (((size_t)k * MT + bt) * 3) * NC * 512 + lane * 8;
+        const unsigned short *c2 = bft.C2 + (size_t)k * 3 * MT * NC * 512 + lane * 8;
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            hcb[c][sp] = ld_bf8(c1 + ((size_t)sp * NC + c) * 512);
+#pragma unroll
+            for (int mtp = 0; mtp < MT; ++mtp) hc2[mtp][c][sp] = ld_bf8(c2 + (((size_t)sp * MT + mtp) * NC + c) * 512);
+          }
+      }
+      int alpha = 0;
+      for (; alpha + 1 < D.r0; alpha += 2, step += 2) {
+        kstep(kq, alpha, step, afa, afb);
+        kstep(kq, alpha + 1, step + 1, afb, afa);
+      }
+      if (alpha < D.r0) {  // odd r0: the tail step leaves the next columns in afb
+        kstep(kq, alpha, step, afa, afb);
+        ++step;
+#pragma unroll
+        for (int tg = 0; tg < NTG; ++tg)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) afa[tg][mt] = afb[tg][mt];
+      }
+    }
+  } else {
   CF ca, cb2;
   load_terms(0, 0, ca);
   auto step_body = [&](const int step, CF &cur, CF &nxt) __attribute__((always_inline)) {
@@ -1213,6 +1345,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
     step_body(step + 1, cb2, ca);
   }
   for (; step < nsteps; ++step) step_body(step, ca, cb2);
+  }
   core_epilogue<float, MT, NGW, NW, WRITE_S1>(Phi, Gp, D, p, bt, gs, NGS, wg_lo, wg_hi, lane, lr, lg, wave, tb, S1,
                                               epart);
 }
