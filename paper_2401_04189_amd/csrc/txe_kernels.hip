@@ -507,7 +507,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   constexpr bool F32 = sizeof(T) == 4;
   constexpr bool PF = F32 || MT <= 2;
   constexpr bool C2S = F32 ? MT <= 3 : MT <= 2;
-  constexpr bool HOLD_G = C2S && (NW == 4 || MT <= 2);
+  constexpr bool HOLD_G = !F32 && C2S && (NW == 4 || MT <= 2);
   constexpr bool LDS_G = F32 && !HOLD_G;
   //   KM     term-major order (FP32 with Chat2 held): see below
   constexpr bool KM = F32 && LDS_G && C2S;
@@ -1716,7 +1716,7 @@ hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_
   const int gper = (a.D.r2 + a.NGS - 1) / a.NGS;
   if ((gper + NW - 1) / NW > NGW) return hipErrorInvalidValue;  // the plan gives every wavefront <= NGW rows
   constexpr int RP = 16 * MT;
-  constexpr bool lds_g = sizeof(T) == 4 && MT >= 3;  // the slab-in-LDS forms of k_core
+  constexpr bool lds_g = sizeof(T) == 4;  // the slab-in-LDS forms of k_core (every FP32 one)
   constexpr size_t slab = lds_g ? (size_t)RP * 16 * (MT <= 4 ? 4 : 8) : 0;
   const size_t zslot = sizeof(T) == 4 ? (size_t)RP * 20 + 16 : (size_t)gper * 16;  // k_core's Z slot
   const size_t lds = (2 * slab + 2 * NW * zslot) * sizeof(T);
