@@ -446,9 +446,11 @@ __device__ __forceinline__ void core_epilogue(typename MF<T>::acc (&Phi)[MT][NGW
 
 // -------------------------------------------------------------------------------------
 // core: per workgroup one pair p, one 16-wide tile bt of beta' and a range of
-// gamma' (split gs of NGS).  Input slabs alpha form the outer loop; the
-// slab's MFMA fragments stay in registers while the four wavefronts walk the
-// Gaussian terms four at a time (wavefront w takes term k = 4*kq + w):
+// gamma' (split gs of NGS).  A step pairs one input slab alpha with one group
+// of NW Gaussian terms (wavefront w takes term k = NW*kq + w).  Slab-major
+// order (slabs outer, term groups inner) or, where the term fragments fit in
+// registers, term-major order (term groups outer, whole slabs streamed
+// through LDS); per step:
 //   phase A
 //     W[gamma][beta']  = sum_beta G[alpha][beta][gamma] Chat1_k[beta'][beta]
 //     Z[gamma'][beta'] = sum_gamma Chat2_k[gamma'][gamma] W[gamma][beta']   (chained)
