@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void k_proj12m(const Tin *__restrict__ psi, Di
 // proj3: G[p][alpha][f] = sum_a V0[a][alpha] T2[p][a][f], f = (beta, gamma)
 // one wavefront per (pair, group of FT f-tiles)
 // -------------------------------------------------------------------------------------
-template <typename T, int FT>
+template <typename T, int FT, int MT>
 __global__ __launch_bounds__(256) void k_proj3(const T *__restrict__ T2, Dims D, int P, Tables<T> tb,
                                                T *__restrict__ G) {
   using M = MF<T>;
@@ -332,37 +332,40 @@ __global__ __launch_bounds__(256) void k_proj3(const T *__restrict__ T2, Dims D,
   const int f0 = fgi * FT;
   const size_t F = (size_t)D.rp1 * D.rp2;
   const T *B = T2 + (size_t)p * D.n0 * F;
-
-  acc C[MAX_MT][FT];
+  // column tiles past the last one read (clamped) tile NF-1 and are not stored
+  int fc[FT];
 #pragma unroll
-  for (int mt = 0; mt < MAX_MT; ++mt)
+  for (int ft = 0; ft < FT; ++ft) fc[ft] = 16 * min(f0 + ft, NF - 1) + lr;
+
+  acc C[MT][FT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft) C[mt][ft] = zero4<acc>();
 
+  // the a loop unrolled by four: the loads of four K = 4 steps are in
+  // flight together
+#pragma unroll 4
   for (int ka = 0; ka < (D.n0 >> 2); ++ka) {
     const int arow = 4 * ka + lg;
     T bf[FT];
 #pragma unroll
-    for (int ft = 0; ft < FT; ++ft) bf[ft] = (f0 + ft < NF) ? B[(size_t)arow * F + 16 * (f0 + ft) + lr] : (T)0;
+    for (int ft = 0; ft < FT; ++ft) bf[ft] = B[(size_t)arow * F + fc[ft]];
 #pragma unroll
-    for (int mt = 0; mt < MAX_MT; ++mt) {
-      if (mt < D.MT0) {
-        const T af = tb.V0K[(size_t)arow * D.rp0 + 16 * mt + lr];
+    for (int mt = 0; mt < MT; ++mt) {
+      const T af = tb.V0K[(size_t)arow * D.rp0 + 16 * mt + lr];
 #pragma unroll
-        for (int ft = 0; ft < FT; ++ft) C[mt][ft] = M::mma(af, bf[ft], C[mt][ft]);
-      }
+      for (int ft = 0; ft < FT; ++ft) C[mt][ft] = M::mma(af, bf[ft], C[mt][ft]);
     }
   }
   T *out = G + (size_t)p * D.rp0 * F;
 #pragma unroll
-  for (int mt = 0; mt < MAX_MT; ++mt) {
-    if (mt < D.MT0) {
+  for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
-      for (int ft = 0; ft < FT; ++ft) {
-        if (f0 + ft < NF) {
+    for (int ft = 0; ft < FT; ++ft) {
+      if (f0 + ft < NF) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) out[(size_t)(16 * mt + drow<T>(lg, v)) * F + 16 * (f0 + ft) + lr] = C[mt][ft][v];
-        }
+        for (int v = 0; v < 4; ++v) out[(size_t)(16 * mt + drow<T>(lg, v)) * F + 16 * (f0 + ft) + lr] = C[mt][ft][v];
       }
     }
   }
@@ -2018,8 +2021,14 @@ hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx,
     const int NF = (a.D.rp1 * a.D.rp2) >> 4;
     const int nfg = (NF + FT - 1) / FT;
     prof->begin(K_PROJ3, s);
-    hipLaunchKernelGGL((k_proj3<T, FT>), dim3(blocks_for((long long)a.P * nfg)), dim3(256), 0, s, a.T2, a.D, a.P,
-                       tb, a.G);
+    const dim3 g3(blocks_for((long long)a.P * nfg));
+    switch (a.D.MT0) {
+      case 1: hipLaunchKernelGGL((k_proj3<T, FT, 1>), g3, dim3(256), 0, s, a.T2, a.D, a.P, tb, a.G); break;
+      case 2: hipLaunchKernelGGL((k_proj3<T, FT, 2>), g3, dim3(256), 0, s, a.T2, a.D, a.P, tb, a.G); break;
+      case 3: hipLaunchKernelGGL((k_proj3<T, FT, 3>), g3, dim3(256), 0, s, a.T2, a.D, a.P, tb, a.G); break;
+      case 4: hipLaunchKernelGGL((k_proj3<T, FT, 4>), g3, dim3(256), 0, s, a.T2, a.D, a.P, tb, a.G); break;
+      default: hipLaunchKernelGGL((k_proj3<T, FT, 5>), g3, dim3(256), 0, s, a.T2, a.D, a.P, tb, a.G); break;
+    }
     prof->end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
