@@ -1873,9 +1873,9 @@ hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStrea
   const int lds_tab = tab <= 64 * 1024 ? 1 : 0;
   const unsigned nbl = lds_tab ? std::min(nb, (unsigned)a.grid_cap) : nb;
   const size_t lds = lds_tab ? tab : 0;
-  // FP64: all b tiles in one launch.  FP32: at most four b tiles per launch
-  // (registers); more take several launches over disjoint b ranges, each
-  // recomputing X for its sources (measured faster at 80^3)
+  // all b tiles in one launch up to six tiles (X computed once per source);
+  // FP64 up to eight.  FP32 beyond six: launches over disjoint ranges of
+  // four b tiles, each recomputing X for its sources (registers)
   if (nbt > 8) return hipErrorInvalidValue;
 #define TXE_BACK(NBTV, MB0)                                                                                      \
   do {                                                                                                           \
@@ -1892,9 +1892,10 @@ hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStrea
     TXE_BACK(2, 0);
   } else if (nbt <= 4) {
     TXE_BACK(4, 0);
+  } else if (nbt <= 6) {
+    TXE_BACK(6, 0);
   } else if constexpr (sizeof(T) == 8) {
-    if (nbt <= 6) TXE_BACK(6, 0);
-    else TXE_BACK(8, 0);
+    TXE_BACK(8, 0);
   } else {
     for (int mb0 = 0; mb0 < nbt; mb0 += 4) TXE_BACK(4, mb0);
   }
