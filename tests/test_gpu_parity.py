@@ -130,8 +130,9 @@ def test_f32_rank_tiles_against_f64(ctx):
 
 
 # per-mode ranks: the tile count follows the largest rank, the live chunks
-# of the last tile follow modes 1 and 2 (one, three and four of four live)
-ANISO = ((40, 20, 20), (20, 36, 44), (44, 44, 18), (18, 30, 48))
+# of the last tile follow modes 1 and 2 (one, three and four of four live);
+# odd r0 gives the term-major cores an odd number of slab steps per group
+ANISO = ((40, 20, 20), (20, 36, 44), (44, 44, 18), (18, 30, 48), (33, 40, 40), (21, 24, 24))
 
 
 def test_f64_anisotropic_ranks(ctx):
@@ -149,6 +150,11 @@ def test_f32_anisotropic_ranks_against_f64(ctx):
         perr = np.abs(p32 - p64).max() / np.abs(p64).max()
         print(f"[f32 r={r}] |dE_x| {abs(e32 - e64):.3e} Ha  e_ij rel {perr:.3e}  Vx rel {verr:.3e}", flush=True)
         assert abs(e32 - e64) <= 1e-5 and perr <= 1e-5 and verr <= 1e-5
+        vb, eb, pb = run_gpu(ctx, s, "bf16x3")
+        verr = rel_vx_err(vb, v64, s.grid.q)
+        perr = np.abs(pb - p64).max() / np.abs(p64).max()
+        print(f"[bf16x3 r={r}] |dE_x| {abs(eb - e64):.3e} Ha  e_ij rel {perr:.3e}  Vx rel {verr:.3e}", flush=True)
+        assert abs(eb - e64) <= 2e-4 * abs(e64) and perr <= 2e-4 and verr <= 2e-4
 
 
 @pytest.mark.parametrize("form,tol", [("bf16x6", 1e-5), ("bf16x3", 2e-4)])
