@@ -507,8 +507,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   //   C2S    Chat2 fragments loaded whole at the start of the step (else one
   //          gamma' tile at a time inside the Z chain)
   //   HOLD_G the slab's A fragments held in registers for all of its steps
-  //   LDS_G  the slab in LDS instead (double-buffered, row stride padded so
-  //          the four lane groups of a fragment load hit different banks)
+  //          (FP64 at up to two tiles)
+  //   LDS_G  the slab in LDS instead (double-buffered; every FP32 form),
+  //          each row laid out so a lane reads its fragments with one load
   constexpr bool F32 = sizeof(T) == 4;
   constexpr bool PF = F32 || MT <= 2;
   constexpr bool C2S = F32 ? MT <= 3 : MT <= 2;
