@@ -653,7 +653,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
     // read once per term group instead of once per (slab, term group).  The
     // sums are the same as in slab-major order (phase B adds the same
     // products to the same Phi accumulators, in another order).
-    constexpr int EPS = (int)((F + CHT - 1) / CHT);  // slab elements per thread and step
+    // the next slab in 16-byte pieces (RP is a multiple of 16, so a piece
+    // stays inside one beta row): EPS pieces per thread and step
+    constexpr int F4 = (int)(F / 4);
+    constexpr int EPS = (F4 + CHT - 1) / CHT;
     typedef T AF[NTG][MT];
     auto load_af = [&](int alpha_, int kq_, AF &af) {
 #pragma unroll
@@ -663,18 +666,24 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
         for (int mt = 0; mt < MT; ++mt) af[tg][mt] = ah[16 * mt];
       }
     };
-    auto kslab_load = [&](int a_, T (&v)[EPS]) {
+    auto kslab_load = [&](int a_, float4 (&v)[EPS]) {
+      const float4 *src = reinterpret_cast<const float4 *>(Gp + (size_t)a_ * F);
 #pragma unroll
-      for (int j = 0; j < EPS; ++j) v[j] = Gp[(size_t)a_ * F + min(j * CHT + tid, (int)F - 1)];
+      for (int j = 0; j < EPS; ++j) v[j] = src[min(j * CHT + tid, F4 - 1)];
     };
-    auto kslab_store = [&](int buf, const T (&v)[EPS]) {
+    auto kslab_store = [&](int buf, const float4 (&v)[EPS]) {
 #pragma unroll
       for (int j = 0; j < EPS; ++j) {
-        const int e = j * CHT + tid;
-        if (e < (int)F) {
-          const int gamma = e % RP;
-          const int gl16 = gamma & 15, ln = (gl16 & 3) << 2 | (gl16 >> 2);
-          Gs[buf * SLAB + (e / RP) * SROW + ln * LPL + (gamma >> 4)] = v[j];
+        const int e4 = j * CHT + tid;
+        if (e4 < F4) {
+          const int beta = (4 * e4) / RP, g0 = (4 * e4) % RP;
+          const float x[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int gamma = g0 + q;
+            const int gl16 = gamma & 15, ln = (gl16 & 3) << 2 | (gl16 >> 2);
+            Gs[buf * SLAB + beta * SROW + ln * LPL + (gamma >> 4)] = x[q];
+          }
         }
       }
     };
@@ -688,7 +697,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
       // and phase-B columns, issued before this step's work
       const bool last_a = alpha + 1 == D.r0;
       const bool more = !last_a || kq + 1 < nkq;  // uniform
-      T gnext[EPS];
+      float4 gnext[EPS];
       kslab_load(last_a ? 0 : alpha + 1, gnext);
       if (more) load_af(last_a ? 0 : alpha + 1, last_a ? kq + 1 : kq, nxt);
       T *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * ZSS;
