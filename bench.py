@@ -1,19 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the Tucker-tensor Fock-exchange hot path on one MI355X.
 
-One step = one exchange apply (pair densities, projection onto the shared
-Tucker bases, core-space Gaussian kernel sum, back-projection, product with
-psi_j and sum over sources, E_x) over the whole 64^3 / 64-orbital workload
-(2080 unique pairs, r = 40, K = 40), inputs resident in HBM.  The metric is
-pair convolutions per second for the FP32-MFMA form, counted only when its
-E_x is within 1e-5 Ha of the FP64 form, which is timed beside it.
+Default workload: the 128^3 block (1,842 orbitals from Gaussians on 310
+rutile sites, r = 80, K = 50).  One step = one exchange apply (pair
+densities, projection onto the shared Tucker bases, core-space Gaussian
+kernel sum, back-projection, product with psi_j and sum over sources, pair
+energies, E_x) for the next batch of 4 targets of the 128-target block
+against all 1,842 sources (7,368 pairs), inputs resident in HBM.  The metric
+is pair convolutions per second of the FP32-MFMA form, counted only when its
+batch energies are within 1e-5 Ha of the FP64 form's, which is timed beside
+it together with the split-bf16 forms.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg4]
 
-`--config cfg5` times the batched workload instead: 24 uneven systems
-(grids 48^3..96^3, 10..120 orbitals, r = 24..64, K = 40) as one captured
-graph replay against 24 separate applies, FP32 MFMA, with every system's
-E_x checked against its FP64 form.
+`--config cfg2` / `cfg3` time the symmetric 64^3 / 80^3 workloads (all unique
+pairs per step); `--config cfg5` times 24 uneven systems as one captured
+graph replay against 24 separate applies, FP32 MFMA, with every system's E_x
+checked against its FP64 form.
 
 Prints one JSON line.  Per-kernel durations come from HIP events the library
 records on its own stream around every launch (txe_profile_*).
@@ -31,8 +34,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pair convolutions/s for Vx psi, MFMA-FP32 vs FP64 at dE_x<=1e-5 Ha; % roofline"
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
-KERNEL_SRC = os.path.join(ROOT, "paper_2401_04189_amd", "csrc", "txe_kernels.hip")
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.0}
+CSRC = os.path.join(ROOT, "paper_2401_04189_amd", "csrc")
+# the sources the core kernel is compiled from (the traffic counters are tied to them)
+KERNEL_SRC = [os.path.join(CSRC, f) for f in ("txe_core.h", "txe_dev.h", "txe_core_f32.hip", "txe_core_f64.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_core.json")
 TUNE_CACHE = os.path.join(ROOT, "paper_2401_04189_amd", "tuned_shapes.json")
 
@@ -57,7 +62,10 @@ def core_kernel_flops_per_pair(n, r, K):
 
 
 def source_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(compute, cfg):
@@ -86,15 +94,18 @@ def time_leg(txe, torch, ctx, sysm, psi, vx, compute, steps, warmup, symmetric, 
     return wall, float(ex.item()), kt
 
 
-def shapes(args, txe, ctx, sysm, psi, compute):
+def shapes(args, txe, ctx, sysm, psi, compute, symmetric=True, i0=0, Ni=None):
     """Launch shapes for one leg: the committed tuning cache, else a live
-    search before the timed region (saved with --retune)."""
+    search before the timed region (saved with --retune), else (--no-tune, or
+    the block workload without --retune) the defaults."""
     if args.no_tune:
         return "defaults"
-    kn, tuned = txe.plan(ctx, sysm, psi, compute)
+    kn, tuned = txe.plan(ctx, sysm, psi, compute, symmetric, i0, Ni)
     if tuned and not args.retune:
         return {"source": "cache", **kn}
-    ms, kn = txe.tune(ctx, sysm, psi, compute, reps=2)
+    if not symmetric and not args.retune:
+        return {"source": "defaults", **kn}
+    ms, kn = txe.tune(ctx, sysm, psi, compute, symmetric, i0, Ni, reps=1 if not symmetric else 2)
     return {"source": "tuned live", **kn}
 
 
@@ -104,73 +115,160 @@ def load_cache(args, txe, ctx):
         txe.tune_load(ctx, TUNE_CACHE)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def block_cpu_baseline(s, seconds, single_seconds):
+    """The CPU FP64 oracle, as it stands, on target 0 of the 128^3 block against
+    its sources in order, until `seconds` of work are done (all host cores as
+    BLAS threads), then a single-thread rate on the next sources."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import txe_oracle as O
+
+    t0 = time.perf_counter()
+    st = O.Setup(s.grid.x, s.grid.q, s.U, s.w, s.alpha)
+    setup_s = time.perf_counter() - t0
+    pi = s.psi[0].double().cpu().numpy()
+
+    def run(j0, budget):
+        done = 0
+        t = time.perf_counter()
+        while time.perf_counter() - t < budget and j0 + done < s.N:
+            O.pair(pi, s.psi[j0 + done].double().cpu().numpy(), st)
+            done += 1
+        return done, time.perf_counter() - t
+
+    done, el = run(0, seconds)
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    with threadpool_limits(limits=1):
+        done1, el1 = run(done, single_seconds)
+    return {"value": round(done / el, 3), "unit": "pair-convolutions/s", "cores": int(threads), "kind": "oracle",
+            "single_thread_value": round(done1 / el1, 3), "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"target 0 of the 128^3 block against its first {done} sources (numpy FP64, {el:.1f} s, "
+                      f"{threads} BLAS threads), then sources {done}..{done + done1 - 1} on one thread "
+                      f"({el1:.1f} s); setup tables {setup_s:.1f} s, not timed"}
+
+
 def bench_block(args, txe, torch, W):
-    """cfg4: a block of targets against all 1,842 sources at 128^3, r = 80,
-    K = 50, in FP64, FP32 MFMA and split-bf16; errors of each reduced form
-    against FP64 per result (block energy, Vx psi per orbital in the W-norm,
-    exchange-matrix diagonal <psi_i, Vx psi_i>_W)."""
+    """The 128^3 block (default): batches of `--batch` targets of the 128-target
+    block against all 1,842 sources, r = 80, K = 50.  One step = one batch
+    (the next one each step).  FP32 MFMA (the value) is timed for exactly
+    --steps steps after --warmup batches; FP64, bf16 x3 and bf16 x6 are timed
+    beside it on the first --side-steps batches.  Every reduced form is
+    compared with FP64 on the batches both timed (|dE_batch|) and on batch 0
+    (Vx psi per orbital in the W-norm, exchange-matrix diagonal from the
+    library)."""
     t0 = time.perf_counter()
     s = W.build_config("cfg4", device="cuda")
     torch.cuda.empty_cache()
-    print(f"generated cfg4 in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    print(f"generated the 128^3 block workload in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ctx = txe.Context(0)
     sysm = txe.System.from_workload(ctx, s)
     load_cache(args, txe, ctx)
     psi = s.psi
-    N, Ni = s.N, args.targets
-    npairs = Ni * N
+    N, B = s.N, args.batch
+    nbatch = 128 // B
+    npairs = B * N
     w3 = s.grid.weights3d(device="cuda")
-    legs = {}
-    for comp in ("f64", "f32", "bf16x3", "bf16x6"):
-        vx = torch.empty((Ni,) + tuple(psi.shape[1:]), dtype=psi.dtype, device="cuda")
-        for _ in range(max(args.warmup, 1)):
-            txe.apply(ctx, sysm, psi, compute=comp, symmetric=False, i0=0, Ni=Ni, vx_out=vx)
+    vx = torch.empty((B,) + tuple(psi.shape[1:]), dtype=psi.dtype, device="cuda")
+    n, r, K = s.grid.n, s.r, s.K
+    legs, ref_batch0 = {}, {}
+    for comp in args.legs.split(","):
+        main = comp == "f32"
+        steps = args.steps if main else max(1, min(args.steps, args.side_steps))
+        warm = args.warmup if main else 1
+        tuned = shapes(args, txe, ctx, sysm, psi, comp, symmetric=False, i0=0, Ni=B)
+        for w in range(warm):
+            txe.apply(ctx, sysm, psi, compute=comp, symmetric=False, i0=(w % nbatch) * B, Ni=B, vx_out=vx)
         torch.cuda.synchronize()
-        print(f"{comp}: warm-up done", file=sys.stderr, flush=True)
+        print(f"{comp}: {warm} warm-up batches done", file=sys.stderr, flush=True)
         ctx.profile(True)
+        exs = []
         t = time.perf_counter()
-        steps = max(1, min(args.steps, 3))
-        for it in range(steps):
-            _, ex, _ = txe.apply(ctx, sysm, psi, compute=comp, symmetric=False, i0=0, Ni=Ni, vx_out=vx)
-            torch.cuda.synchronize()
-            print(f"{comp}: step {it} done", file=sys.stderr, flush=True)
+        for k in range(steps):
+            exs.append(txe.apply(ctx, sysm, psi, compute=comp, symmetric=False, i0=(k % nbatch) * B, Ni=B,
+                                 vx_out=vx)[1])
+            if k % 5 == 4 or k == steps - 1:
+                print(f"{comp}: step {k + 1}/{steps} enqueued", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
         sec = (time.perf_counter() - t) / steps
         kt = ctx.kernel_times()
         ctx.profile(False)
-        diag = (psi[:Ni] * vx * w3).sum(dim=(1, 2, 3))
-        legs[comp] = dict(sec=sec, ex=float(ex), vx=vx, diag=diag, kt=kt, steps=steps)
-        print(f"{comp}: {sec * 1e3:.1f} ms", file=sys.stderr, flush=True)
-    ref = legs["f64"]
+        # batch 0 once more, untimed, for the per-orbital comparisons
+        v0, e0, _, d0 = txe.apply(ctx, sysm, psi, compute=comp, symmetric=False, i0=0, Ni=B, want_orb=True)
+        torch.cuda.synchronize()
+        ref_batch0[comp] = (v0, float(e0), d0)
+        legs[comp] = dict(sec=sec, steps=steps, warmup=warm, ex=[float(e) for e in exs], kt=kt, shapes=tuned)
+        print(f"{comp}: {1e3 * sec:.1f} ms per batch", file=sys.stderr, flush=True)
+    peak = {"f64": PEAK_TFLOPS["f64"], "f32": PEAK_TFLOPS["f32"], "bf16x3": PEAK_TFLOPS["bf16"] / 3,
+            "bf16x6": PEAK_TFLOPS["bf16"] / 6}
+    core_fl = core_kernel_flops_per_pair(n, r, K)
     out_legs = {}
     for comp, L in legs.items():
-        e = {"value": round(npairs / L["sec"], 1), "ms_per_step": round(1e3 * L["sec"], 3), "E_block": L["ex"],
-             "core_ms_per_step": round(L["kt"]["core"][0] / L["steps"], 3),
-             "core_launches_per_step": L["kt"]["core"][1] // L["steps"]}
-        if comp != "f64":
-            num = ((L["vx"] - ref["vx"]) ** 2 * w3).sum(dim=(1, 2, 3))
-            den = (ref["vx"] ** 2 * w3).sum(dim=(1, 2, 3))
-            e["dE_block_Ha"] = abs(L["ex"] - ref["ex"])
+        core_ms, core_n = L["kt"]["core"]
+        launches = max(core_n, 1)
+        launch_ms = core_ms / launches
+        achieved = core_fl * npairs * L["steps"] / (core_ms * 1e-3) / 1e12
+        e = {"value": round(npairs / L["sec"], 1), "ms_per_step": round(1e3 * L["sec"], 3), "steps": L["steps"],
+             "warmup": L["warmup"], "E_batch0": L["ex"][0],
+             "kernel_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in L["kt"].items()},
+             "launches_per_step": {k: v[1] // L["steps"] for k, v in L["kt"].items()},
+             "core_tflops": round(achieved, 3), "core_peak_tflops": round(peak[comp], 1),
+             "core_frac": round(achieved / peak[comp], 4), "core_launch_ms": round(launch_ms, 3),
+             "launch_shapes": L["shapes"]}
+        if comp != "f64" and "f64" in legs:
+            both = min(len(L["ex"]), len(legs["f64"]["ex"]))
+            v0, e0, d0 = ref_batch0[comp]
+            v64, e64, d64 = ref_batch0["f64"]
+            num = ((v0 - v64) ** 2 * w3).sum(dim=(1, 2, 3))
+            den = (v64 ** 2 * w3).sum(dim=(1, 2, 3))
+            e["dE_batch_Ha_max"] = max(abs(a - b) for a, b in zip(L["ex"][:both], legs["f64"]["ex"][:both]))
+            e["batches_compared"] = both
             e["vx_rel_wnorm_max"] = float(torch.sqrt(num / den).max())
-            e["diag_abs_max_Ha"] = float((L["diag"] - ref["diag"]).abs().max())
-            e["over_fp64"] = round(ref["sec"] / L["sec"], 3)
+            e["diag_abs_max_Ha"] = float((d0 - d64).abs().max())
+            e["within_1e-5_Ha"] = e["dE_batch_Ha_max"] <= 1e-5
+            e["over_fp64"] = round(legs["f64"]["sec"] / L["sec"], 3)
         out_legs[comp] = e
-    use = "f32" if out_legs["f32"]["dE_block_Ha"] <= 1e-5 else "f64"
-    core_ms = out_legs[use]["core_ms_per_step"]  # all launches of one step (the block is chunked)
-    achieved = core_kernel_flops_per_pair(s.grid.n, s.r, s.K) * npairs / (core_ms * 1e-3) / 1e12
+    use = "f32" if out_legs.get("f32", {}).get("within_1e-5_Ha") else "f64"
+    U = out_legs[use]
+    roof = {"bound": "mfma", "kernel": "core", "achieved": U["core_tflops"], "peak": PEAK_TFLOPS[use],
+            "unit": "TFLOP/s", "frac": round(U["core_tflops"] / PEAK_TFLOPS[use], 4),
+            "traffic": load_traffic(use, "cfg4"), "launch_ms": U["core_launch_ms"],
+            "flops_per_launch": core_fl * npairs / max(U["launches_per_step"]["core"], 1)}
+    measured = ctx.ceiling(use)
+    roof["measured_peak"] = round(measured, 1)
+    roof["frac_of_measured"] = round(U["core_tflops"] / measured, 4)
     out = {
-        "metric": METRIC, "value": out_legs[use]["value"], "unit": "pair-convolutions/s",
-        "n_gpus": 1, "steps": legs[use]["steps"], "warmup": args.warmup,
-        "ms_per_step": out_legs[use]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": U["value"], "unit": "pair-convolutions/s",
+        "n_gpus": 1, "steps": legs[use]["steps"], "warmup": legs[use]["warmup"],
+        "ms_per_step": U["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": use, "data": "synthetic",
-        "config": {"workload": W.WORKLOAD_NAMES["cfg4"], "timed_block": f"targets 0..{Ni - 1} x {N} sources",
-                   "pairs": npairs, "rank": list(s.r), "terms": s.K},
+        "config": {"workload": W.WORKLOAD_NAMES["cfg4"] + f"; one step = the next {B}-target batch of the block "
+                   f"against all {N} sources ({npairs} pairs)", "grid": list(n), "orbitals": N, "rank": list(r),
+                   "terms": K, "batch_targets": B, "pairs_per_step": npairs, "mode": "block (targets x all sources)"},
         "legs": out_legs,
-        "roofline": {"bound": "mfma", "kernel": "core", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[use],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[use], 4), "traffic": None,
-                     "launch_ms": round(core_ms / max(out_legs[use]["core_launches_per_step"], 1), 3)},
+        "fp32_over_fp64": out_legs.get("f32", {}).get("over_fp64"),
+        "whole_path_tflops": round(flops_per_pair(n, r, K) * npairs / (U["ms_per_step"] * 1e-3) / 1e12, 3),
+        "roofline": roof,
+        "measured_ceilings": {"f64_mfma_tflops": round(ctx.ceiling("f64"), 1),
+                              "f32_mfma_tflops": round(ctx.ceiling("f32"), 1),
+                              "bf16_mfma_tflops": round(ctx.ceiling("bf16"), 1),
+                              "hbm_stream_gbs": round(ctx.ceiling("hbm"), 1)},
     }
+    if args.retune:
+        txe.tune_save(ctx, TUNE_CACHE)
     sysm.close()
     ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = block_cpu_baseline(s, args.cpu_seconds, args.cpu_single_seconds)
     print(json.dumps(out), flush=True)
 
 
@@ -318,17 +416,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
-    ap.add_argument("--targets", type=int, default=8, help="cfg4: targets of the timed block (all 1,842 sources)")
+    ap.add_argument("--config", default="cfg4", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"],
+                    help="workload: cfg4 = the 128^3 block (default), cfg2 = 64^3 symmetric, cfg3 = 80^3 "
+                         "symmetric, cfg5 = 24 uneven systems in one graph")
+    ap.add_argument("--batch", type=int, default=4, choices=[1, 2, 4, 8, 16],
+                    help="cfg4: targets per step (batch of the 128-target block, all 1,842 sources)")
+    ap.add_argument("--side-steps", type=int, default=3,
+                    help="cfg4: timed batches of the FP64 and split-bf16 legs (the FP32 leg times --steps)")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--retune", action="store_true",
                     help="search launch shapes live (before the timed region) and write them to the cache file")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-single-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise kernel that reads and writes 512 MiB (reference for "
                          "the HBM byte counters)")
-    ap.add_argument("--legs", default="f64,f32,bf16x3,bf16x6", help="compute forms to time (comma separated)")
+    ap.add_argument("--legs", default="f32,f64,bf16x3,bf16x6", help="compute forms to time (comma separated)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

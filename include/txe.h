@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define TXE_ABI_VERSION 2
+#define TXE_ABI_VERSION 3
 
 typedef enum {
   TXE_OK = 0,
@@ -122,6 +122,11 @@ typedef struct {
   double *e_pairs;          /* device: per-pair energies e_ij (FP64) or NULL.  Symmetric:   */
                             /* N(N+1)/2 entries, pair (i<=j) at i*N - i(i-1)/2 + (j-i);     */
                             /* block: Ni*N entries, pair (i0+t, j) at t*N + j               */
+  double *e_orb;            /* device: Ni FP64 entries or NULL: the exchange-matrix         */
+                            /* diagonal <psi_i, Vx psi_i>_W = -sum_j e_ij of each target    */
+                            /* (entry t: orbital i0+t, or t in symmetric mode), summed in   */
+                            /* FP64 over j ascending.  ex, e_pairs and e_orb must be 8-byte */
+                            /* aligned and overlap neither each other, psi nor vxpsi.       */
 } txe_apply_args;
 
 /* ABI version (TXE_ABI_VERSION). */
@@ -144,8 +149,14 @@ txe_status txe_conv_matrix_1d(int32_t n, const double *x, double alpha, double *
  * default stream).  The context owns a reusable device workspace. */
 txe_status txe_context_create(int32_t device, void *hip_stream, txe_context **out);
 txe_status txe_context_destroy(txe_context *ctx);
-/* Change the stream later work is enqueued on. */
+/* Change the stream later work is enqueued on.  When the new stream differs
+ * from the old one (and neither is being captured), the new stream first
+ * waits for the work already enqueued on the old one, so consecutive calls on
+ * one context stay ordered on its single workspace. */
 txe_status txe_context_set_stream(txe_context *ctx, void *hip_stream);
+/* Diagnostics: how many txe_context_set_stream calls so far ordered the new
+ * stream after the old one with an event (host int64 *count). */
+txe_status txe_context_stream_changes(txe_context *ctx, int64_t *count);
 /* Grow the workspace to at least `bytes` now (so that later applies allocate
  * nothing).  A limit for tests: env TXE_TEST_MAX_WORKSPACE (bytes). */
 txe_status txe_workspace_reserve(txe_context *ctx, size_t bytes);
@@ -168,9 +179,14 @@ txe_status txe_profile_read(txe_context *ctx, int32_t kernel, double *total_ms, 
 const char *txe_kernel_name(int32_t kernel);
 
 /* System: validates the description (U orthonormality included), builds the
- * FP64 tables C_k^d, V_d, Chat_k^d on the host, rounds them to every compute
- * precision and uploads them.  Copies all host arrays; keeps no caller
- * pointer.  Synchronises the context stream once (upload). */
+ * FP64 tables on the host -- the 1-D convolution matrices C_k^d of the
+ * Gaussian terms (eqs. `quadVal`, `discInteg` with linear elements, or the
+ * caller's C), V_d = diag(q_d) U_d and Chat_k^d = V_d^T C_k^d U_d (the 1-D
+ * operators of eq. `final` restricted to the bases of eq. `TuckerDecompField`)
+ * -- rounds them to every compute precision and uploads them.  Copies all
+ * host arrays; keeps no caller pointer.  Synchronises the context stream once
+ * (upload).  Errors: TXE_ERR_SHAPE / _ARG on the description, TXE_ERR_DEVICE
+ * when an upload fails (nothing is kept). */
 txe_status txe_system_create(txe_context *ctx, const txe_system_desc *desc, txe_system **out);
 txe_status txe_system_destroy(txe_system *sys);
 
@@ -183,7 +199,15 @@ txe_status txe_system_conv(const txe_system *sys, int32_t mode, double *C_out, d
 txe_status txe_workspace_query(txe_context *ctx, const txe_system *sys, const txe_apply_args *args,
                                size_t *bytes);
 
-/* One exchange apply (Vx psi for the targets and/or E_x). */
+/* One exchange apply: Vx psi for the targets (eq. `ExchangeOperator` with the
+ * Hadamard sum of eq. `hadam`), E_x (exact-exchange term of S, section
+ * "Preliminaries"), the pair energies and the exchange-matrix diagonal, each
+ * optional, through the Tucker-core evaluation of section "Convolution
+ * operation" (eqs. `TuckerDecompField`, `gauss`, `final`).  Validates every
+ * argument first (TXE_ERR_ARG / _SHAPE, nothing enqueued), grows the context
+ * workspace when needed (TXE_ERR_NOMEM past the limit, TXE_ERR_STATE if that
+ * would happen while the stream is captured), then enqueues the kernels on
+ * the context stream without waiting. */
 txe_status txe_apply(txe_context *ctx, const txe_system *sys, const txe_apply_args *args);
 
 /* Batched apply: S independent problems (each its own system, orbitals and

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtxe.so")
 
-SOURCES = ["txe_kernels.hip", "txe_ace.hip", "txe_ceiling.hip", "txe_api.cpp", "txe_setup.cpp"]
+SOURCES = ["txe_core_f32.hip", "txe_core_f64.hip", "txe_core_bf16.hip", "txe_back.hip", "txe_proj.hip",
+           "txe_chunk.hip", "txe_ace.hip", "txe_ceiling.hip", "txe_api.cpp", "txe_setup.cpp"]
 ARCH = "gfx950"
 
 
@@ -35,21 +36,30 @@ def flags():
     ]
 
 
-def build(verbose=False, extra=()):
-    objs = []
+def _compile(src, extra, verbose):
+    obj = os.path.join(HERE, "_build", src + ".o")
+    cmd = [hipcc(), *flags(), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l and l.strip())
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{out}")
+    return obj, " ".join(shlex.quote(c) for c in cmd), out
+
+
+def build(verbose=False, extra=(), jobs=None):
+    """Compiles every source (in parallel, at most `jobs` at once) and links."""
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(HERE, "_build", src + ".o")
-        cmd = [hipcc(), *flags(), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        res = list(ex.map(lambda src: _compile(src, extra, verbose), SOURCES))
+    objs = []
+    for obj, cmd, out in res:
         if verbose:
-            print(" ".join(shlex.quote(c) for c in cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        out = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
-                        if "packed-fp32-ops" not in l and l.strip())
-        if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed on {src}:\n{out}")
-        if verbose and out:
-            print(out)
+            print(cmd, flush=True)
+            if out:
+                print(out)
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

@@ -60,6 +60,8 @@ struct txe_context {
   std::vector<hipEvent_t> lane_done;
   hipEvent_t fork = nullptr;
   hipStream_t cap = nullptr;             // private stream for graph capture
+  hipEvent_t handoff = nullptr;          // orders a new stream after the old one (set_stream)
+  long long handoffs = 0;                // stream changes that were ordered by that event
 };
 
 template <typename T>
@@ -171,6 +173,7 @@ extern "C" txe_status txe_context_destroy(txe_context *ctx) {
   for (hipEvent_t e : ctx->lane_done) hipEventDestroy(e);
   if (ctx->fork) hipEventDestroy(ctx->fork);
   if (ctx->cap) hipStreamDestroy(ctx->cap);
+  if (ctx->handoff) hipEventDestroy(ctx->handoff);
   delete ctx;
   return ok();
 }
@@ -206,7 +209,30 @@ extern "C" const char *txe_kernel_name(int32_t kernel) {
 
 extern "C" txe_status txe_context_set_stream(txe_context *ctx, void *hip_stream) {
   if (!ctx) return fail(TXE_ERR_ARG, "ctx is null");
-  ctx->stream = (hipStream_t)hip_stream;
+  const hipStream_t next = (hipStream_t)hip_stream;
+  if (next == ctx->stream) return ok();
+  // Work already enqueued on the old stream uses the context's workspace:
+  // the new stream waits for it (an event recorded on the old stream), so
+  // applies issued from two streams never overlap on that workspace.  A
+  // stream under capture neither records nor waits here (its own capture
+  // orders it; the caller joins captures explicitly).
+  hipStreamCaptureStatus c0 = hipStreamCaptureStatusNone, c1 = hipStreamCaptureStatusNone;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamIsCapturing(ctx->stream, &c0));
+  HIP_TRY(hipStreamIsCapturing(next, &c1));
+  if (c0 == hipStreamCaptureStatusNone && c1 == hipStreamCaptureStatusNone) {
+    if (!ctx->handoff) HIP_TRY(hipEventCreateWithFlags(&ctx->handoff, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ctx->handoff, ctx->stream));
+    HIP_TRY(hipStreamWaitEvent(next, ctx->handoff, 0));
+    ++ctx->handoffs;
+  }
+  ctx->stream = next;
+  return ok();
+}
+
+extern "C" txe_status txe_context_stream_changes(txe_context *ctx, int64_t *count) {
+  if (!ctx || !count) return fail(TXE_ERR_ARG, "null argument");
+  *count = ctx->handoffs;
   return ok();
 }
 
@@ -610,6 +636,13 @@ struct Plan {
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
+// true when both ranges are non-null and share a byte
+static bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+  const char *a0 = (const char *)a, *b0 = (const char *)b;
+  return a && b && a0 < b0 + nb && b0 < a0 + na;
+}
+
+
 static void plan_sizes(const Dims &D, Plan &pl) {
   const size_t P = (size_t)pl.Pmax;
   const size_t perT2 = (size_t)D.n0 * D.rp1 * D.rp2;
@@ -708,16 +741,30 @@ static txe_status validate_args(const txe_context *ctx, const txe_system *sys, c
       return fail(TXE_ERR_SHAPE, "target block [%d, %d) not inside [0, %d)", a->i0, a->i0 + a->Ni, a->N);
   }
   if (a->out_weighted != 0 && a->out_weighted != 1) return fail(TXE_ERR_ARG, "out_weighted must be 0 or 1");
-  if (!a->vxpsi && !a->ex && !a->e_pairs) return fail(TXE_ERR_ARG, "nothing to compute (vxpsi, ex and e_pairs are null)");
+  if (!a->vxpsi && !a->ex && !a->e_pairs && !a->e_orb)
+    return fail(TXE_ERR_ARG, "nothing to compute (vxpsi, ex, e_pairs and e_orb are null)");
   const size_t elt = a->dtype == TXE_DTYPE_F64 ? 8 : 4;
   const size_t grid = (size_t)sys->n[0] * sys->n[1] * sys->n[2];
-  if (a->vxpsi) {
-    const char *p0 = (const char *)a->psi, *p1 = p0 + (size_t)a->N * grid * elt;
-    const char *v0 = (const char *)a->vxpsi, *v1 = v0 + (size_t)a->Ni * grid * elt;
-    if (v0 < p1 && p0 < v1) return fail(TXE_ERR_ARG, "vxpsi overlaps psi");
-  }
+  const size_t npairs = a->symmetric ? (size_t)a->N * (a->N + 1) / 2 : (size_t)a->Ni * a->N;
+  // every output against every input and every other output
+  struct Buf {
+    const void *p;
+    size_t bytes;
+    const char *name;
+  };
+  const Buf bufs[5] = {{a->psi, (size_t)a->N * grid * elt, "psi"},
+                       {a->vxpsi, (size_t)a->Ni * grid * elt, "vxpsi"},
+                       {a->ex, 8, "ex"},
+                       {a->e_pairs, npairs * 8, "e_pairs"},
+                       {a->e_orb, (size_t)a->Ni * 8, "e_orb"}};
+  for (int o = 1; o < 5; ++o)
+    for (int b = 0; b < o; ++b)
+      if (overlaps(bufs[o].p, bufs[o].bytes, bufs[b].p, bufs[b].bytes))
+        return fail(TXE_ERR_ARG, "%s overlaps %s", bufs[o].name, bufs[b].name);
   if (((uintptr_t)a->psi % (4 * elt)) != 0) return fail(TXE_ERR_ARG, "psi must be %zu-byte aligned", 4 * elt);
   if (a->vxpsi && ((uintptr_t)a->vxpsi % elt) != 0) return fail(TXE_ERR_ARG, "vxpsi is misaligned");
+  if (((uintptr_t)a->ex % 8) || ((uintptr_t)a->e_pairs % 8) || ((uintptr_t)a->e_orb % 8))
+    return fail(TXE_ERR_ARG, "ex, e_pairs and e_orb must be 8-byte aligned");
   return TXE_OK;
 }
 
@@ -789,8 +836,9 @@ static hipError_t run_plan(const txe_system *sys, const txe_apply_args *args, co
     }
   }
   if (e == hipSuccess)
-    e = run_energy((const double *)(ws + pl.off_epair), pl.npairs, pl.symmetric ? 1 : 0, args->N, args->ex,
-                   args->e_pairs, s, prof);
+    e = run_energy((const double *)(ws + pl.off_epair), pl.npairs, pl.symmetric ? 1 : 0, args->N,
+                   pl.symmetric ? 0 : args->i0, pl.symmetric ? args->N : args->Ni, args->ex, args->e_pairs,
+                   args->e_orb, s, prof);
   return e;
 }
 
@@ -866,6 +914,7 @@ static txe_status batch_plan(txe_context *ctx, int S, const txe_system *const *s
     if (a.vxpsi) outs.push_back({(const char *)a.vxpsi, (const char *)a.vxpsi + (size_t)a.Ni * grid * elt, i});
     if (a.ex) outs.push_back({(const char *)a.ex, (const char *)a.ex + 8, i});
     if (a.e_pairs) outs.push_back({(const char *)a.e_pairs, (const char *)a.e_pairs + b.plans[i].npairs * 8, i});
+    if (a.e_orb) outs.push_back({(const char *)a.e_orb, (const char *)a.e_orb + (size_t)a.Ni * 8, i});
   }
   std::sort(outs.begin(), outs.end(), [](const Range &x, const Range &y) { return x.lo < y.lo; });
   for (size_t k = 1; k < outs.size(); ++k)
@@ -1199,11 +1248,6 @@ extern "C" txe_status txe_measure_ceiling(txe_context *ctx, int32_t kind, double
 // ------------------------------------------------------------------------------------
 // adaptively compressed exchange
 // ------------------------------------------------------------------------------------
-static bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
-  const char *a0 = (const char *)a, *b0 = (const char *)b;
-  return a && b && a0 < b0 + nb && b0 < a0 + na;
-}
-
 extern "C" txe_status txe_ace_build(txe_context *ctx, const txe_system *sys, int32_t N, int32_t dtype,
                                     const void *psi, const void *W, double *xi, double *M_out, double *L_out,
                                     int32_t *info) {

@@ -1,0 +1,427 @@
+// Back-projection, product with psi_j and the sum over sources (eq.
+// `hadam`), accumulated in registers without atomics.
+#include "txe_dev.h"
+
+namespace txe {
+
+// -------------------------------------------------------------------------------------
+// back: for target t, slab a and a group of NCG c-tiles, over all sources s:
+//   X[beta][c]  = sum_gamma S1[p(t,s)][a][gamma][beta] U2[c][gamma]
+//   phi[b][c]   = sum_beta U1[b][beta] X[beta][c]                      (chained)
+//   acc[b][c]  += psi_s[a][b][c] phi[b][c]
+// then Vx psi_t[a][b][c] = -scale * acc (times w(r) when weighted).  Two
+// forms of the same sum:
+//   k_back_s  streaming: runtime rank loops, loads next to their MFMA; small
+//             register footprint, so many wavefronts per SIMD hide latency
+//   k_back_b  batched: compile-time rank tiles, the source-independent U2
+//             fragments hoisted out of the source loop, each source's S1
+//             rows loaded in batches ahead of their MFMAs (clamped addresses
+//             and selects instead of branches); fewer, busier wavefronts
+// -------------------------------------------------------------------------------------
+template <typename T, typename Tin, int NBT, int NCG, bool LDS_TAB>
+__global__ __launch_bounds__(256) void k_back_s(const T *__restrict__ S1, const Tin *__restrict__ psi, Dims D,
+                                              PairMap pm, int N, int t_begin, int t_count, Tables<T> tb,
+                                              Tin *__restrict__ vx, const double *__restrict__ out_scale,
+                                              int weighted, const double *__restrict__ q0,
+                                              const double *__restrict__ q1, const double *__restrict__ q2) {
+  using M = MF<T>;
+  using acc = typename M::acc;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
+  const int nct = D.nc2 >> 4, nbt = D.nb1 >> 4;
+  const int ncg = (nct + NCG - 1) / NCG;
+  // shared operands (U2^T and the chained U1 fragments) staged once per workgroup
+  const T *U2t = tb.U2T, *U1c = tb.U1chain;
+  if constexpr (LDS_TAB) {
+    T *s2 = reinterpret_cast<T *>(smem_raw);
+    T *s1 = s2 + (size_t)D.rp2 * D.nc2;
+    const int m2 = D.rp2 * D.nc2, m1 = nbt * D.MT1 * 256;
+    for (int idx = threadIdx.x; idx < m2; idx += 256) s2[idx] = tb.U2T[idx];
+    for (int idx = threadIdx.x; idx < m1; idx += 256) s1[idx] = tb.U1chain[idx];
+    __syncthreads();
+    U2t = s2;
+    U1c = s1;
+  }
+  const long long total = (long long)t_count * D.n0 * ncg;
+  for (long long item = (long long)blockIdx.x * 4 + wave; item < total; item += (long long)gridDim.x * 4) {
+  const int cgi = (int)(item % ncg);
+  const long long rest = item / ncg;
+  const int a = (int)(rest % D.n0);
+  const int t = t_begin + (int)(rest / D.n0);          // local target index
+  const int tglob = pm.symmetric ? t : pm.i0 + t;      // orbital index of the target
+  const int c0 = cgi * NCG;
+  const size_t plane = (size_t)D.n1 * D.n2;
+  const size_t S1pair = (size_t)D.n0 * D.rp2 * D.rp1;
+
+  acc Acc[NBT][NCG];
+#pragma unroll
+  for (int mb = 0; mb < NBT; ++mb)
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) Acc[mb][cg] = zero4<acc>();
+
+  for (int s = 0; s < N; ++s) {
+    long long pg;
+    if (pm.symmetric) {
+      const int i = min(tglob, s), j = max(tglob, s);
+      pg = sym_start(i, pm.N) + (j - i);
+    } else {
+      pg = (long long)t * pm.N + s;
+    }
+    const T *S = S1 + (size_t)(pg - pm.p0) * S1pair + (size_t)a * D.rp2 * D.rp1 + lr;
+    acc X[MAX_MT][NCG];
+#pragma unroll
+    for (int mb = 0; mb < MAX_MT; ++mb)
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) X[mb][cg] = zero4<acc>();
+    for (int kt = 0; kt < (D.r2k >> 2); ++kt) {
+      const int gam = 4 * kt + lg;
+      const bool gv = gam < D.r2;
+      T bu[NCG];
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg)
+        bu[cg] = (gv && c0 + cg < nct) ? U2t[(size_t)gam * D.nc2 + 16 * (c0 + cg) + lr] : (T)0;
+      const T *srow = S + (size_t)gam * D.rp1;
+#pragma unroll
+      for (int mb = 0; mb < MAX_MT; ++mb) {
+        if (mb < D.MT1) {
+          const T af = gv ? srow[16 * mb] : (T)0;
+#pragma unroll
+          for (int cg = 0; cg < NCG; ++cg) X[mb][cg] = M::mma(af, bu[cg], X[mb][cg]);
+        }
+      }
+    }
+    const Tin *ps = psi + (size_t)s * D.n0 * plane + (size_t)a * plane;
+#pragma unroll
+    for (int mbb = 0; mbb < NBT; ++mbb) {
+      if (mbb < nbt) {
+        acc ph[NCG];
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg) ph[cg] = zero4<acc>();
+#pragma unroll
+        for (int mbe = 0; mbe < MAX_MT; ++mbe) {
+          if (mbe < D.MT1) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const T af = U1c[(((size_t)mbb * D.MT1 + mbe) * 4 + v) * 64 + lane];
+#pragma unroll
+              for (int cg = 0; cg < NCG; ++cg) ph[cg] = M::mma(af, X[mbe][cg][v], ph[cg]);
+            }
+          }
+        }
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg) {
+          const int c = 16 * (c0 + cg) + lr;
+          if (c0 + cg < nct && c < D.n2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int b = 16 * mbb + drow<T>(lg, v);
+              if (b < D.n1) Acc[mbb][cg][v] += (T)ps[(size_t)b * D.n2 + c] * ph[cg][v];
+            }
+          }
+        }
+      }
+    }
+  }
+  const double scale = out_scale ? *out_scale : 1.0;
+  Tin *out = vx + (size_t)t * D.n0 * plane + (size_t)a * plane;
+#pragma unroll
+  for (int mbb = 0; mbb < NBT; ++mbb) {
+    if (mbb < nbt) {
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) {
+        const int c = 16 * (c0 + cg) + lr;
+        if (c0 + cg < nct && c < D.n2) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int b = 16 * mbb + drow<T>(lg, v);
+            if (b < D.n1) {
+              double val = -scale * (double)Acc[mbb][cg][v];
+              if (weighted) val *= q0[a] * q1[b] * q2[c];
+              out[(size_t)b * D.n2 + c] = (Tin)val;
+            }
+          }
+        }
+      }
+    }
+  }
+  }
+}
+
+template <typename T, typename Tin, typename Tps, int MT, int NBT, int NCG, bool LDS_TAB>
+__global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const Tps *__restrict__ psi, Dims D,
+                                                PairMap pm, int N, int t_begin, int t_count, Tables<T> tb,
+                                                Tin *__restrict__ vx, const double *__restrict__ out_scale,
+                                                int weighted, const double *__restrict__ q0,
+                                                const double *__restrict__ q1, const double *__restrict__ q2,
+                                                int mb0) {
+  using M = MF<T>;
+  using acc = typename M::acc;
+  constexpr int RP = 16 * MT;
+  // S1 rows (gamma') per batch of loads: all of them while registers allow
+  constexpr int KTB = sizeof(T) == 4 ? 2 : 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
+  const int nct = D.nc2 >> 4, nbt = D.nb1 >> 4;
+  const int ncg = (nct + NCG - 1) / NCG;
+  const int nkt = (D.r2 + 3) >> 2;  // gamma' rows in use, in fours
+  // shared operands (U2^T and the chained U1 fragments), staged once per
+  // workgroup in LDS when they fit (the choice is compile-time, so the
+  // reads are LDS or global loads, never generic ones)
+  T *s2 = reinterpret_cast<T *>(smem_raw);
+  T *s1 = s2 + (size_t)RP * D.nc2;
+  if constexpr (LDS_TAB) {
+    const int m2 = RP * D.nc2, m1 = nbt * MT * 256;
+    for (int idx = threadIdx.x; idx < m2; idx += 256) s2[idx] = tb.U2T[idx];
+    for (int idx = threadIdx.x; idx < m1; idx += 256) s1[idx] = tb.U1chain[idx];
+    __syncthreads();
+  }
+  const T *U2t = LDS_TAB ? s2 : tb.U2T;
+  const T *U1c = LDS_TAB ? s1 : tb.U1chain;
+  const size_t plane = (size_t)D.n1 * D.n2;
+  const size_t S1pair = (size_t)D.n0 * RP * RP;
+  const long long total = (long long)t_count * D.n0 * ncg;
+  // per-lane offsets are 32-bit and unsigned, added to wave-uniform bases
+  const unsigned soff = (unsigned)(lg * RP + lr);  // S1 fragment element of this lane
+  for (long long item = (long long)blockIdx.x * 4 + wave; item < total; item += (long long)gridDim.x * 4) {
+    const int cgi = (int)(item % ncg);
+    const long long rest = item / ncg;
+    const int a = (int)(rest % D.n0);
+    const int t = t_begin + (int)(rest / D.n0);          // local target index
+    const int tglob = pm.symmetric ? t : pm.i0 + t;      // orbital index of the target
+    // c tiles of this wavefront (a phantom tile past the last one repeats it
+    // and is never stored)
+    int ct[NCG];
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) ct[cg] = min(cgi * NCG + cg, nct - 1);
+    // U2 fragments do not depend on the source: B[gamma'][c]
+    T bu[4 * MT][NCG];
+#pragma unroll
+    for (int kt = 0; kt < 4 * MT; ++kt)
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) bu[kt][cg] = U2t[(unsigned)((4 * kt + lg) * D.nc2 + 16 * ct[cg] + lr)];
+    // psi_j values of this wavefront's output points, clamped into the grid
+    // (points past the edge are computed and never stored)
+    unsigned poff[NBT][4];  // within one plane (n1 n2 < 2^31)
+#pragma unroll
+    for (int mbb = 0; mbb < NBT; ++mbb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) poff[mbb][v] = (unsigned)(min(16 * (mb0 + mbb) + drow<T>(lg, v), D.n1 - 1) * D.n2);
+    unsigned pc[NCG];
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) pc[cg] = (unsigned)min(16 * ct[cg] + lr, D.n2 - 1);
+
+    acc Acc[NBT][NCG];
+#pragma unroll
+    for (int mb = 0; mb < NBT; ++mb)
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) Acc[mb][cg] = zero4<acc>();
+
+    for (int s = 0; s < N; ++s) {
+      long long pg;
+      if (pm.symmetric) {
+        const int i = min(tglob, s), j = max(tglob, s);
+        pg = sym_start(i, pm.N) + (j - i);
+      } else {
+        pg = (long long)t * pm.N + s;
+      }
+      const auto *S = wave_uniform(S1 + (size_t)(pg - pm.p0) * S1pair + (size_t)a * RP * RP);
+      const auto *ps = wave_uniform(psi + (size_t)s * D.n0 * plane + (size_t)a * plane);
+      // the U1 fragments do not depend on the source, but holding all of
+      // them across the source loop costs NBT * MT * 4 registers: an offset
+      // made opaque per source by an empty asm makes them reload
+      unsigned u1o = (unsigned)(mb0 * MT * 256 + lane);
+      asm volatile("" : "+v"(u1o));
+      // X[beta'][c] = sum_gamma' S1[gamma'][beta'] U2[c][gamma']
+      acc X[MT][NCG];
+#pragma unroll
+      for (int mb = 0; mb < MT; ++mb)
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg) X[mb][cg] = zero4<acc>();
+#pragma unroll
+      for (int kb = 0; kb < 4 * MT; kb += KTB) {
+        if (kb >= nkt) break;  // uniform: padded gamma' rows only
+        T sf[KTB][MT];
+#pragma unroll
+        for (int k = 0; k < KTB; ++k) {
+          const int gam = 4 * (kb + k) + lg;
+#pragma unroll
+          for (int mb = 0; mb < MT; ++mb) {
+            const T x = S[soff + (unsigned)(4 * (kb + k) * RP + 16 * mb)];
+            sf[k][mb] = gam < D.r2 ? x : (T)0;  // rows past r2 are not written by the core kernel
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < KTB; ++k)
+#pragma unroll
+          for (int mb = 0; mb < MT; ++mb)
+#pragma unroll
+            for (int cg = 0; cg < NCG; ++cg) X[mb][cg] = M::mma(sf[k][mb], bu[kb + k][cg], X[mb][cg]);
+      }
+      // phi[b][c] = sum_beta' U1[b][beta'] X[beta'][c] (chained), then Acc += psi_j phi
+#pragma unroll
+      for (int mbb = 0; mbb < NBT; ++mbb) {
+        if (mb0 + mbb >= nbt) break;  // uniform
+        // one b tile at a time: keeps the U1 fragments and psi values of the
+        // other tiles out of registers
+        __builtin_amdgcn_sched_barrier(0);
+        // psi_j at this b tile's points, loaded ahead of the chain that needs them
+        Tps pv[NCG][4];
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) pv[cg][v] = ps[poff[mbb][v] + pc[cg]];
+        acc ph[NCG];
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg) ph[cg] = zero4<acc>();
+#pragma unroll
+        for (int mbe = 0; mbe < MT; ++mbe)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T af = U1c[u1o + (unsigned)(((mbb * MT + mbe) * 4 + v) * 64)];
+#pragma unroll
+            for (int cg = 0; cg < NCG; ++cg) ph[cg] = M::mma(af, X[mbe][cg][v], ph[cg]);
+          }
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Acc[mbb][cg][v] += (T)pv[cg][v] * ph[cg][v];
+      }
+    }
+    const double scale = out_scale ? *out_scale : 1.0;
+    Tin *out = vx + (size_t)t * D.n0 * plane + (size_t)a * plane;
+#pragma unroll
+    for (int mbb = 0; mbb < NBT; ++mbb) {
+      if (mb0 + mbb >= nbt) break;
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) {
+        const int c = 16 * (cgi * NCG + cg) + lr;
+        if (cgi * NCG + cg < nct && c < D.n2) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int b = 16 * (mb0 + mbb) + drow<T>(lg, v);
+            if (b < D.n1) {
+              double val = -scale * (double)Acc[mbb][cg][v];
+              if (weighted) val *= q0[a] * q1[b] * q2[c];
+              out[(size_t)b * D.n2 + c] = (Tin)val;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+template <typename T, typename Tin, int NCG>
+hipError_t launch_back_s_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  const int nct = a.D.nc2 >> 4, nbt = a.D.nb1 >> 4;
+  const long long waves = (long long)a.t_count * a.D.n0 * ((nct + NCG - 1) / NCG);
+  const unsigned nb = blocks_for(waves);
+  const Tin *psi = (const Tin *)a.psi;
+  Tin *vx = (Tin *)a.vx;
+  // shared operands in LDS when they fit in 64 KiB; the grid is then capped
+  // and each workgroup walks several items
+  const size_t tab = ((size_t)a.D.rp2 * a.D.nc2 + (size_t)nbt * a.D.MT1 * 256) * sizeof(T);
+  const bool lds_tab = tab <= 64 * 1024;
+  const unsigned nbl = lds_tab ? std::min(nb, (unsigned)a.grid_cap) : nb;
+#define TXE_BACK(NBTV)                                                                                         \
+  if (lds_tab)                                                                                                   \
+    hipLaunchKernelGGL((k_back_s<T, Tin, NBTV, NCG, true>), dim3(nbl), dim3(256), tab, s, a.S1, psi, a.D, a.pm,  \
+                       a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1],         \
+                       a.qdev[2]);                                                                               \
+  else                                                                                                           \
+    hipLaunchKernelGGL((k_back_s<T, Tin, NBTV, NCG, false>), dim3(nb), dim3(256), 0, s, a.S1, psi, a.D, a.pm,    \
+                       a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1],         \
+                       a.qdev[2])
+  if (nbt <= 2) TXE_BACK(2);
+  else if (nbt <= 4) TXE_BACK(4);
+  else if (nbt <= 6) TXE_BACK(6);
+  else if (nbt <= 8) TXE_BACK(8);
+  else return hipErrorInvalidValue;
+#undef TXE_BACK
+  return hipGetLastError();
+}
+
+template <typename T, typename Tin, typename Tps, int MT, int NCG>
+hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  const int nct = a.D.nc2 >> 4, nbt = a.D.nb1 >> 4;
+  const long long waves = (long long)a.t_count * a.D.n0 * ((nct + NCG - 1) / NCG);
+  const unsigned nb = blocks_for(waves);
+  // psi_j as read: the orbitals, or their FP32 copy (the values the FP32
+  // kernel rounds them to anyway)
+  const Tps *psi = std::is_same<Tps, Tin>::value ? (const Tps *)a.psi : (const Tps *)a.psi32;
+  Tin *vx = (Tin *)a.vx;
+  // shared operands in LDS when they fit in 64 KiB; the grid is then capped
+  // and each workgroup walks several items
+  const size_t tab = ((size_t)16 * MT * a.D.nc2 + (size_t)nbt * MT * 256) * sizeof(T);
+  const int lds_tab = tab <= 64 * 1024 ? 1 : 0;
+  const unsigned nbl = lds_tab ? std::min(nb, (unsigned)a.grid_cap) : nb;
+  const size_t lds = lds_tab ? tab : 0;
+  // all b tiles in one launch up to six tiles (X computed once per source);
+  // FP64 up to eight.  FP32 beyond six: launches over disjoint ranges of
+  // four b tiles, each recomputing X for its sources (registers)
+  if (nbt > 8) return hipErrorInvalidValue;
+#define TXE_BACK(NBTV, MB0)                                                                                      \
+  do {                                                                                                           \
+    if (lds_tab)                                                                                                 \
+      hipLaunchKernelGGL((k_back_b<T, Tin, Tps, MT, NBTV, NCG, true>), dim3(nbl), dim3(256), lds, s, a.S1, psi, a.D,  \
+                         a.pm, a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0],           \
+                         a.qdev[1], a.qdev[2], MB0);                                                             \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_back_b<T, Tin, Tps, MT, NBTV, NCG, false>), dim3(nbl), dim3(256), 0, s, a.S1, psi, a.D,   \
+                         a.pm, a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0],           \
+                         a.qdev[1], a.qdev[2], MB0);                                                             \
+  } while (0)
+  if (nbt <= 2) {
+    TXE_BACK(2, 0);
+  } else if (nbt <= 4) {
+    TXE_BACK(4, 0);
+  } else if (nbt <= 6) {
+    TXE_BACK(6, 0);
+  } else if constexpr (sizeof(T) == 8) {
+    TXE_BACK(8, 0);
+  } else {
+    for (int mb0 = 0; mb0 < nbt; mb0 += 4) TXE_BACK(4, mb0);
+  }
+#undef TXE_BACK
+  return hipGetLastError();
+}
+
+template <typename T, typename Tin, typename Tps, int NCG>
+hipError_t launch_back_b_tps(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  switch (a.D.MT1) {
+    case 1: return launch_back_b_mt<T, Tin, Tps, 1, NCG>(tb, a, s);
+    case 2: return launch_back_b_mt<T, Tin, Tps, 2, NCG>(tb, a, s);
+    case 3: return launch_back_b_mt<T, Tin, Tps, 3, NCG>(tb, a, s);
+    case 4: return launch_back_b_mt<T, Tin, Tps, 4, NCG>(tb, a, s);
+    case 5: return launch_back_b_mt<T, Tin, Tps, 5, NCG>(tb, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, typename Tin, int NCG>
+hipError_t launch_back_b_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  if constexpr (sizeof(T) == 4 && sizeof(Tin) == 8)
+    if (a.psi32) return launch_back_b_tps<T, Tin, float, NCG>(tb, a, s);
+  return launch_back_b_tps<T, Tin, Tin, NCG>(tb, a, s);
+}
+
+template <typename T, typename Tin>
+hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+  // form: streaming (k_back_s, runtime rank loops, high occupancy) or
+  // batched (k_back_b, compile-time rank tiles, loads issued per source in
+  // batches).  Default: batched, which measured fastest on the 64^3 and
+  // 80^3 workloads in both precisions
+  const bool batched = a.back_form ? a.back_form == 2 : true;
+  // two c-tiles per wavefront while the b-tile accumulators are few
+  const int ncg = a.back_ncg ? a.back_ncg : ((a.D.nb1 >> 4) <= 4 ? 2 : 1);
+  if (batched) return ncg == 2 ? launch_back_b_ncg<T, Tin, 2>(tb, a, s) : launch_back_b_ncg<T, Tin, 1>(tb, a, s);
+  return ncg == 2 ? launch_back_s_ncg<T, Tin, 2>(tb, a, s) : launch_back_s_ncg<T, Tin, 1>(tb, a, s);
+}
+
+template hipError_t launch_back<double, double>(const Tables<double> &, const ChunkArgs<double> &, hipStream_t);
+template hipError_t launch_back<float, double>(const Tables<float> &, const ChunkArgs<float> &, hipStream_t);
+template hipError_t launch_back<float, float>(const Tables<float> &, const ChunkArgs<float> &, hipStream_t);
+
+}  // namespace txe

@@ -169,6 +169,19 @@ struct Prof {
   }
 };
 
+// Stage launchers of one chunk (each in its own translation unit):
+// projection (psi rounding when needed, proj12, proj3), core kernel sum
+// (FP64 / FP32 MFMA, or split bf16 with NS parts), back-projection.
+template <typename T, typename Tin>
+hipError_t launch_projection(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s, Prof *prof);
+template <typename T>
+hipError_t launch_core(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s);
+template <int NS>
+hipError_t launch_core_bf(const Tables<float> &tb, const BfTables &bft, const ChunkArgs<float> &a, bool want_vx,
+                          hipStream_t s);
+template <typename T, typename Tin>
+hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s);
+
 // Runs one chunk (projection, core sum, back-projection, pair energies).
 // Returns hipSuccess or the first launch error.
 hipError_t run_chunk_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s,
@@ -179,9 +192,10 @@ hipError_t run_chunk_f32(const Tables<float> &tb, const ChunkArgs<float> &a, boo
 // products (nsplit = 2: three products, 3: six products).
 hipError_t run_chunk_bf16(const Tables<float> &tb, const BfTables &bt, int nsplit, const ChunkArgs<float> &a,
                           bool psi_f64, bool want_vx, hipStream_t s, Prof *prof);
-// E_x = sum_p c_p e_pair[p] (fixed order), and an optional copy of e_pair.
-hipError_t run_energy(const double *epair, long long npairs, int symmetric, int N, double *ex, double *e_out,
-                      hipStream_t s, Prof *prof);
+// E_x = sum_p c_p e_pair[p] (fixed order), an optional copy of e_pair and
+// the optional exchange-matrix diagonal -sum_j e_ij of each target.
+hipError_t run_energy(const double *epair, long long npairs, int symmetric, int N, int i0, int Ni, double *ex,
+                      double *e_out, double *e_orb, hipStream_t s, Prof *prof);
 
 // Adaptively compressed exchange (txe_ace.hip).  ace_gram: G[i][j] =
 // sum_g w(g) X_i(g) Y_j(g) (part: gram_nchunks(NX, NY, ng) * NX * NY

@@ -50,6 +50,7 @@ class ApplyArgs(ctypes.Structure):
         ("out_weighted", _c_int),
         ("ex", ctypes.c_void_p),
         ("e_pairs", ctypes.c_void_p),
+        ("e_orb", ctypes.c_void_p),
     ]
 
 
@@ -62,6 +63,7 @@ SIGNATURES = {
     "txe_context_create": (_c_int, [_c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "txe_context_destroy": (_c_int, [ctypes.c_void_p]),
     "txe_context_set_stream": (_c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "txe_context_stream_changes": (_c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "txe_workspace_reserve": (_c_int, [ctypes.c_void_p, ctypes.c_size_t]),
     "txe_system_create": (_c_int, [ctypes.c_void_p, ctypes.POINTER(SystemDesc), ctypes.POINTER(ctypes.c_void_p)]),
     "txe_system_destroy": (_c_int, [ctypes.c_void_p]),
@@ -152,6 +154,12 @@ class Context:
 
     def set_stream(self, stream):
         _check(lib().txe_context_set_stream(self.h, ctypes.c_void_p(_stream_ptr(stream))))
+
+    def stream_changes(self):
+        """Stream changes so far that were ordered after the previous stream."""
+        n = ctypes.c_int64()
+        _check(lib().txe_context_stream_changes(self.h, ctypes.byref(n)))
+        return n.value
 
     def reserve(self, nbytes):
         _check(lib().txe_workspace_reserve(self.h, int(nbytes)))
@@ -252,7 +260,7 @@ class System:
 
 
 def make_args(psi, compute="f64", symmetric=True, i0=0, Ni=None, vx=None, ex=None, e_pairs=None,
-              out_scale=None, out_weighted=False):
+              out_scale=None, out_weighted=False, e_orb=None):
     import torch
 
     a = ApplyArgs()
@@ -268,11 +276,12 @@ def make_args(psi, compute="f64", symmetric=True, i0=0, Ni=None, vx=None, ex=Non
     a.out_weighted = 1 if out_weighted else 0
     a.ex = ex.data_ptr() if ex is not None else None
     a.e_pairs = e_pairs.data_ptr() if e_pairs is not None else None
+    a.e_orb = e_orb.data_ptr() if e_orb is not None else None
     return a
 
 
 def _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_scale=None, out_weighted=False,
-             vx_out=None):
+             vx_out=None, want_orb=False):
     """ApplyArgs for one problem with freshly allocated outputs."""
     import torch
 
@@ -289,23 +298,28 @@ def _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_sca
     ex = torch.empty((), dtype=torch.float64, device=psi.device)
     npairs = N * (N + 1) // 2 if symmetric else Ni * N
     ep = torch.empty(npairs, dtype=torch.float64, device=psi.device) if want_pairs else None
-    a = make_args(psi, compute, symmetric, i0, Ni, vx, ex, ep, out_scale, out_weighted)
+    eo = torch.empty(Ni, dtype=torch.float64, device=psi.device) if want_orb else None
+    a = make_args(psi, compute, symmetric, i0, Ni, vx, ex, ep, out_scale, out_weighted, eo)
+    if want_orb:
+        return a, vx, ex, ep, eo
     return a, vx, ex, ep
 
 
 def apply(ctx: Context, sysm: System, psi, compute="f64", symmetric=True, i0=0, Ni=None, want_vx=True,
-          want_pairs=False, out_scale=None, out_weighted=False, vx_out=None):
+          want_pairs=False, out_scale=None, out_weighted=False, vx_out=None, want_orb=False):
     """Vx psi (targets) and E_x for the orbitals `psi` (a CUDA tensor N x n0 x n1 x n2).
 
     Returns (vx, ex, e_pairs): vx is None when want_vx is False; ex is a
-    0-d float64 CUDA tensor; e_pairs is None unless want_pairs."""
+    0-d float64 CUDA tensor; e_pairs is None unless want_pairs.  With
+    want_orb a fourth entry holds the exchange-matrix diagonal
+    <psi_i, Vx psi_i>_W of each target (FP64, from the library)."""
     import torch
 
-    a, vx, ex, ep = _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_scale, out_weighted,
-                             vx_out)
+    out = _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_scale, out_weighted, vx_out,
+                   want_orb)
     ctx.set_stream(torch.cuda.current_stream(psi.device))
-    _check(lib().txe_apply(ctx.h, sysm.h, ctypes.byref(a)))
-    return vx, ex, ep
+    _check(lib().txe_apply(ctx.h, sysm.h, ctypes.byref(out[0])))
+    return tuple(out[1:])
 
 
 def _batch(items, compute, want_vx, want_pairs):

@@ -3,9 +3,12 @@ the same seeded inputs.
 
 FP64 bar (both from the method's own tolerances): |dE_x|/|E_x| <= 1e-9 and
 max_i ||dVx psi_i||_W / ||Vx psi_i||_W <= 1e-9; pair energies e_ij to 1e-9
-of the largest.  FP32 MFMA: the same quantities against the GPU FP64 path,
-at |dE_x| <= 1e-5 Ha (the reduced-precision gate) and 1e-5 relative on Vx psi.
+of the largest.  Reduced precision (FP32 MFMA, split bf16) against the GPU
+FP64 path: |dE_x| <= 1e-5 Ha absolute (the reduced-precision gate) for every
+form; Vx psi and e_ij relative errors at 1e-5 (FP32, bf16 x6) or 2e-4 (bf16
+x3, whose products keep ~16 bits per operand).
 """
+GATE_HA = 1e-5
 import numpy as np
 import pytest
 import torch
@@ -126,7 +129,7 @@ def test_f32_rank_tiles_against_f64(ctx):
         verr = rel_vx_err(v32, v64, s.grid.q)
         perr = np.abs(p32 - p64).max() / np.abs(p64).max()
         print(f"[f32 r={r}] |dE_x| {abs(e32 - e64):.3e} Ha  e_ij rel {perr:.3e}  Vx rel {verr:.3e}", flush=True)
-        assert abs(e32 - e64) <= 1e-5 and perr <= 1e-5 and verr <= 1e-5
+        assert abs(e32 - e64) <= GATE_HA and perr <= 1e-5 and verr <= 1e-5
 
 
 # per-mode ranks: the tile count follows the largest rank, the live chunks
@@ -149,12 +152,12 @@ def test_f32_anisotropic_ranks_against_f64(ctx):
         verr = rel_vx_err(v32, v64, s.grid.q)
         perr = np.abs(p32 - p64).max() / np.abs(p64).max()
         print(f"[f32 r={r}] |dE_x| {abs(e32 - e64):.3e} Ha  e_ij rel {perr:.3e}  Vx rel {verr:.3e}", flush=True)
-        assert abs(e32 - e64) <= 1e-5 and perr <= 1e-5 and verr <= 1e-5
+        assert abs(e32 - e64) <= GATE_HA and perr <= 1e-5 and verr <= 1e-5
         vb, eb, pb = run_gpu(ctx, s, "bf16x3")
         verr = rel_vx_err(vb, v64, s.grid.q)
         perr = np.abs(pb - p64).max() / np.abs(p64).max()
         print(f"[bf16x3 r={r}] |dE_x| {abs(eb - e64):.3e} Ha  e_ij rel {perr:.3e}  Vx rel {verr:.3e}", flush=True)
-        assert abs(eb - e64) <= 2e-4 * abs(e64) and perr <= 2e-4 and verr <= 2e-4
+        assert abs(eb - e64) <= GATE_HA and perr <= 2e-4 and verr <= 2e-4
 
 
 @pytest.mark.parametrize("form,tol", [("bf16x6", 1e-5), ("bf16x3", 2e-4)])
@@ -171,7 +174,7 @@ def test_bf16_split_against_f64(ctx, form, tol):
         perr = np.abs(pb - p64).max() / np.abs(p64).max()
         print(f"[{form} r={r}] |dE_x| {abs(eb - e64):.3e} Ha (of {abs(e64):.3f})  e_ij rel {perr:.3e}  "
               f"Vx rel {verr:.3e}", flush=True)
-        assert abs(eb - e64) <= tol * abs(e64) and perr <= tol and verr <= tol
+        assert abs(eb - e64) <= GATE_HA and perr <= tol and verr <= tol
 
 
 def test_f32_block_chunked(ctx, monkeypatch):

@@ -273,6 +273,31 @@ def test_block_mode_matches_symmetric(sys_small):
     assert np.abs(v1 - vx[1:3]).max() <= 1e-13 * np.abs(vx).max()
 
 
+def test_apply_target_matches_block_mode(sys_small):
+    """The one-target helper (the FP64 reference of the sampled GPU tests)
+    against block mode, which the invariants above pin: the same target over
+    all sources, and over a subset of sources (block mode on the subset
+    array); its W-inner product with psi_i is the exchange-matrix diagonal
+    -sum_j e_ij."""
+    s, st = sys_small
+    psi = s.psi.numpy()
+    N = psi.shape[0]
+    scale = None
+    for i in range(N):
+        vb, _ = O.apply(psi, st, mode="block", i0=i, Ni=1)
+        vt = O.apply_target(psi, st, i)
+        scale = scale or np.abs(vb).max()
+        assert np.abs(vt - vb[0]).max() <= 1e-14 * scale
+    sub = [2, 0, 3]
+    vt = O.apply_target(psi, st, 2, sources=sub)
+    vb, _ = O.apply(psi[sub], st, mode="block", i0=0, Ni=1)
+    assert np.abs(vt - vb[0]).max() <= 1e-14 * scale
+    pairs = {}
+    O.apply(psi, st, mode="block", i0=1, Ni=1, pairs_out=pairs)
+    diag = float((O.weights3d(st.q) * psi[1] * O.apply_target(psi, st, 1)).sum())
+    assert abs(diag + sum(pairs[(1, j)] for j in range(N))) <= 1e-12 * abs(diag)
+
+
 def test_gradient_central_differences(sys_small):
     s, st = sys_small
     psi = s.psi.numpy()
