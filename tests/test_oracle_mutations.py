@@ -131,3 +131,56 @@ def test_ace_mistakes_are_caught(monkeypatch, mistake):
     monkeypatch.setattr(O, "ace_build", bad_build if mistake != "sign" else orig_build)
     monkeypatch.setattr(O, "ace_apply", bad_apply)
     assert _ace_pins_fail()
+
+
+# ---------------------------------------------------------------------------------------
+# per-pair bases (the sequentially truncated HOSVD)
+# ---------------------------------------------------------------------------------------
+import tests.test_oracle_sthosvd as S  # noqa: E402
+
+
+def _sthosvd_pins_fail():
+    g = W.graded_grid((10, 12, 9), (4.0, 4.5, 3.5), stretch=1.3)
+    psi, _ = W.make_orbitals(g, 2, 3, (0.5, 2.0), seed=71, box=1.5)
+    fixture = (g, psi[0].numpy() * psi[1].numpy())
+    checks = [lambda: S.test_factors_orthonormal_and_full_rank_exact(fixture),
+              lambda: S.test_truncation_error_identity_and_bound(fixture, (4, 5, 3)),
+              S.test_known_multilinear_rank_recovered_and_error_decays,
+              S.test_separable_density_rank_one_energy,
+              S.test_full_rank_per_pair_equals_dense_kernel]
+    for c in checks:
+        try:
+            c()
+        except (AssertionError, ValueError, np.linalg.LinAlgError):
+            return True
+    return False
+
+
+def test_unmutated_sthosvd_passes():
+    assert not _sthosvd_pins_fail()
+
+
+def _st_mutant(mistake):
+    """One plausible mistake in the sequential truncation."""
+    def sthosvd(rho, q, ranks):
+        X = np.asarray(rho, dtype=np.float64)
+        if mistake != "unweighted":
+            for d in range(3):
+                X = O.mode_product(X, np.diag(np.sqrt(q[d])), d)
+        X0 = X.copy()
+        U, cut = [], []
+        for d in range(3):
+            src = X0 if mistake == "not_sequential" else X
+            W_, sv, _ = np.linalg.svd(O.unfold(src, d), full_matrices=False)
+            Ut = W_[:, -ranks[d]:] if mistake == "trailing_vectors" else W_[:, :ranks[d]]
+            cut.append(sv[ranks[d]:] ** 2)
+            X = O.mode_product(X, Ut.T, d)
+            U.append(Ut if mistake == "unscaled_factors" else Ut / np.sqrt(q[d])[:, None])
+        return U, X, cut
+    return sthosvd
+
+
+@pytest.mark.parametrize("mistake", ["unweighted", "not_sequential", "trailing_vectors", "unscaled_factors"])
+def test_sthosvd_mistakes_are_caught(monkeypatch, mistake):
+    monkeypatch.setattr(O, "sthosvd", _st_mutant(mistake))
+    assert _sthosvd_pins_fail(), f"planted mistake {mistake} in the per-pair decomposition went unnoticed"
