@@ -37,7 +37,7 @@ METRIC = "pair convolutions/s for Vx psi, MFMA-FP32 vs FP64 at dE_x<=1e-5 Ha; % 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.0}
 CSRC = os.path.join(ROOT, "paper_2401_04189_amd", "csrc")
 # the sources the core kernel is compiled from (the traffic counters are tied to them)
-KERNEL_SRC = [os.path.join(CSRC, f) for f in ("txe_core.h", "txe_dev.h", "txe_core_f32.hip", "txe_core_f64.hip")]
+KERNEL_SRC = [os.path.join(CSRC, f) for f in ("txe_core.h", "txe_dev.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_core.json")
 TUNE_CACHE = os.path.join(ROOT, "paper_2401_04189_amd", "tuned_shapes.json")
 

@@ -620,6 +620,14 @@ extern "C" txe_status txe_system_conv(const txe_system *sys, int32_t mode, doubl
 // ------------------------------------------------------------------------------------
 // apply
 // ------------------------------------------------------------------------------------
+// One chunk of an apply: its tile of pairs and its back-projection launches.
+struct Chunk {
+  PairMap pm;
+  long long P;
+  int nbr;
+  BackRange br[2];
+};
+
 struct Plan {
   bool f64;
   bool symmetric;
@@ -627,11 +635,11 @@ struct Plan {
   long long npairs;
   int NGS;
   Knobs kn;
-  int tchunk;          // targets per chunk (block mode)
-  long long Pmax;      // pairs per chunk
+  long long Pmax;      // pairs of the largest chunk
   size_t elt;
   size_t psi32_elems;  // FP32 copy of FP64 orbitals for the projection (0: none)
   size_t off_T2, off_G, off_S1, off_epart, off_epair, off_psi32, total;
+  std::vector<Chunk> chunks;
 };
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -641,7 +649,6 @@ static bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
   const char *a0 = (const char *)a, *b0 = (const char *)b;
   return a && b && a0 < b0 + nb && b0 < a0 + na;
 }
-
 
 static void plan_sizes(const Dims &D, Plan &pl) {
   const size_t P = (size_t)pl.Pmax;
@@ -658,7 +665,112 @@ static void plan_sizes(const Dims &D, Plan &pl) {
   pl.total = off;
 }
 
-static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, const Knobs &kn, Plan &pl) {
+// Largest chunk (pairs) whose workspace fits `limit` bytes: plan_sizes is
+// affine in Pmax.
+static long long max_pairs(const Dims &D, Plan &pl, size_t limit) {
+  pl.Pmax = 0;
+  plan_sizes(D, pl);
+  const size_t fixed = pl.total;
+  pl.Pmax = 1;
+  plan_sizes(D, pl);
+  const size_t per = pl.total - fixed + 256 * 4;  // + alignment slack of the four per-pair regions
+  if (pl.total > limit) return 0;
+  return (long long)((limit - fixed) / per);
+}
+
+static PairMap tile(int tri, int ra, int nr, int ca, int nc, int symmetric, int N, int i0) {
+  PairMap m;
+  m.tri = tri; m.ra = ra; m.nr = nr; m.ca = ca; m.nc = nc;
+  m.symmetric = symmetric; m.N = N; m.i0 = i0;
+  return m;
+}
+
+static BackRange brange(int t0, int nt, int s0, int ns, int side, int acc_in, int finish, int out0) {
+  BackRange b;
+  b.t0 = t0; b.nt = nt; b.s0 = s0; b.ns = ns;
+  b.side = side; b.acc_in = acc_in; b.finish = finish; b.out0 = out0;
+  return b;
+}
+
+// Chunks of an apply under a workspace limit.
+//   Symmetric: all unique pairs in one triangle when they fit; otherwise
+//   the orbitals in B blocks of b and the tiles (I, J >= I) row by row: the
+//   triangle of block I, the rectangles (I, J > I) feeding targets I (row
+//   side) and J (column side).  Every target then meets its sources in
+//   ascending order across the tiles.
+//   Block: targets in chunks of tc against all sources; when one target
+//   against all sources does not fit, one target at a time against source
+//   chunks of sc, in ascending order.
+static txe_status plan_chunks(const txe_system *sys, const txe_apply_args *a, Plan &pl, size_t limit) {
+  const Dims &D = sys->D;
+  const long long maxP = max_pairs(D, pl, limit);
+  pl.chunks.clear();
+  if (maxP < 1) {
+    pl.Pmax = 1;
+    plan_sizes(D, pl);
+    return fail(TXE_ERR_NOMEM, "one pair needs %zu workspace bytes (limit %zu)", pl.total, limit);
+  }
+  const int N = a->N;
+  if (pl.symmetric) {
+    if (pl.npairs <= maxP) {
+      pl.chunks.push_back({tile(1, 0, N, 0, N, 1, N, 0), pl.npairs, 1, {brange(0, N, 0, N, 2, 0, 1, 0), {}}});
+    } else {
+      long long b = (long long)std::floor(std::sqrt((double)maxP));
+      while (b > 1 && b * b > maxP) --b;
+      const int B = (int)((N + b - 1) / b);
+      const int bs = (N + B - 1) / B;  // balanced block size (<= b)
+      for (int I = 0; I < B; ++I) {
+        const int ra = I * bs, nr = std::min(bs, N - ra);
+        for (int J = I; J < B; ++J) {
+          const int ca = J * bs, nc = std::min(bs, N - ca);
+          if (nr <= 0 || nc <= 0) continue;
+          Chunk c{};
+          if (I == J) {
+            c.pm = tile(1, ra, nr, ra, nr, 1, N, 0);
+            c.P = (long long)nr * (nr + 1) / 2;
+            c.nbr = 1;
+            c.br[0] = brange(ra, nr, ra, nr, 2, I > 0, I == B - 1, 0);
+          } else {
+            c.pm = tile(0, ra, nr, ca, nc, 1, N, 0);
+            c.P = (long long)nr * nc;
+            c.nbr = 2;
+            c.br[0] = brange(ra, nr, ca, nc, 0, 1, J == B - 1, 0);   // targets I, sources J
+            c.br[1] = brange(ca, nc, ra, nr, 1, I > 0, 0, 0);        // targets J, sources I
+          }
+          pl.chunks.push_back(c);
+        }
+      }
+    }
+  } else {
+    const int i0 = a->i0, Ni = a->Ni;
+    if (N <= maxP) {
+      const int tmax = (int)std::min<long long>(Ni, maxP / N);
+      const int nch = (Ni + tmax - 1) / tmax;
+      const int tc = (Ni + nch - 1) / nch;
+      for (int t = 0; t < Ni; t += tc) {
+        const int nt = std::min(tc, Ni - t);
+        pl.chunks.push_back({tile(0, i0 + t, nt, 0, N, 0, N, i0), (long long)nt * N, 1,
+                             {brange(i0 + t, nt, 0, N, 0, 0, 1, i0), {}}});
+      }
+    } else {
+      const int nsc = (int)((N + maxP - 1) / maxP);
+      const int sc = (N + nsc - 1) / nsc;
+      for (int t = 0; t < Ni; ++t)
+        for (int c0 = 0; c0 < N; c0 += sc) {
+          const int nc = std::min(sc, N - c0);
+          pl.chunks.push_back({tile(0, i0 + t, 1, c0, nc, 0, N, i0), (long long)nc, 1,
+                               {brange(i0 + t, 1, c0, nc, 0, c0 > 0, c0 + nc == N, i0), {}}});
+        }
+    }
+  }
+  pl.Pmax = 0;
+  for (const Chunk &c : pl.chunks) pl.Pmax = std::max(pl.Pmax, c.P);
+  plan_sizes(D, pl);
+  return TXE_OK;
+}
+
+static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, const Knobs &kn, Plan &pl,
+                            size_t limit) {
   const Dims &D = sys->D;
   pl.kn = kn;
   pl.f64 = a->compute == TXE_COMPUTE_F64;
@@ -666,7 +778,8 @@ static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, cons
   pl.want_vx = a->vxpsi != nullptr;
   pl.elt = pl.f64 ? sizeof(double) : sizeof(float);
   // the reduced-precision forms project FP64 orbitals from an FP32 copy
-  // (half the bytes of the projection's orbital reads)
+  // (half the bytes of the projection's orbital reads) when it fits beside
+  // the chunk workspace
   pl.psi32_elems = (!pl.f64 && a->dtype == TXE_DTYPE_F64) ? (size_t)a->N * D.n0 * D.n1 * D.n2 : 0;
   pl.npairs = pl.symmetric ? (long long)a->N * (a->N + 1) / 2 : (long long)a->Ni * a->N;
   const int mt = std::max(D.MT0, std::max(D.MT1, D.MT2));
@@ -677,26 +790,8 @@ static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, cons
   int ngs = (D.r2 + rows - 1) / rows * std::max(1, kn.ngs_mul);
   const int gper = (D.r2 + ngs - 1) / ngs;
   pl.NGS = (D.r2 + gper - 1) / gper;
-  const size_t limit = workspace_limit();
-  if (pl.symmetric) {
-    pl.tchunk = a->N;
-    pl.Pmax = pl.npairs;
-    plan_sizes(D, pl);
-    if (pl.total > limit)
-      return fail(TXE_ERR_NOMEM, "symmetric apply needs %zu workspace bytes (limit %zu); use block mode", pl.total, limit);
-    return TXE_OK;
-  }
-  // block mode: largest target chunk that fits the limit
-  int tc = a->Ni;
-  while (true) {
-    pl.tchunk = tc;
-    pl.Pmax = (long long)tc * a->N;
-    plan_sizes(D, pl);
-    if (pl.total <= limit) break;
-    if (tc == 1) return fail(TXE_ERR_NOMEM, "one target needs %zu workspace bytes (limit %zu)", pl.total, limit);
-    tc = (tc + 1) / 2;
-  }
-  return TXE_OK;
+  if (pl.psi32_elems && pl.psi32_elems * sizeof(float) > limit / 4) pl.psi32_elems = 0;
+  return plan_chunks(sys, a, pl, limit);
 }
 
 // Key of the tuning cache: device architecture and every size that selects
@@ -774,7 +869,7 @@ extern "C" txe_status txe_workspace_query(txe_context *ctx, const txe_system *sy
   txe_status st = validate_args(ctx, sys, args);
   if (st != TXE_OK) return st;
   Plan pl;
-  if ((st = make_plan(sys, args, knobs_for(ctx, sys, args), pl)) != TXE_OK) return st;
+  if ((st = make_plan(sys, args, knobs_for(ctx, sys, args), pl, workspace_limit())) != TXE_OK) return st;
   *bytes = pl.total;
   return ok();
 }
@@ -783,9 +878,6 @@ template <typename T>
 static ChunkArgs<T> chunk_args(const txe_system *sys, const txe_apply_args *a, const Plan &pl, char *ws) {
   ChunkArgs<T> c{};
   c.D = sys->D;
-  c.pm.symmetric = pl.symmetric ? 1 : 0;
-  c.pm.N = a->N;
-  c.pm.i0 = a->i0;
   c.N = a->N;
   c.NGS = pl.NGS;
   c.proj_gt = pl.kn.proj_gt;
@@ -805,24 +897,21 @@ static ChunkArgs<T> chunk_args(const txe_system *sys, const txe_apply_args *a, c
   return c;
 }
 
-// Enqueues one planned apply on stream s with workspace ws (pl.total bytes).
+// Enqueues one planned apply on stream s with workspace ws (pl.total bytes):
+// its chunks in order, then the energy reductions over all pair energies.
 static hipError_t run_plan(const txe_system *sys, const txe_apply_args *args, const Plan &pl, char *ws,
                            hipStream_t s, Prof *prof) {
   hipError_t e = hipSuccess;
   const bool psi64 = args->dtype == TXE_DTYPE_F64;
-  const int nchunks = pl.symmetric ? 1 : (args->Ni + pl.tchunk - 1) / pl.tchunk;
-  for (int ci = 0; ci < nchunks && e == hipSuccess; ++ci) {
-    const int tb = pl.symmetric ? 0 : ci * pl.tchunk;
-    const int tcnt = pl.symmetric ? args->N : std::min(pl.tchunk, args->Ni - tb);
-    const long long p0 = pl.symmetric ? 0 : (long long)tb * args->N;
-    const int P = (int)(pl.symmetric ? pl.npairs : (long long)tcnt * args->N);
+  for (size_t ci = 0; ci < pl.chunks.size() && e == hipSuccess; ++ci) {
+    const Chunk &ch = pl.chunks[ci];
     if (pl.f64) {
       ChunkArgs<double> c = chunk_args<double>(sys, args, pl, ws);
-      c.pm.p0 = p0; c.P = P; c.t_begin = tb; c.t_count = tcnt;
+      c.pm = ch.pm; c.P = (int)ch.P; c.nbr = ch.nbr; c.br[0] = ch.br[0]; c.br[1] = ch.br[1];
       e = run_chunk_f64(sys->t64.t, c, pl.want_vx, s, prof);
     } else {
       ChunkArgs<float> c = chunk_args<float>(sys, args, pl, ws);
-      c.pm.p0 = p0; c.P = P; c.t_begin = tb; c.t_count = tcnt;
+      c.pm = ch.pm; c.P = (int)ch.P; c.nbr = ch.nbr; c.br[0] = ch.br[0]; c.br[1] = ch.br[1];
       if (pl.psi32_elems) {
         c.psi32 = (const float *)(ws + pl.off_psi32);
         c.psi32_fill = ci == 0 ? 1 : 0;
@@ -853,7 +942,7 @@ static txe_status apply_with(txe_context *ctx, const txe_system *sys, const txe_
   if (st != TXE_OK) return st;
   if (ctx->sticky) return fail(TXE_ERR_DEVICE, "context has a previous device error: %s", ctx->sticky_msg.c_str());
   Plan pl;
-  if ((st = make_plan(sys, args, kn, pl)) != TXE_OK) return st;
+  if ((st = make_plan(sys, args, kn, pl, workspace_limit())) != TXE_OK) return st;
   if ((st = ensure_workspace(ctx, pl.total)) != TXE_OK) return st;
   HIP_TRY(hipSetDevice(ctx->device));
   const hipError_t e = run_plan(sys, args, pl, (char *)ctx->ws, ctx->stream, &ctx->prof);
@@ -900,7 +989,8 @@ static txe_status batch_plan(txe_context *ctx, int S, const txe_system *const *s
   for (int i = 0; i < S; ++i) {
     txe_status st = validate_args(ctx, systems[i], &args[i]);
     if (st != TXE_OK) return fail(st, "system %d: %s", i, g_last_error.c_str());
-    if ((st = make_plan(systems[i], &args[i], knobs_for(ctx, systems[i], &args[i]), b.plans[i])) != TXE_OK)
+    if ((st = make_plan(systems[i], &args[i], knobs_for(ctx, systems[i], &args[i]), b.plans[i], workspace_limit())) !=
+        TXE_OK)
       return fail(st, "system %d: %s", i, g_last_error.c_str());
     cost[i] = cost_estimate(systems[i], b.plans[i]);
   }

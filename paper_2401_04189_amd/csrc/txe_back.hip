@@ -20,7 +20,7 @@ namespace txe {
 // -------------------------------------------------------------------------------------
 template <typename T, typename Tin, int NBT, int NCG, bool LDS_TAB>
 __global__ __launch_bounds__(256) void k_back_s(const T *__restrict__ S1, const Tin *__restrict__ psi, Dims D,
-                                              PairMap pm, int N, int t_begin, int t_count, Tables<T> tb,
+                                              PairMap pm, BackRange br, Tables<T> tb,
                                               Tin *__restrict__ vx, const double *__restrict__ out_scale,
                                               int weighted, const double *__restrict__ q0,
                                               const double *__restrict__ q1, const double *__restrict__ q2) {
@@ -43,32 +43,37 @@ __global__ __launch_bounds__(256) void k_back_s(const T *__restrict__ S1, const 
     U2t = s2;
     U1c = s1;
   }
-  const long long total = (long long)t_count * D.n0 * ncg;
+  const long long total = (long long)br.nt * D.n0 * ncg;
   for (long long item = (long long)blockIdx.x * 4 + wave; item < total; item += (long long)gridDim.x * 4) {
   const int cgi = (int)(item % ncg);
   const long long rest = item / ncg;
   const int a = (int)(rest % D.n0);
-  const int t = t_begin + (int)(rest / D.n0);          // local target index
-  const int tglob = pm.symmetric ? t : pm.i0 + t;      // orbital index of the target
+  const int tglob = br.t0 + (int)(rest / D.n0);       // orbital index of the target
   const int c0 = cgi * NCG;
   const size_t plane = (size_t)D.n1 * D.n2;
   const size_t S1pair = (size_t)D.n0 * D.rp2 * D.rp1;
 
+  Tin *out = vx + (size_t)(tglob - br.out0) * D.n0 * plane + (size_t)a * plane;
   acc Acc[NBT][NCG];
 #pragma unroll
   for (int mb = 0; mb < NBT; ++mb)
 #pragma unroll
-    for (int cg = 0; cg < NCG; ++cg) Acc[mb][cg] = zero4<acc>();
-
-  for (int s = 0; s < N; ++s) {
-    long long pg;
-    if (pm.symmetric) {
-      const int i = min(tglob, s), j = max(tglob, s);
-      pg = sym_start(i, pm.N) + (j - i);
-    } else {
-      pg = (long long)t * pm.N + s;
+    for (int cg = 0; cg < NCG; ++cg) {
+      Acc[mb][cg] = zero4<acc>();
+      // raw sums of the target's earlier sources (an earlier chunk)
+      const int c = 16 * (c0 + cg) + lr;
+      if (br.acc_in && mb < nbt && c0 + cg < nct && c < D.n2) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int b = 16 * mb + drow<T>(lg, v);
+          if (b < D.n1) Acc[mb][cg][v] = (T)out[(size_t)b * D.n2 + c];
+        }
+      }
     }
-    const T *S = S1 + (size_t)(pg - pm.p0) * S1pair + (size_t)a * D.rp2 * D.rp1 + lr;
+
+  for (int s = br.s0; s < br.s0 + br.ns; ++s) {
+    const long long pl = local_pair(pm, br, tglob, s);
+    const T *S = S1 + (size_t)pl * S1pair + (size_t)a * D.rp2 * D.rp1 + lr;
     acc X[MAX_MT][NCG];
 #pragma unroll
     for (int mb = 0; mb < MAX_MT; ++mb)
@@ -124,7 +129,6 @@ __global__ __launch_bounds__(256) void k_back_s(const T *__restrict__ S1, const 
     }
   }
   const double scale = out_scale ? *out_scale : 1.0;
-  Tin *out = vx + (size_t)t * D.n0 * plane + (size_t)a * plane;
 #pragma unroll
   for (int mbb = 0; mbb < NBT; ++mbb) {
     if (mbb < nbt) {
@@ -136,9 +140,13 @@ __global__ __launch_bounds__(256) void k_back_s(const T *__restrict__ S1, const 
           for (int v = 0; v < 4; ++v) {
             const int b = 16 * mbb + drow<T>(lg, v);
             if (b < D.n1) {
-              double val = -scale * (double)Acc[mbb][cg][v];
-              if (weighted) val *= q0[a] * q1[b] * q2[c];
-              out[(size_t)b * D.n2 + c] = (Tin)val;
+              if (br.finish) {
+                double val = -scale * (double)Acc[mbb][cg][v];
+                if (weighted) val *= q0[a] * q1[b] * q2[c];
+                out[(size_t)b * D.n2 + c] = (Tin)val;
+              } else {
+                out[(size_t)b * D.n2 + c] = (Tin)Acc[mbb][cg][v];  // raw sum, exact in Tin
+              }
             }
           }
         }
@@ -150,7 +158,7 @@ __global__ __launch_bounds__(256) void k_back_s(const T *__restrict__ S1, const 
 
 template <typename T, typename Tin, typename Tps, int MT, int NBT, int NCG, bool LDS_TAB>
 __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const Tps *__restrict__ psi, Dims D,
-                                                PairMap pm, int N, int t_begin, int t_count, Tables<T> tb,
+                                                PairMap pm, BackRange br, Tables<T> tb,
                                                 Tin *__restrict__ vx, const double *__restrict__ out_scale,
                                                 int weighted, const double *__restrict__ q0,
                                                 const double *__restrict__ q1, const double *__restrict__ q2,
@@ -181,15 +189,15 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
   const T *U1c = LDS_TAB ? s1 : tb.U1chain;
   const size_t plane = (size_t)D.n1 * D.n2;
   const size_t S1pair = (size_t)D.n0 * RP * RP;
-  const long long total = (long long)t_count * D.n0 * ncg;
+  const long long total = (long long)br.nt * D.n0 * ncg;
   // per-lane offsets are 32-bit and unsigned, added to wave-uniform bases
   const unsigned soff = (unsigned)(lg * RP + lr);  // S1 fragment element of this lane
   for (long long item = (long long)blockIdx.x * 4 + wave; item < total; item += (long long)gridDim.x * 4) {
     const int cgi = (int)(item % ncg);
     const long long rest = item / ncg;
     const int a = (int)(rest % D.n0);
-    const int t = t_begin + (int)(rest / D.n0);          // local target index
-    const int tglob = pm.symmetric ? t : pm.i0 + t;      // orbital index of the target
+    const int tglob = br.t0 + (int)(rest / D.n0);       // orbital index of the target
+    Tin *out = vx + (size_t)(tglob - br.out0) * D.n0 * plane + (size_t)a * plane;
     // c tiles of this wavefront (a phantom tile past the last one repeats it
     // and is never stored)
     int ct[NCG];
@@ -217,16 +225,28 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
     for (int mb = 0; mb < NBT; ++mb)
 #pragma unroll
       for (int cg = 0; cg < NCG; ++cg) Acc[mb][cg] = zero4<acc>();
-
-    for (int s = 0; s < N; ++s) {
-      long long pg;
-      if (pm.symmetric) {
-        const int i = min(tglob, s), j = max(tglob, s);
-        pg = sym_start(i, pm.N) + (j - i);
-      } else {
-        pg = (long long)t * pm.N + s;
+    if (br.acc_in) {
+      // raw sums of the target's earlier sources (an earlier chunk)
+#pragma unroll
+      for (int mbb = 0; mbb < NBT; ++mbb) {
+        if (mb0 + mbb >= nbt) break;  // uniform
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg) {
+          const int c = 16 * (cgi * NCG + cg) + lr;
+          if (cgi * NCG + cg < nct && c < D.n2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int b = 16 * (mb0 + mbb) + drow<T>(lg, v);
+              if (b < D.n1) Acc[mbb][cg][v] = (T)out[(size_t)b * D.n2 + c];
+            }
+          }
+        }
       }
-      const auto *S = wave_uniform(S1 + (size_t)(pg - pm.p0) * S1pair + (size_t)a * RP * RP);
+    }
+
+    for (int s = br.s0; s < br.s0 + br.ns; ++s) {
+      const long long pl = local_pair(pm, br, tglob, s);
+      const auto *S = wave_uniform(S1 + (size_t)pl * S1pair + (size_t)a * RP * RP);
       const auto *ps = wave_uniform(psi + (size_t)s * D.n0 * plane + (size_t)a * plane);
       // the U1 fragments do not depend on the source, but holding all of
       // them across the source loop costs NBT * MT * 4 registers: an offset
@@ -290,7 +310,6 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
       }
     }
     const double scale = out_scale ? *out_scale : 1.0;
-    Tin *out = vx + (size_t)t * D.n0 * plane + (size_t)a * plane;
 #pragma unroll
     for (int mbb = 0; mbb < NBT; ++mbb) {
       if (mb0 + mbb >= nbt) break;
@@ -302,9 +321,13 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
           for (int v = 0; v < 4; ++v) {
             const int b = 16 * (mb0 + mbb) + drow<T>(lg, v);
             if (b < D.n1) {
-              double val = -scale * (double)Acc[mbb][cg][v];
-              if (weighted) val *= q0[a] * q1[b] * q2[c];
-              out[(size_t)b * D.n2 + c] = (Tin)val;
+              if (br.finish) {
+                double val = -scale * (double)Acc[mbb][cg][v];
+                if (weighted) val *= q0[a] * q1[b] * q2[c];
+                out[(size_t)b * D.n2 + c] = (Tin)val;
+              } else {
+                out[(size_t)b * D.n2 + c] = (Tin)Acc[mbb][cg][v];  // raw sum, exact in Tin
+              }
             }
           }
         }
@@ -314,9 +337,9 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
 }
 
 template <typename T, typename Tin, int NCG>
-hipError_t launch_back_s_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+hipError_t launch_back_s_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
   const int nct = a.D.nc2 >> 4, nbt = a.D.nb1 >> 4;
-  const long long waves = (long long)a.t_count * a.D.n0 * ((nct + NCG - 1) / NCG);
+  const long long waves = (long long)br.nt * a.D.n0 * ((nct + NCG - 1) / NCG);
   const unsigned nb = blocks_for(waves);
   const Tin *psi = (const Tin *)a.psi;
   Tin *vx = (Tin *)a.vx;
@@ -328,12 +351,10 @@ hipError_t launch_back_s_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStre
 #define TXE_BACK(NBTV)                                                                                         \
   if (lds_tab)                                                                                                   \
     hipLaunchKernelGGL((k_back_s<T, Tin, NBTV, NCG, true>), dim3(nbl), dim3(256), tab, s, a.S1, psi, a.D, a.pm,  \
-                       a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1],         \
-                       a.qdev[2]);                                                                               \
+                       br, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1], a.qdev[2]);                    \
   else                                                                                                           \
     hipLaunchKernelGGL((k_back_s<T, Tin, NBTV, NCG, false>), dim3(nb), dim3(256), 0, s, a.S1, psi, a.D, a.pm,    \
-                       a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1],         \
-                       a.qdev[2])
+                       br, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1], a.qdev[2])
   if (nbt <= 2) TXE_BACK(2);
   else if (nbt <= 4) TXE_BACK(4);
   else if (nbt <= 6) TXE_BACK(6);
@@ -344,9 +365,9 @@ hipError_t launch_back_s_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStre
 }
 
 template <typename T, typename Tin, typename Tps, int MT, int NCG>
-hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
   const int nct = a.D.nc2 >> 4, nbt = a.D.nb1 >> 4;
-  const long long waves = (long long)a.t_count * a.D.n0 * ((nct + NCG - 1) / NCG);
+  const long long waves = (long long)br.nt * a.D.n0 * ((nct + NCG - 1) / NCG);
   const unsigned nb = blocks_for(waves);
   // psi_j as read: the orbitals, or their FP32 copy (the values the FP32
   // kernel rounds them to anyway)
@@ -366,12 +387,10 @@ hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStrea
   do {                                                                                                           \
     if (lds_tab)                                                                                                 \
       hipLaunchKernelGGL((k_back_b<T, Tin, Tps, MT, NBTV, NCG, true>), dim3(nbl), dim3(256), lds, s, a.S1, psi, a.D,  \
-                         a.pm, a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0],           \
-                         a.qdev[1], a.qdev[2], MB0);                                                             \
+                         a.pm, br, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1], a.qdev[2], MB0);      \
     else                                                                                                         \
       hipLaunchKernelGGL((k_back_b<T, Tin, Tps, MT, NBTV, NCG, false>), dim3(nbl), dim3(256), 0, s, a.S1, psi, a.D,   \
-                         a.pm, a.N, a.t_begin, a.t_count, tb, vx, a.out_scale, a.weighted, a.qdev[0],           \
-                         a.qdev[1], a.qdev[2], MB0);                                                             \
+                         a.pm, br, tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1], a.qdev[2], MB0);      \
   } while (0)
   if (nbt <= 2) {
     TXE_BACK(2, 0);
@@ -389,26 +408,26 @@ hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStrea
 }
 
 template <typename T, typename Tin, typename Tps, int NCG>
-hipError_t launch_back_b_tps(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+hipError_t launch_back_b_tps(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
   switch (a.D.MT1) {
-    case 1: return launch_back_b_mt<T, Tin, Tps, 1, NCG>(tb, a, s);
-    case 2: return launch_back_b_mt<T, Tin, Tps, 2, NCG>(tb, a, s);
-    case 3: return launch_back_b_mt<T, Tin, Tps, 3, NCG>(tb, a, s);
-    case 4: return launch_back_b_mt<T, Tin, Tps, 4, NCG>(tb, a, s);
-    case 5: return launch_back_b_mt<T, Tin, Tps, 5, NCG>(tb, a, s);
+    case 1: return launch_back_b_mt<T, Tin, Tps, 1, NCG>(tb, a, br, s);
+    case 2: return launch_back_b_mt<T, Tin, Tps, 2, NCG>(tb, a, br, s);
+    case 3: return launch_back_b_mt<T, Tin, Tps, 3, NCG>(tb, a, br, s);
+    case 4: return launch_back_b_mt<T, Tin, Tps, 4, NCG>(tb, a, br, s);
+    case 5: return launch_back_b_mt<T, Tin, Tps, 5, NCG>(tb, a, br, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T, typename Tin, int NCG>
-hipError_t launch_back_b_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+hipError_t launch_back_b_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
   if constexpr (sizeof(T) == 4 && sizeof(Tin) == 8)
-    if (a.psi32) return launch_back_b_tps<T, Tin, float, NCG>(tb, a, s);
-  return launch_back_b_tps<T, Tin, Tin, NCG>(tb, a, s);
+    if (a.psi32) return launch_back_b_tps<T, Tin, float, NCG>(tb, a, br, s);
+  return launch_back_b_tps<T, Tin, Tin, NCG>(tb, a, br, s);
 }
 
 template <typename T, typename Tin>
-hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
+hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
   // form: streaming (k_back_s, runtime rank loops, high occupancy) or
   // batched (k_back_b, compile-time rank tiles, loads issued per source in
   // batches).  Default: batched, which measured fastest on the 64^3 and
@@ -416,12 +435,15 @@ hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s
   const bool batched = a.back_form ? a.back_form == 2 : true;
   // two c-tiles per wavefront while the b-tile accumulators are few
   const int ncg = a.back_ncg ? a.back_ncg : ((a.D.nb1 >> 4) <= 4 ? 2 : 1);
-  if (batched) return ncg == 2 ? launch_back_b_ncg<T, Tin, 2>(tb, a, s) : launch_back_b_ncg<T, Tin, 1>(tb, a, s);
-  return ncg == 2 ? launch_back_s_ncg<T, Tin, 2>(tb, a, s) : launch_back_s_ncg<T, Tin, 1>(tb, a, s);
+  if (batched) return ncg == 2 ? launch_back_b_ncg<T, Tin, 2>(tb, a, br, s) : launch_back_b_ncg<T, Tin, 1>(tb, a, br, s);
+  return ncg == 2 ? launch_back_s_ncg<T, Tin, 2>(tb, a, br, s) : launch_back_s_ncg<T, Tin, 1>(tb, a, br, s);
 }
 
-template hipError_t launch_back<double, double>(const Tables<double> &, const ChunkArgs<double> &, hipStream_t);
-template hipError_t launch_back<float, double>(const Tables<float> &, const ChunkArgs<float> &, hipStream_t);
-template hipError_t launch_back<float, float>(const Tables<float> &, const ChunkArgs<float> &, hipStream_t);
+template hipError_t launch_back<double, double>(const Tables<double> &, const ChunkArgs<double> &, const BackRange &,
+                                                hipStream_t);
+template hipError_t launch_back<float, double>(const Tables<float> &, const ChunkArgs<float> &, const BackRange &,
+                                               hipStream_t);
+template hipError_t launch_back<float, float>(const Tables<float> &, const ChunkArgs<float> &, const BackRange &,
+                                              hipStream_t);
 
 }  // namespace txe

@@ -19,12 +19,14 @@ namespace txe {
 // -------------------------------------------------------------------------------------
 // pair energies: e_pair[p0 + p] = sum of the core kernel's partials (fixed order)
 // -------------------------------------------------------------------------------------
-__global__ void k_epair(const double *__restrict__ epart, int P, int parts, long long p0, double *__restrict__ epair) {
+__global__ void k_epair(const double *__restrict__ epart, int P, int parts, PairMap pm, double *__restrict__ epair) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   double s = 0.0;
   for (int q = 0; q < parts; ++q) s += epart[(size_t)p * parts + q];
-  epair[p0 + p] = s;
+  int i, j;
+  pair_ij(pm, p, i, j);
+  epair[apply_pair(pm, i, j)] = s;
 }
 
 // E_x = sum_p c_p e_pair[p]; c_p = -1/2 for ordered pairs (block mode) and
@@ -84,6 +86,19 @@ __global__ __launch_bounds__(256) void k_orb(const double *__restrict__ epair, i
 
 namespace {
 
+// the core kernel instance of the largest rank-tile count of the system
+template <typename T>
+hipError_t launch_core(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
+  switch (std::max(a.D.MT0, std::max(a.D.MT1, a.D.MT2))) {
+    case 1: return launch_core_for_mt<T, 1>(tb, a, want_vx, s);
+    case 2: return launch_core_for_mt<T, 2>(tb, a, want_vx, s);
+    case 3: return launch_core_for_mt<T, 3>(tb, a, want_vx, s);
+    case 4: return launch_core_for_mt<T, 4>(tb, a, want_vx, s);
+    case 5: return launch_core_for_mt<T, 5>(tb, a, want_vx, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T, typename Tin>
 hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s, Prof *prof,
                        const BfTables *bft = nullptr, int nsplit = 0) {
@@ -102,15 +117,17 @@ hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx,
   {
     const int parts = a.D.MT1 * a.NGS;
     prof->begin(K_EPAIR, s);
-    hipLaunchKernelGGL(k_epair, dim3((a.P + 255) / 256), dim3(256), 0, s, a.epart, a.P, parts, a.pm.p0, a.epair);
+    hipLaunchKernelGGL(k_epair, dim3((a.P + 255) / 256), dim3(256), 0, s, a.epart, a.P, parts, a.pm, a.epair);
     prof->end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (want_vx) {
-    prof->begin(K_BACK, s);
-    e = launch_back<T, Tin>(tb, a, s);
-    prof->end(s);
-    if (e != hipSuccess) return e;
+    for (int b = 0; b < a.nbr; ++b) {
+      prof->begin(K_BACK, s);
+      e = launch_back<T, Tin>(tb, a, a.br[b], s);
+      prof->end(s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }

@@ -111,7 +111,7 @@ __device__ __forceinline__ void core_epilogue(typename MF<T>::acc (&Phi)[MT][NGW
 // of the A operand is gamma 4(m mod 4) + m / 4) so that its entry v holds
 // gamma 4v + lg too.
 // -------------------------------------------------------------------------------------
-template <typename T, int MT, int NGW, int NW, bool WRITE_S1, int TL>
+template <typename T, int MT, int NGW, int NW, bool WRITE_S1, int TL, int TZ>
 __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Dims D, int P, int NGS, Tables<T> tb,
                                                  T *__restrict__ S1, double *__restrict__ epart) {
   using M = MF<T>;
@@ -147,15 +147,20 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   //          (FP64 at up to two tiles)
   //   LDS_G  the slab in LDS instead (double-buffered; every FP32 form),
   //          each row laid out so a lane reads its fragments with one load
+  //   KM     term-major order (see below): every FP32 form and FP64 at up
+  //          to three tiles; it holds the term's Chat1 fragments and the
+  //          Chat2 fragments of the TZ gamma' tiles this workgroup's split
+  //          meets, with the slab in LDS
   constexpr bool F32 = sizeof(T) == 4;
+  constexpr bool KM = F32 || MT <= 3;
   constexpr bool PF = F32 || MT <= 2;
   constexpr bool C2S = F32 ? MT <= 3 : MT <= 2;
-  constexpr bool HOLD_G = !F32 && C2S && (NW == 4 || MT <= 2);
-  constexpr bool LDS_G = F32 && !HOLD_G;
-  //   KM     term-major order (FP32 with Chat2 held): see below
-  constexpr bool KM = F32 && LDS_G && C2S;
+  constexpr bool HOLD_G = !KM && !F32 && C2S && (NW == 4 || MT <= 2);
+  constexpr bool LDS_G = KM || (F32 && !HOLD_G);
   // slab gamma row (inside its tile) that this lane feeds to the W chain
   const int lrg = F32 ? ((lr & 3) << 2 | (lr >> 2)) : lr;
+  // and the lane that reads slab row gamma (inside its tile) from LDS
+  auto lane_of = [](int g16) { return F32 ? ((g16 & 3) << 2 | (g16 >> 2)) : g16; };
   constexpr int NKT = 4 * (MT - 1) + TL;  // K = 4 steps of the beta contraction
   // LDS slab row beta: for each of the 16 lanes of a fragment its MT gamma
   // values (gamma = 16 mg + lane) side by side, padded to LPL, so a lane
@@ -269,8 +274,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
       const int e = c * CH + j * CHT + tid;
       if (e < (int)F) {
         const int gamma = e % RP;
-        const int gl16 = gamma & 15, ln = (gl16 & 3) << 2 | (gl16 >> 2);  // lane that reads it
-        Gs[buf * SLAB + (e / RP) * SROW + ln * LPL + (gamma >> 4)] = v[j];
+        Gs[buf * SLAB + (e / RP) * SROW + lane_of(gamma & 15) * LPL + (gamma >> 4)] = v[j];
       }
     }
   };
@@ -284,16 +288,19 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   }
   if constexpr (KM) {
     // Term-major order: the outer loop walks the groups of NW terms, the
-    // inner loop the slabs alpha.  Each wavefront holds its term's Chat1 and
-    // Chat2 fragments in registers for all r0 slabs, and one whole slab
+    // inner loop the slabs alpha.  Each wavefront holds its term's Chat1
+    // fragments and the Chat2 fragments of the gamma' tiles of this
+    // workgroup's split in registers for all r0 slabs, and one whole slab
     // streams through the LDS double buffer per step, so the term tables are
     // read once per term group instead of once per (slab, term group).  The
     // sums are the same as in slab-major order (phase B adds the same
     // products to the same Phi accumulators, in another order).
-    // the next slab in 16-byte pieces (RP is a multiple of 16, so a piece
-    // stays inside one beta row): EPS pieces per thread and step
-    constexpr int F4 = (int)(F / 4);
-    constexpr int EPS = (F4 + CHT - 1) / CHT;
+    // The next slab arrives in 16-byte pieces (RP is a multiple of 16, so a
+    // piece stays inside one beta row): EPS pieces per thread and step.
+    typedef typename std::conditional<F32, float4, double2>::type V16;
+    constexpr int PE = 16 / (int)sizeof(T);       // elements per piece
+    constexpr int FP = (int)(F / PE);
+    constexpr int EPS = (FP + CHT - 1) / CHT;
     typedef T AF[NTG][MT];
     auto load_af = [&](int alpha_, int kq_, AF &af) {
 #pragma unroll
@@ -303,38 +310,48 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
         for (int mt = 0; mt < MT; ++mt) af[tg][mt] = ah[16 * mt];
       }
     };
-    auto kslab_load = [&](int a_, float4 (&v)[EPS]) {
-      const float4 *src = reinterpret_cast<const float4 *>(Gp + (size_t)a_ * F);
+    auto kslab_load = [&](int a_, V16 (&v)[EPS]) {
+      const V16 *src = reinterpret_cast<const V16 *>(Gp + (size_t)a_ * F);
 #pragma unroll
-      for (int j = 0; j < EPS; ++j) v[j] = src[min(j * CHT + tid, F4 - 1)];
+      for (int j = 0; j < EPS; ++j) v[j] = src[min(j * CHT + tid, FP - 1)];
     };
-    auto kslab_store = [&](int buf, const float4 (&v)[EPS]) {
+    auto kslab_store = [&](int buf, const V16 (&v)[EPS]) {
 #pragma unroll
       for (int j = 0; j < EPS; ++j) {
         const int e4 = j * CHT + tid;
-        if (e4 < F4) {
-          const int beta = (4 * e4) / RP, g0 = (4 * e4) % RP;
-          const float x[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+        if (e4 < FP) {
+          const int beta = (PE * e4) / RP, g0 = (PE * e4) % RP;
+          const T *x = reinterpret_cast<const T *>(&v[j]);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < PE; ++q) {
             const int gamma = g0 + q;
-            const int gl16 = gamma & 15, ln = (gl16 & 3) << 2 | (gl16 >> 2);
-            Gs[buf * SLAB + beta * SROW + ln * LPL + (gamma >> 4)] = x[q];
+            Gs[buf * SLAB + beta * SROW + lane_of(gamma & 15) * LPL + (gamma >> 4)] = x[q];
           }
         }
       }
     };
+    // the gamma' tiles this workgroup's split meets: mtb .. mtb + nz - 1 (<= TZ)
+    const int mtb = g_lo >> 4;
+    const int nz = min(TZ, ((max(g_hi, g_lo + 1) - 1) >> 4) - mtb + 1);
     T tcb[4 * MT];
-    T c2s[MT][MT][4];
+    T c2s[TZ][MT][4];
     AF afa, afb;
     load_af(0, 0, afa);
+    auto store_z = [&](T *Zw, int mtp, const acc &Zt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gp = 16 * mtp + drow<T>(lg, v);
+        if constexpr (F32) Zw[gp * ZRS + lr] = Zt[v];
+        else if (gp >= g_lo && gp < g_hi) Zw[(gp - g_lo) * 16 + lr] = Zt[v];
+      }
+    };
     auto kstep = [&](const int kq, const int alpha, const int step, AF &cur, AF &nxt) __attribute__((always_inline)) {
       const int k = NW * kq + wave;
       // the next step's slab (alpha + 1, or alpha 0 of the next term group)
       // and phase-B columns, issued before this step's work
       const bool last_a = alpha + 1 == D.r0;
       const bool more = !last_a || kq + 1 < nkq;  // uniform
-      float4 gnext[EPS];
+      V16 gnext[EPS];
       kslab_load(last_a ? 0 : alpha + 1, gnext);
       if (more) load_af(last_a ? 0 : alpha + 1, last_a ? kq + 1 : kq, nxt);
       T *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * ZSS;
@@ -345,45 +362,69 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
 #pragma unroll
         for (int kt = 0; kt < 4 * MT; ++kt) {
           if (kt >= NKT) break;
-          const float4 f =
-              *reinterpret_cast<const float4 *>(Gs + (step & 1) * SLAB + (4 * kt + lg) * SROW + lr * LPL);
-          const T gl[4] = {f.x, f.y, f.z, f.w};
+          const V16 *src = reinterpret_cast<const V16 *>(Gs + (step & 1) * SLAB + (4 * kt + lg) * SROW + lr * LPL);
+          T gl[LPL];
+#pragma unroll
+          for (int q = 0; q < (MT + PE - 1) / PE; ++q) {
+            const V16 f = src[q];
+            const T *x = reinterpret_cast<const T *>(&f);
+#pragma unroll
+            for (int e = 0; e < PE; ++e) gl[PE * q + e] = x[e];
+          }
 #pragma unroll
           for (int mg = 0; mg < MT; ++mg) W[mg] = M::mma(gl[mg], tcb[kt], W[mg]);
         }
-        acc Z[MT];
+        acc Z[TZ];
 #pragma unroll
-        for (int mtp = 0; mtp < MT; ++mtp) Z[mtp] = zero4<acc>();
+        for (int z = 0; z < TZ; ++z) Z[z] = zero4<acc>();
 #pragma unroll
         for (int mg = 0; mg < MT; ++mg)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             if (mg == MT - 1 && v >= TL) break;
 #pragma unroll
-            for (int mtp = 0; mtp < MT; ++mtp) Z[mtp] = M::mma(c2s[mtp][mg][v], W[mg][v], Z[mtp]);
+            for (int z = 0; z < TZ; ++z) Z[z] = M::mma(c2s[z][mg][v], W[mg][v], Z[z]);
           }
 #pragma unroll
-        for (int mtp = 0; mtp < MT; ++mtp)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) Zw[(16 * mtp + drow<T>(lg, v)) * ZRS + lr] = Z[mtp][v];
+        for (int z = 0; z < TZ; ++z)
+          if (z < nz) store_z(Zw, mtb + z, Z[z]);
       } else {
-        for (int idx = lane; idx < (g_hi - g_lo) * 16; idx += 64) Zw[(g_lo + (idx >> 4)) * ZRS + (idx & 15)] = (T)0;
+        if constexpr (F32)
+          for (int idx = lane; idx < (g_hi - g_lo) * 16; idx += 64) Zw[(g_lo + (idx >> 4)) * ZRS + (idx & 15)] = (T)0;
+        else
+          for (int idx = lane; idx < gper * 16; idx += 64) Zw[idx] = (T)0;
       }
       if (more) kslab_store((step + 1) & 1, gnext);
       __syncthreads();
       const T *zb = Zs + (size_t)(step & 1) * zsz + lr;
-      T bz[NTG][NGW];
-#pragma unroll
-      for (int tg = 0; tg < NTG; ++tg)
-#pragma unroll
-        for (int ng = 0; ng < NGW; ++ng) bz[tg][ng] = zb[(4 * tg + lg) * ZSS + min(wg_lo + ng, RP - 1) * ZRS];
-#pragma unroll
-      for (int ng = 0; ng < NGW; ++ng) {
-        if (NW == 8 && ng >= gw) break;
+      if constexpr (F32) {
+        // all Z rows read before the first MFMA
+        T bz[NTG][NGW];
 #pragma unroll
         for (int tg = 0; tg < NTG; ++tg)
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(cur[tg][mt], bz[tg][ng], Phi[mt][ng]);
+          for (int ng = 0; ng < NGW; ++ng) bz[tg][ng] = zb[(4 * tg + lg) * ZSS + min(wg_lo + ng, RP - 1) * ZRS];
+#pragma unroll
+        for (int ng = 0; ng < NGW; ++ng) {
+          if (NW == 8 && ng >= gw) break;
+#pragma unroll
+          for (int tg = 0; tg < NTG; ++tg)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(cur[tg][mt], bz[tg][ng], Phi[mt][ng]);
+        }
+      } else {
+        // FP64: each row's read next to its MFMAs keeps the register file
+        // for the Phi accumulators
+#pragma unroll
+        for (int tg = 0; tg < NTG; ++tg) {
+          const T *zrow = zb + (size_t)(4 * tg + lg) * ZSS;
+#pragma unroll
+          for (int ng = 0; ng < NGW; ++ng) {
+            const T bz = zrow[min(wg_lo - g_lo + ng, gper - 1) * 16];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) Phi[mt][ng] = M::mma(cur[tg][mt], bz, Phi[mt][ng]);
+          }
+        }
       }
     };
     int step = 0;
@@ -392,9 +433,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
       if (k < D.K) {
         load_c1(k, tcb);
 #pragma unroll
-        for (int mtp = 0; mtp < MT; ++mtp)
+        for (int z = 0; z < TZ; ++z)
 #pragma unroll
-          for (int mg = 0; mg < MT; ++mg) load_c2(k, mtp, mg, c2s[mtp][mg]);
+          for (int mg = 0; mg < MT; ++mg) load_c2(k, min(mtb + z, MT - 1), mg, c2s[z][mg]);
       }
       int alpha = 0;
       for (; alpha + 1 < D.r0; alpha += 2, step += 2) {
@@ -611,64 +652,66 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
                                           epart);
 }
 
-template <typename T, int MT, int NGW, int NW, int TL>
+template <typename T, int MT, int NGW, int NW, int TL, int TZ>
 hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
   const int gper = (a.D.r2 + a.NGS - 1) / a.NGS;
   if ((gper + NW - 1) / NW > NGW) return hipErrorInvalidValue;  // the plan gives every wavefront <= NGW rows
   constexpr int RP = 16 * MT;
-  constexpr bool lds_g = sizeof(T) == 4;  // the slab-in-LDS forms of k_core (every FP32 one)
+  constexpr bool km = sizeof(T) == 4 || MT <= 3;   // k_core's term-major forms (slab in LDS)
+  constexpr bool lds_g = km || sizeof(T) == 4;
   constexpr size_t slab = lds_g ? (size_t)RP * 16 * (MT <= 4 ? 4 : 8) : 0;
   const size_t zslot = sizeof(T) == 4 ? (size_t)RP * 20 + 16 : (size_t)gper * 16;  // k_core's Z slot
   const size_t lds = (2 * slab + 2 * NW * zslot) * sizeof(T);
   const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
+  const void *fn = want_vx ? (const void *)k_core<T, MT, NGW, NW, true, TL, TZ>
+                           : (const void *)k_core<T, MT, NGW, NW, false, TL, TZ>;
   if (lds > 64 * 1024) {  // opt in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
-    const void *fn =
-        want_vx ? (const void *)k_core<T, MT, NGW, NW, true, TL> : (const void *)k_core<T, MT, NGW, NW, false, TL>;
     const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
   }
   if (want_vx)
-    hipLaunchKernelGGL((k_core<T, MT, NGW, NW, true, TL>), dim3(nb), dim3(64 * NW), lds, s, a.G, a.D, a.P, a.NGS, tb,
-                       a.S1, a.epart);
+    hipLaunchKernelGGL((k_core<T, MT, NGW, NW, true, TL, TZ>), dim3(nb), dim3(64 * NW), lds, s, a.G, a.D, a.P, a.NGS,
+                       tb, a.S1, a.epart);
   else
-    hipLaunchKernelGGL((k_core<T, MT, NGW, NW, false, TL>), dim3(nb), dim3(64 * NW), lds, s, a.G, a.D, a.P, a.NGS, tb,
-                       a.S1, a.epart);
+    hipLaunchKernelGGL((k_core<T, MT, NGW, NW, false, TL, TZ>), dim3(nb), dim3(64 * NW), lds, s, a.G, a.D, a.P,
+                       a.NGS, tb, a.S1, a.epart);
   return hipGetLastError();
 }
 
-
-// FP32: one core per count of live chunks in the last tile of modes 1 and 2
-template <int MT, int NGW, int NW>
-hipError_t launch_core_f32_tl(const Tables<float> &tb, const ChunkArgs<float> &a, bool want_vx, hipStream_t s) {
-  const int rt = max(a.D.r1, a.D.r2) - 16 * (MT - 1);
-  switch (min(4, max(1, (rt + 3) / 4))) {
-    case 1: return launch_core_mt<float, MT, NGW, NW, 1>(tb, a, want_vx, s);
-    case 2: return launch_core_mt<float, MT, NGW, NW, 2>(tb, a, want_vx, s);
-    case 3: return launch_core_mt<float, MT, NGW, NW, 3>(tb, a, want_vx, s);
-    default: return launch_core_mt<float, MT, NGW, NW, 4>(tb, a, want_vx, s);
+// gamma' tiles the widest split of the plan meets
+inline int split_tiles(const Dims &D, int NGS) {
+  const int gper = (D.r2 + NGS - 1) / NGS;
+  int need = 1;
+  for (int gs = 0; gs < NGS; ++gs) {
+    const int lo = gs * gper, hi = std::min(D.r2, lo + gper);
+    if (lo < hi) need = std::max(need, (hi - 1) / 16 - lo / 16 + 1);
   }
+  return need;
 }
 
-template <typename T>
-hipError_t launch_core(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
-  const int mt = max(a.D.MT0, max(a.D.MT1, a.D.MT2));
-  if constexpr (sizeof(T) == 8) {
-    switch (mt) {
-      case 1: return launch_core_mt<T, 1, NGW64[1], 4, 4>(tb, a, want_vx, s);
-      case 2: return launch_core_mt<T, 2, NGW64[2], 4, 4>(tb, a, want_vx, s);
-      case 3: return launch_core_mt<T, 3, NGW64[3], 4, 4>(tb, a, want_vx, s);
-      case 4: return launch_core_mt<T, 4, NGW64[4], 4, 4>(tb, a, want_vx, s);
-      case 5: return launch_core_mt<T, 5, NGW64[5], 4, 4>(tb, a, want_vx, s);
-    }
-  } else {
-    switch (mt) {
-      case 1: return launch_core_f32_tl<1, NGW32x8[1], 8>(tb, a, want_vx, s);
-      case 2: return launch_core_f32_tl<2, NGW32x8[2], 8>(tb, a, want_vx, s);
-      case 3: return launch_core_f32_tl<3, NGW32x8[3], 8>(tb, a, want_vx, s);
-      case 4: return launch_core_f32_tl<4, NGW32[4], 4>(tb, a, want_vx, s);
-      case 5: return launch_core_f32_tl<5, NGW32[5], 4>(tb, a, want_vx, s);
-    }
+// One rank-tile count: the live chunks TL of the last tile of modes 1 and 2
+// and the held gamma' tiles TZ (3 when the split meets at most three tiles,
+// else all MT) select the instance.
+template <typename T, int MT>
+hipError_t launch_core_for_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
+  constexpr bool f64 = sizeof(T) == 8;
+  constexpr int NW = f64 ? 4 : NW32[MT];
+  constexpr int NGW = f64 ? NGW64[MT] : (NW == 8 ? NGW32x8[MT] : NGW32[MT]);
+  constexpr int TZ3 = MT <= 3 ? MT : 3;
+  const bool narrow = split_tiles(a.D, a.NGS) <= TZ3;
+  const int rt = std::max(a.D.r1, a.D.r2) - 16 * (MT - 1);
+  const int tl = std::min(4, std::max(1, (rt + 3) / 4));
+#define TXE_CORE_TL(TLV)                                                               \
+  case TLV:                                                                            \
+    return narrow ? launch_core_mt<T, MT, NGW, NW, TLV, TZ3>(tb, a, want_vx, s)        \
+                  : launch_core_mt<T, MT, NGW, NW, TLV, MT>(tb, a, want_vx, s);
+  switch (tl) {
+    TXE_CORE_TL(1)
+    TXE_CORE_TL(2)
+    TXE_CORE_TL(3)
+    TXE_CORE_TL(4)
   }
+#undef TXE_CORE_TL
   return hipErrorInvalidValue;
 }
 

@@ -1,0 +1,6 @@
+// FP32 MFMA instances of the core kernel: five rank tiles.
+#include "txe_core.h"
+
+namespace txe {
+template hipError_t launch_core_for_mt<float, 5>(const Tables<float> &, const ChunkArgs<float> &, bool, hipStream_t);
+}  // namespace txe

@@ -103,21 +103,45 @@ __device__ __forceinline__ int xcd_order(int b, int nb) {
   return x * q + min(x, rem) + slot;
 }
 
-__device__ __forceinline__ void pair_ij(const PairMap &pm, long long pg, int &i, int &j) {
-  if (!pm.symmetric) {
-    i = pm.i0 + (int)(pg / pm.N);
-    j = (int)(pg % pm.N);
-    return;
-  }
-  const double Nd = (double)pm.N;
-  const double b = 2.0 * Nd + 1.0;
-  long long ii = (long long)floor((b - sqrt(b * b - 8.0 * (double)pg)) * 0.5);
+// row r <= column c of triangle index p of an n x n triangle numbered row by
+// row (p = r n - r(r-1)/2 + (c - r))
+__device__ __forceinline__ void tri_rc(long long p, int n, int &r, int &c) {
+  const double b = 2.0 * (double)n + 1.0;
+  long long ii = (long long)floor((b - sqrt(b * b - 8.0 * (double)p)) * 0.5);
   if (ii < 0) ii = 0;
-  if (ii > pm.N - 1) ii = pm.N - 1;
-  while (ii > 0 && sym_start(ii, pm.N) > pg) --ii;
-  while (ii + 1 < pm.N && sym_start(ii + 1, pm.N) <= pg) ++ii;
-  i = (int)ii;
-  j = (int)(ii + (pg - sym_start(ii, pm.N)));
+  if (ii > n - 1) ii = n - 1;
+  while (ii > 0 && sym_start(ii, n) > p) --ii;
+  while (ii + 1 < n && sym_start(ii + 1, n) <= p) ++ii;
+  r = (int)ii;
+  c = (int)(ii + (p - sym_start(ii, n)));
+}
+
+// orbitals (i, j) of local pair p of a tile
+__device__ __forceinline__ void pair_ij(const PairMap &pm, long long p, int &i, int &j) {
+  if (pm.tri) {
+    int r, c;
+    tri_rc(p, pm.nr, r, c);
+    i = pm.ra + r;
+    j = pm.ra + c;
+  } else {
+    i = pm.ra + (int)(p / pm.nc);
+    j = pm.ca + (int)(p % pm.nc);
+  }
+}
+
+// the apply's number of pair (i, j) (i <= j in symmetric mode)
+__device__ __forceinline__ long long apply_pair(const PairMap &pm, int i, int j) {
+  return pm.symmetric ? sym_start(i, pm.N) + (j - i) : (long long)(i - pm.i0) * pm.N + j;
+}
+
+// local pair of target t and source s in a back-projection launch
+__device__ __forceinline__ long long local_pair(const PairMap &pm, const BackRange &br, int t, int s) {
+  if (br.side == 2) {
+    const int r = min(t, s) - pm.ra, c = max(t, s) - pm.ra;
+    return sym_start(r, pm.nr) + (c - r);
+  }
+  if (br.side == 0) return (long long)(t - pm.ra) * pm.nc + (s - pm.ca);
+  return (long long)(s - pm.ra) * pm.nc + (t - pm.ca);
 }
 
 

@@ -29,14 +29,31 @@ struct Dims {
   int K, Kp;                  // Gaussian terms, and K rounded up to KCHUNK
 };
 
-// Pair enumeration: symmetric mode numbers the unique pairs i <= j row by
-// row (pair (i,j) at i*N - i(i-1)/2 + (j-i)); block mode numbers target
-// t (orbital i0+t) against source j at t*N + j.
+// The pairs of one chunk: a tile of orbital pairs, either the rectangle
+// rows x cols (block mode: targets x sources; symmetric mode: the pairs
+// i < j between two disjoint orbital blocks) or the triangle i <= j of one
+// orbital block (symmetric mode).  Local pair p numbers the tile row by row:
+// rectangle (i - ra) * nc + (j - ca), triangle r * nr - r(r-1)/2 + (c - r)
+// with r = i - ra, c = j - ra.  The apply numbers all of its pairs (the pair
+// energies) as symmetric: i*N - i(i-1)/2 + (j-i), block: (i - i0)*N + j.
 struct PairMap {
-  int symmetric;
-  int N;
-  int i0;
-  long long p0;               // global index of the chunk's first pair
+  int tri;                    // 1: triangle of the rows (cols = rows), 0: rectangle
+  int ra, nr;                 // first orbital and count of the rows
+  int ca, nc;                 // first orbital and count of the columns
+  int symmetric, N, i0;       // the apply's numbering
+};
+
+// One back-projection launch over a chunk: targets [t0, t0 + nt) against
+// sources [s0, s0 + ns).  side 0: the targets are the tile's rows (pair
+// (t, s)); 1: its columns (pair (s, t)); 2: triangle (pair (min, max)).
+// acc_in: start from the raw sums an earlier chunk left in vx; finish: write
+// -scale * sum (times w when weighted) instead of the raw sum.  Each target's
+// sources are visited in ascending order across the chunks of an apply, so a
+// chunked apply adds the same terms in the same order as a single chunk.
+// Output row of target t: t - out0.
+struct BackRange {
+  int t0, nt, s0, ns;
+  int side, acc_in, finish, out0;
 };
 
 // Device copies of the setup tables in one compute precision.  Every table
@@ -83,8 +100,9 @@ struct ChunkArgs {
   Dims D;
   PairMap pm;
   int P;                      // pairs in the chunk
-  int N;                      // sources (all orbitals)
-  int t_begin, t_count;       // targets of the back-projection (local target indices)
+  int N;                      // orbitals of the apply
+  BackRange br[2];            // back-projection launches of the chunk (nbr of them)
+  int nbr;
   int NGS;                    // gamma' splits in the core kernel
   int proj_gt;                // gamma tiles per wavefront in proj12 (1, 2 or 3)
   int back_ncg;               // c tiles per wavefront in back (1 or 2; 0 = by size)
@@ -102,7 +120,7 @@ struct ChunkArgs {
   const double *qdev[3];
   T *T2, *G, *S1;
   double *epart;              // [P][MT1][NGS]
-  double *epair;              // all pairs of the apply, global index
+  double *epair;              // all pairs of the apply, in the apply's numbering
 };
 
 // Optional per-kernel timing with HIP events recorded on the launch stream.
@@ -174,13 +192,13 @@ struct Prof {
 // (FP64 / FP32 MFMA, or split bf16 with NS parts), back-projection.
 template <typename T, typename Tin>
 hipError_t launch_projection(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s, Prof *prof);
-template <typename T>
-hipError_t launch_core(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s);
+template <typename T, int MT>
+hipError_t launch_core_for_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s);
 template <int NS>
 hipError_t launch_core_bf(const Tables<float> &tb, const BfTables &bft, const ChunkArgs<float> &a, bool want_vx,
                           hipStream_t s);
 template <typename T, typename Tin>
-hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s);
+hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s);
 
 // Runs one chunk (projection, core sum, back-projection, pair energies).
 // Returns hipSuccess or the first launch error.

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dim
   const int a = (int)(rest % D.n0);
   const int p = (int)(rest / D.n0);
   int i, j;
-  pair_ij(pm, pm.p0 + p, i, j);
+  pair_ij(pm, p, i, j);
   const size_t plane = (size_t)D.n1 * D.n2;
   const Tin *pi = psi + ((size_t)i * D.n0 + a) * plane;
   const Tin *pj = psi + ((size_t)j * D.n0 + a) * plane;
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_proj12m(const Tin *__restrict__ psi, Di
     const int a = (int)(item % D.n0);
     const int p = (int)(item / D.n0);
     int i, j;
-    pair_ij(pm, pm.p0 + p, i, j);
+    pair_ij(pm, p, i, j);
     const Tin *pi = psi + ((size_t)i * D.n0 + a) * plane;
     const Tin *pj = psi + ((size_t)j * D.n0 + a) * plane;
     acc T2a[MT][MT];

@@ -8,7 +8,6 @@ FP64 path: |dE_x| <= 1e-5 Ha absolute (the reduced-precision gate) for every
 form; Vx psi and e_ij relative errors at 1e-5 (FP32, bf16 x6) or 2e-4 (bf16
 x3, whose products keep ~16 bits per operand).
 """
-GATE_HA = 1e-5
 import numpy as np
 import pytest
 import torch
@@ -19,6 +18,7 @@ from paper_2401_04189_amd import txe, workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-9
+GATE_HA = 1e-5   # reduced precision: |dE_x| against the GPU FP64 path
 
 
 @pytest.fixture(scope="module")
@@ -193,6 +193,56 @@ def test_f32_block_chunked(ctx, monkeypatch):
         assert torch.equal(vx, full[c][0]) and torch.equal(ep, full[c][2])
         assert float(ex) == float(full[c][1])
     monkeypatch.delenv("TXE_TEST_MAX_WORKSPACE")
+    sysm.close()
+
+
+@pytest.mark.parametrize("comp", ["f64", "f32", "bf16x3"])
+def test_symmetric_chunked_bitwise(ctx, monkeypatch, comp):
+    """Symmetric mode split into triangular and rectangular pair tiles (forced
+    by small workspace limits: 3 and 6 orbital blocks) adds every target's
+    sources in the same order as one chunk, so Vx psi (also scaled and
+    weighted), E_x, the pair energies and the exchange-matrix diagonal are
+    bitwise those of one chunk."""
+    s = W.small_system(n=16, L=5.0, N=11, r=7, K=8, seed=42)
+    sysm = txe.System.from_workload(ctx, s)
+    # reduced forms on FP32 orbitals: with FP64 orbitals a small limit also
+    # drops the FP32 orbital copy, which rounds the pair densities differently
+    psi = s.psi.cuda() if comp == "f64" else s.psi.cuda().float()
+    scale = torch.tensor(-1.75, dtype=torch.float64, device="cuda")
+    kw = dict(compute=comp, want_pairs=True, want_orb=True)
+    one = txe.apply(ctx, sysm, psi, **kw)
+    onew = txe.apply(ctx, sysm, psi, out_scale=scale, out_weighted=True, **kw)
+    torch.cuda.synchronize()
+    need = txe.workspace_bytes(ctx, sysm, psi, compute=comp)
+    for frac in (6, 25):
+        monkeypatch.setenv("TXE_TEST_MAX_WORKSPACE", str(need // frac))
+        for ref, extra in ((one, {}), (onew, dict(out_scale=scale, out_weighted=True))):
+            got = txe.apply(ctx, sysm, psi, **kw, **extra)
+            torch.cuda.synchronize()
+            for a, b in zip(got, ref):
+                assert torch.equal(a, b), f"limit need/{frac}"
+        monkeypatch.delenv("TXE_TEST_MAX_WORKSPACE")
+    sysm.close()
+
+
+def test_block_source_chunks_bitwise(ctx, monkeypatch):
+    """Block mode where one target against all sources exceeds the workspace:
+    one target at a time against ascending source chunks, bitwise equal to
+    one chunk in both precisions."""
+    s = W.small_system(n=16, L=5.0, N=9, r=7, K=8, seed=43)
+    sysm = txe.System.from_workload(ctx, s)
+    for comp in ("f64", "f32"):
+        psi = s.psi.cuda() if comp == "f64" else s.psi.cuda().float()
+        ref = txe.apply(ctx, sysm, psi, compute=comp, symmetric=False, i0=2, Ni=5, want_pairs=True, want_orb=True)
+        torch.cuda.synchronize()
+        # room for about three pairs: fewer than the nine sources of one target
+        full = txe.workspace_bytes(ctx, sysm, psi, compute=comp, symmetric=False, i0=2, Ni=5)
+        monkeypatch.setenv("TXE_TEST_MAX_WORKSPACE", str(full // 14))
+        got = txe.apply(ctx, sysm, psi, compute=comp, symmetric=False, i0=2, Ni=5, want_pairs=True, want_orb=True)
+        torch.cuda.synchronize()
+        monkeypatch.delenv("TXE_TEST_MAX_WORKSPACE")
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), comp
     sysm.close()
 
 
