@@ -210,6 +210,28 @@ txe_status txe_workspace_query(txe_context *ctx, const txe_system *sys, const tx
  * the context stream without waiting. */
 txe_status txe_apply(txe_context *ctx, const txe_system *sys, const txe_apply_args *args);
 
+/* Bytes of the per-GPU device array txe_apply_noalloc works in. */
+#define TXE_NOALLOC_SCRATCH_BYTES ((size_t)512 << 20)
+
+/* Allocation-free apply, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same arguments, outputs and validation as txe_apply, but
+ * the workspace is a file-scope device array of TXE_NOALLOC_SCRATCH_BYTES per
+ * GPU, held from context creation (where its address is looked up, once per
+ * device) until the process ends, instead of the context's workspace; the
+ * apply is planned in pair chunks that fit it.  The reduced-precision forms
+ * read FP64 orbitals directly when their FP32 copy would not fit beside the
+ * chunk workspace (the pair densities are then rounded from FP64), so their
+ * results can differ from txe_apply's in the last bits; FP64 results are
+ * bitwise those of txe_apply.  Calls no hipMalloc / hipFree and records no
+ * timing events.  Errors: as txe_apply, plus TXE_ERR_NOMEM when one pair's
+ * workspace exceeds the array and TXE_ERR_DEVICE when the array's address
+ * could not be obtained on this device.  Every call on one GPU shares that
+ * GPU's array and leaves its contents behind (nothing in it needs to start
+ * at zero): calls that overlap on one GPU (other streams or contexts) race on
+ * it, so the caller must order them. */
+txe_status txe_apply_noalloc(txe_context *ctx, const txe_system *sys, const txe_apply_args *args);
+
 /* Batched apply: S independent problems (each its own system, orbitals and
  * outputs, e.g. the uneven molecules of a screening run) enqueued as one
  * unit.  The systems are spread over `lanes` concurrent HIP streams

@@ -155,6 +155,12 @@ extern "C" txe_status txe_context_create(int32_t device, void *hip_stream, txe_c
   if (device < 0 || device >= ndev) return fail(TXE_ERR_ARG, "device %d not in [0, %d)", device, ndev);
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, device));
+  // set-up of the allocation-free apply's scratch array on this device (its
+  // address is looked up once per device and kept; a failure is reported by
+  // txe_apply_noalloc)
+  HIP_TRY(hipSetDevice(device));
+  void *scr = nullptr;
+  (void)scratch_address(device, &scr);
   auto *c = new txe_context();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
@@ -946,6 +952,28 @@ static txe_status apply_with(txe_context *ctx, const txe_system *sys, const txe_
   if ((st = ensure_workspace(ctx, pl.total)) != TXE_OK) return st;
   HIP_TRY(hipSetDevice(ctx->device));
   const hipError_t e = run_plan(sys, args, pl, (char *)ctx->ws, ctx->stream, &ctx->prof);
+  if (e != hipSuccess) return device_failed(ctx, e);
+  return ok();
+}
+
+extern "C" txe_status txe_apply_noalloc(txe_context *ctx, const txe_system *sys, const txe_apply_args *args) {
+  if (!ctx || !sys || !args) return fail(TXE_ERR_ARG, "null argument");
+  txe_status st = validate_args(ctx, sys, args);
+  if (st != TXE_OK) return st;
+  if (ctx->sticky) return fail(TXE_ERR_DEVICE, "context has a previous device error: %s", ctx->sticky_msg.c_str());
+  Plan pl;
+  if ((st = make_plan(sys, args, knobs_for(ctx, sys, args), pl, TXE_NOALLOC_SCRATCH_BYTES)) != TXE_OK)
+    return st == TXE_ERR_NOMEM ? fail(st, "allocation-free apply: %s (scratch array of %zu bytes)",
+                                      g_last_error.c_str(), (size_t)TXE_NOALLOC_SCRATCH_BYTES)
+                               : st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  void *ws = nullptr;
+  const hipError_t es = scratch_address(ctx->device, &ws);
+  if (es != hipSuccess || !ws)
+    return fail(TXE_ERR_DEVICE, "the scratch array of device %d is unavailable: %s", ctx->device,
+                hipGetErrorString(es));
+  Prof off;  // no timing events on this path
+  const hipError_t e = run_plan(sys, args, pl, (char *)ws, ctx->stream, &off);
   if (e != hipSuccess) return device_failed(ctx, e);
   return ok();
 }

@@ -226,6 +226,10 @@ hipError_t ace_chol_inv(const double *M, int N, double *L, double *T, int *info,
 hipError_t ace_comb(bool x64, bool o64, const double *A, int MR, int K, const void *X, long long ng, double scale,
                     int lower, void *out, hipStream_t s);
 
+// Device address of the allocation-free apply's scratch array on `device`
+// (txe_scratch.hip; the current device must be `device`).
+hipError_t scratch_address(int device, void **ptr);
+
 // Ceiling microbenchmarks (txe_ceiling.hip): kind 0 f64, 1 f32, 2 bf16 MFMA
 // in TFLOP/s; 3 HBM stream in GB/s.  Allocates, synchronises the stream.
 hipError_t measure_ceiling(int kind, hipStream_t s, double *value);

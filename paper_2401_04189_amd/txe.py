@@ -71,6 +71,7 @@ SIGNATURES = {
     "txe_workspace_query": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs),
                                      ctypes.POINTER(ctypes.c_size_t)]),
     "txe_apply": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs)]),
+    "txe_apply_noalloc": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs)]),
     "txe_profile_enable": (_c_int, [ctypes.c_void_p, _c_int]),
     "txe_profile_read": (_c_int, [ctypes.c_void_p, _c_int, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]),
@@ -319,6 +320,20 @@ def apply(ctx: Context, sysm: System, psi, compute="f64", symmetric=True, i0=0, 
                    want_orb)
     ctx.set_stream(torch.cuda.current_stream(psi.device))
     _check(lib().txe_apply(ctx.h, sysm.h, ctypes.byref(out[0])))
+    return tuple(out[1:])
+
+
+def apply_noalloc(ctx: Context, sysm: System, psi, compute="f64", symmetric=True, i0=0, Ni=None, want_vx=True,
+                  want_pairs=False, out_scale=None, out_weighted=False, vx_out=None, want_orb=False):
+    """As apply(), through txe_apply_noalloc: the library allocates nothing
+    (its workspace is a fixed device array per GPU); the outputs are
+    allocated here unless given."""
+    import torch
+
+    out = _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_scale, out_weighted, vx_out,
+                   want_orb)
+    ctx.set_stream(torch.cuda.current_stream(psi.device))
+    _check(lib().txe_apply_noalloc(ctx.h, sysm.h, ctypes.byref(out[0])))
     return tuple(out[1:])
 
 
