@@ -32,6 +32,15 @@ time, in the order the paper gives the steps:
         W_i = Vx psi_i, the matrix M_ij = <psi_i, W_j>_W, its Cholesky factor
         M = -L L^T, the projection vectors xi_k = sum_i W_i (L^-1)_ki (eq.
         `eta`) and the operator V_ACE = -sum_k xi_k <xi_k, .>_W.
+  * O9  Discretisation as the paper states it (section "Convolution
+        operation" and the S-FE mesh of section "Creation of Structured FE
+        basis"): 1-D meshes of cells with Lagrange elements of order p, the
+        nodes of a cell at its Gauss-Lobatto-Legendre points, the end nodes
+        of the domain held at zero; the convolution matrices of eqs.
+        `quadVal` / `discInteg` for those elements; and the convolution
+        evaluated at every 1-D node and reconstructed (eq. `final`):
+        phi_ij = sum_k w_k G x0 (C_k^0 U0) x1 (C_k^1 U1) x2 (C_k^2 U2), with
+        e_ij = <rho_ij, phi_ij>_W on the grid.
   * O8  Per-pair bases (section "Convolution operation", eq.
         `TuckerDecompField` with factors f_ij, g_ij, h_ij of each pair): the
         sequentially truncated HOSVD of each pair density (modes 0, 1, 2 in
@@ -303,6 +312,123 @@ def apply_sthosvd(psi, st: Setup, ranks, mode="symmetric", i0=0, Ni=None, pairs_
     for t, i in enumerate(range(i0, i0 + Ni)):
         for j in range(N):
             phi, e, _, _, _ = pair_sthosvd(psi[i], psi[j], st, ranks)
+            if pairs_out is not None:
+                pairs_out[(i, j)] = e
+            vx[t] -= psi[j] * phi
+            ex += -0.5 * e
+    return vx, ex
+
+
+# ---------------------------------------------------------------------------------------
+# O9: Lagrange elements of order p, their convolution matrices, and collocation
+# ---------------------------------------------------------------------------------------
+def gll_points(p):
+    """The p + 1 Gauss-Lobatto-Legendre points of [-1, 1] (the ends and the
+    roots of P_p'), and their quadrature weights 2 / (p (p+1) P_p(s)^2)."""
+    Pp = np.polynomial.legendre.Legendre.basis(p)
+    inner = np.sort(Pp.deriv().roots().real) if p > 1 else np.array([])
+    s = np.concatenate([[-1.0], inner, [1.0]])
+    w = 2.0 / (p * (p + 1) * Pp(s) ** 2)
+    return s, w
+
+
+def fe_mesh_1d(edges, p):
+    """Nodes and nodal quadrature weights of a 1-D mesh of cells
+    [edges[e], edges[e+1]] with order-p Lagrange elements at the GLL points of
+    each cell; the two end nodes of the domain carry zero (Dirichlet) and are
+    not unknowns.  Returns (x, q, cells): the n = ncell p - 1 unknown nodes,
+    their weights (GLL weight times half the cell length, summed over the
+    cells a node belongs to), and per cell the node indices of its p + 1
+    points (-1 for a held end node)."""
+    edges = np.asarray(edges, dtype=np.float64)
+    s, w = gll_points(p)
+    nc = len(edges) - 1
+    xs = np.zeros(nc * p + 1)
+    qs = np.zeros(nc * p + 1)
+    cells = []
+    for e in range(nc):
+        lo, hi = edges[e], edges[e + 1]
+        idx = e * p + np.arange(p + 1)
+        xs[idx] = lo + 0.5 * (s + 1.0) * (hi - lo)
+        qs[idx] += w * 0.5 * (hi - lo)
+        cells.append(idx - 1)
+    cells = [np.where((c < 0) | (c >= nc * p - 1), -1, c) for c in cells]
+    return xs[1:-1], qs[1:-1], cells
+
+
+def lagrange_eval(nodes, k, t):
+    """The k-th Lagrange polynomial of `nodes` at points t."""
+    out = np.ones_like(t)
+    for m, xm in enumerate(nodes):
+        if m != k:
+            out *= (t - xm) / (nodes[k] - xm)
+    return out
+
+
+def conv_matrix_fe(edges, p, alpha, order=_GL_ORDER):
+    """C[a, b] = int exp(-alpha (x_a - t)^2) N_b(t) dt for the order-p
+    Lagrange basis N_b of fe_mesh_1d (eqs. `quadVal`, `discInteg`), by
+    composite Gauss-Legendre quadrature on every cell, cut into pieces of
+    width at most 1/(4 sqrt(alpha))."""
+    x, _, cells = fe_mesh_1d(edges, p)
+    edges = np.asarray(edges, dtype=np.float64)
+    s, _ = gll_points(p)
+    t_ref, w_ref = np.polynomial.legendre.leggauss(order)
+    C = np.zeros((len(x), len(x)))
+    for e, idx in enumerate(cells):
+        lo, hi = edges[e], edges[e + 1]
+        nodes = lo + 0.5 * (s + 1.0) * (hi - lo)
+        width = hi - lo
+        m = 1 if alpha <= 0 else max(1, int(math.ceil(width * 4.0 * math.sqrt(alpha))))
+        cuts = lo + width * np.arange(m + 1) / m
+        a_, b_ = cuts[:-1, None], cuts[1:, None]
+        t = (0.5 * (b_ - a_) * t_ref[None, :] + 0.5 * (a_ + b_)).reshape(-1)
+        wt = (0.5 * (b_ - a_) * w_ref[None, :]).reshape(-1)
+        kern = np.exp(-alpha * (x[:, None] - t[None, :]) ** 2) * wt[None, :]
+        for k, b in enumerate(idx):
+            if b >= 0:
+                C[:, b] += kern @ lagrange_eval(nodes, k, t)
+    return C
+
+
+def pair_collocation(psi_i, psi_j, st: Setup):
+    """(phi_ij, e_ij) with the convolution evaluated at every 1-D node and
+    reconstructed: phi = sum_k w_k G x0 (C_k^0 U0) x1 (C_k^1 U1) x2 (C_k^2 U2),
+    e_ij = <rho_ij, phi>_W (grid sum)."""
+    rho = psi_i * psi_j
+    G = project(rho, st.V)
+    phi = np.zeros_like(rho)
+    for k in range(len(st.w)):
+        T = G
+        for d in range(3):
+            T = mode_product(T, st.C[d][k] @ st.U[d], d)
+        phi += st.w[k] * T
+    return phi, float((weights3d(st.q) * rho * phi).sum())
+
+
+def apply_collocation(psi, st: Setup, mode="symmetric", i0=0, Ni=None, pairs_out=None):
+    """Vx psi and E_x with the collocation form of every pair (O4, O5)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    N = psi.shape[0]
+    if mode == "symmetric":
+        vx = np.zeros_like(psi)
+        ex = 0.0
+        for i in range(N):
+            for j in range(i, N):
+                phi, e = pair_collocation(psi[i], psi[j], st)
+                if pairs_out is not None:
+                    pairs_out[(i, j)] = e
+                vx[i] -= psi[j] * phi
+                if j != i:
+                    vx[j] -= psi[i] * phi
+                ex += -0.5 * e if i == j else -e
+        return vx, ex
+    Ni = N - i0 if Ni is None else Ni
+    vx = np.zeros((Ni,) + psi.shape[1:])
+    ex = 0.0
+    for t, i in enumerate(range(i0, i0 + Ni)):
+        for j in range(N):
+            phi, e = pair_collocation(psi[i], psi[j], st)
             if pairs_out is not None:
                 pairs_out[(i, j)] = e
             vx[t] -= psi[j] * phi

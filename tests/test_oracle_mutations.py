@@ -184,3 +184,52 @@ def _st_mutant(mistake):
 def test_sthosvd_mistakes_are_caught(monkeypatch, mistake):
     monkeypatch.setattr(O, "sthosvd", _st_mutant(mistake))
     assert _sthosvd_pins_fail(), f"planted mistake {mistake} in the per-pair decomposition went unnoticed"
+
+
+# ---------------------------------------------------------------------------------------
+# order-p elements and the collocation form
+# ---------------------------------------------------------------------------------------
+import tests.test_oracle_fe as FE  # noqa: E402
+
+
+def _fe_pins_fail():
+    checks = [lambda: FE.test_gll_rule(5), FE.test_order_one_is_the_linear_hat_construction,
+              lambda: FE.test_convolution_matrix_reproduces_polynomials(5, 30.0),
+              FE.test_collocation_at_full_rank_is_the_dense_kernel]
+    for c in checks:
+        try:
+            c()
+        except (AssertionError, ValueError, IndexError):
+            return True
+    return False
+
+
+def test_unmutated_fe_passes():
+    assert not _fe_pins_fail()
+
+
+_orig_fe = {"gll_points": O.gll_points, "fe_mesh_1d": O.fe_mesh_1d, "pair_collocation": O.pair_collocation}
+
+
+def _equispaced_nodes(p):                      # Lagrange nodes equally spaced instead of GLL
+    s, w = _orig_fe["gll_points"](p)
+    return np.linspace(-1.0, 1.0, p + 1), w
+
+
+def _weights_without_jacobian(edges, p):       # nodal weights missing the half cell length
+    x, q, cells = _orig_fe["fe_mesh_1d"](edges, p)
+    return x, q * 2.0 / (edges[1] - edges[0]), cells
+
+
+def _collocation_without_kernel(psi_i, psi_j, st):   # reconstruction forgets C_k
+    rho = psi_i * psi_j
+    G = O.project(rho, st.V)
+    phi = sum(st.w[k] * O.reconstruct(G, st.U) for k in range(len(st.w)))
+    return phi, float((O.weights3d(st.q) * rho * phi).sum())
+
+
+@pytest.mark.parametrize("name,fn", [("gll_points", _equispaced_nodes), ("fe_mesh_1d", _weights_without_jacobian),
+                                     ("pair_collocation", _collocation_without_kernel)])
+def test_fe_mistakes_are_caught(monkeypatch, name, fn):
+    monkeypatch.setattr(O, name, fn)
+    assert _fe_pins_fail(), f"planted mistake in {name} went unnoticed"
