@@ -127,6 +127,13 @@ typedef struct {
                             /* (entry t: orbital i0+t, or t in symmetric mode), summed in   */
                             /* FP64 over j ascending.  ex, e_pairs and e_orb must be 8-byte */
                             /* aligned and overlap neither each other, psi nor vxpsi.       */
+  int32_t pair_bases;       /* 0: the system's bases U_d for every pair.  1: each pair's    */
+                            /* own bases, the sequentially truncated HOSVD of its density   */
+                            /* (modes 0, 1, 2 in turn, ranks r[d] of the system, in the W   */
+                            /* inner product; eq. `TuckerDecompField` with factors of each  */
+                            /* pair), its own Chat_k^d = V_ij,d^T C_k^d U_ij,d and its own  */
+                            /* back-projection.  Requires FP64 compute and n[d] <= 96       */
+                            /* (TXE_ERR_UNSUPPORTED otherwise).                             */
 } txe_apply_args;
 
 /* ABI version (TXE_ABI_VERSION). */
@@ -194,6 +201,27 @@ txe_status txe_system_destroy(txe_system *sys);
  * may be NULL) and Chat_out (host, K*r*r, row-major Chat_k[p][s], may be
  * NULL). */
 txe_status txe_system_conv(const txe_system *sys, int32_t mode, double *C_out, double *Chat_out);
+
+/* Order-p Lagrange finite elements on a 1-D mesh of cells (section
+ * "Creation of Structured FE basis": the nodes of a cell are its
+ * Gauss-Lobatto-Legendre points; the 3-D basis is the tensor product of the
+ * 1-D Lagrange polynomials).  Host only, no device work; usable without a GPU.
+ *   edges: host, ncells + 1 strictly increasing finite values (the cell ends);
+ *   p: element order, 1 <= p <= 10.
+ * The two end nodes of the domain are held at zero and are not unknowns, so a
+ * mesh has n = ncells * p - 1 unknowns (the library's grids need n a multiple
+ * of 4).  txe_fe_mesh_1d writes their positions x (host, n) and nodal
+ * quadrature weights q (host, n: GLL weight times half the cell length,
+ * summed over the cells a node belongs to); either may be NULL.
+ * txe_fe_conv_matrices writes, for K Gaussian exponents alpha (host, K, finite,
+ * >= 0), C (host, K*n*n, row-major per term) with
+ * C_k[a][b] = int exp(-alpha_k (x_a - t)^2) N_b(t) dt (eqs. `quadVal`,
+ * `discInteg`), the matrices txe_system_desc.C takes.  Errors: TXE_ERR_ARG
+ * (null or non-finite input, edges not increasing), TXE_ERR_SHAPE (ncells,
+ * p or K out of range); nothing is written then. */
+txe_status txe_fe_mesh_1d(const double *edges, int32_t ncells, int32_t p, double *x, double *q);
+txe_status txe_fe_conv_matrices(const double *edges, int32_t ncells, int32_t p, const double *alpha, int32_t K,
+                                double *C);
 
 /* Workspace bytes one apply with these arguments needs. */
 txe_status txe_workspace_query(txe_context *ctx, const txe_system *sys, const txe_apply_args *args,

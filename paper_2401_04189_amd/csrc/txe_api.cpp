@@ -87,6 +87,9 @@ struct txe_system {
   DevTables<float> t32;
   DevBf tbf;
   double *qdev[3] = {nullptr, nullptr, nullptr};
+  // per-pair bases: D C_k^d D^-1 (D = diag(sqrt(q_d)), [K][n][n] per mode) and w_k
+  double *csdev[3] = {nullptr, nullptr, nullptr};
+  double *wdev = nullptr;
 };
 
 #define HIP_TRY(expr)                                                                        \
@@ -480,8 +483,11 @@ extern "C" txe_status txe_system_destroy(txe_system *sys) {
   free_tables(sys->t64);
   free_tables(sys->t32);
   for (void *p : sys->tbf.owned) hipFree(p);
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < 3; ++d) {
     if (sys->qdev[d]) hipFree(sys->qdev[d]);
+    if (sys->csdev[d]) hipFree(sys->csdev[d]);
+  }
+  if (sys->wdev) hipFree(sys->wdev);
   delete sys;
   return ok();
 }
@@ -611,7 +617,68 @@ extern "C" txe_status txe_system_create(txe_context *ctx, const txe_system_desc 
     }
     S->qdev[d] = (double *)p;
   }
+  // tables of the per-pair-bases mode (grids it supports, n <= 96): D C_k^d D^-1 per mode, and w
+  const bool pb_grid = std::max(S->n[0], std::max(S->n[1], S->n[2])) <= PB_MAX_N;
+  for (int d = 0; d < 3 && pb_grid; ++d) {
+    const int n = S->n[d];
+    std::vector<double> cs((size_t)S->K * n * n);
+    for (int k = 0; k < S->K; ++k)
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b)
+          cs[((size_t)k * n + a) * n + b] =
+              std::sqrt(S->q[d][a]) * S->C[d][((size_t)k * n + a) * n + b] / std::sqrt(S->q[d][b]);
+    void *p = nullptr;
+    if (hipMalloc(&p, cs.size() * sizeof(double)) != hipSuccess ||
+        hipMemcpy(p, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      if (p) hipFree(p);
+      txe_system_destroy(S);
+      return fail(TXE_ERR_DEVICE, "upload of the per-pair-basis tables failed");
+    }
+    S->csdev[d] = (double *)p;
+  }
+  {
+    void *p = nullptr;
+    if (hipMalloc(&p, S->K * sizeof(double)) != hipSuccess ||
+        hipMemcpy(p, S->w.data(), S->K * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      if (p) hipFree(p);
+      txe_system_destroy(S);
+      return fail(TXE_ERR_DEVICE, "upload of w failed");
+    }
+    S->wdev = (double *)p;
+  }
   *out = S;
+  return ok();
+}
+
+static txe_status fe_check(const double *edges, int32_t ncells, int32_t p) {
+  if (!edges) return fail(TXE_ERR_ARG, "edges is null");
+  if (ncells < 1 || ncells > (1 << 20)) return fail(TXE_ERR_SHAPE, "ncells = %d out of [1, 2^20]", ncells);
+  if (p < 1 || p > FE_MAX_ORDER) return fail(TXE_ERR_SHAPE, "order p = %d out of [1, %d]", p, FE_MAX_ORDER);
+  if ((long long)ncells * p - 1 < 1) return fail(TXE_ERR_SHAPE, "the mesh has no unknown node");
+  for (int e = 0; e <= ncells; ++e)
+    if (!std::isfinite(edges[e])) return fail(TXE_ERR_ARG, "edges[%d] is not finite", e);
+  for (int e = 0; e < ncells; ++e)
+    if (!(edges[e + 1] > edges[e])) return fail(TXE_ERR_ARG, "edges must increase (edges[%d])", e + 1);
+  return TXE_OK;
+}
+
+extern "C" txe_status txe_fe_mesh_1d(const double *edges, int32_t ncells, int32_t p, double *x, double *q) {
+  txe_status st = fe_check(edges, ncells, p);
+  if (st != TXE_OK) return st;
+  fe_mesh_1d(edges, ncells, p, x, q);
+  return ok();
+}
+
+extern "C" txe_status txe_fe_conv_matrices(const double *edges, int32_t ncells, int32_t p, const double *alpha,
+                                           int32_t K, double *C) {
+  txe_status st = fe_check(edges, ncells, p);
+  if (st != TXE_OK) return st;
+  if (!alpha || !C) return fail(TXE_ERR_ARG, "alpha and C must not be null");
+  if (K < 1 || K > 4096) return fail(TXE_ERR_SHAPE, "K = %d out of [1, 4096]", K);
+  for (int k = 0; k < K; ++k)
+    if (!std::isfinite(alpha[k]) || alpha[k] < 0) return fail(TXE_ERR_ARG, "alpha[%d] must be finite and >= 0", k);
+  const size_t n = (size_t)ncells * p - 1;
+  for (int k = 0; k < K; ++k) fe_conv_matrix(edges, ncells, p, alpha[k], C + (size_t)k * n * n);
   return ok();
 }
 
@@ -646,6 +713,11 @@ struct Plan {
   size_t psi32_elems;  // FP32 copy of FP64 orbitals for the projection (0: none)
   size_t off_T2, off_G, off_S1, off_epart, off_epair, off_psi32, total;
   std::vector<Chunk> chunks;
+  // per-pair bases: per-pair element counts and offsets of its regions
+  bool pair_bases = false;
+  size_t pb_X, pb_X1, pb_X2, pb_X3, pb_S, pb_B, pb_U[3], pb_ah, pb_c1, pb_c2, pb_u0;
+  size_t off_X, off_X1, off_X2, off_X3, off_S, off_B, off_V, off_Wr, off_U[3], off_ah, off_c1, off_c2, off_u0;
+  int ldS = 0;
 };
 
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -658,10 +730,33 @@ static bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
 
 static void plan_sizes(const Dims &D, Plan &pl) {
   const size_t P = (size_t)pl.Pmax;
-  const size_t perT2 = (size_t)D.n0 * D.rp1 * D.rp2;
+  const size_t perT2 = pl.pair_bases ? 0 : (size_t)D.n0 * D.rp1 * D.rp2;
   const size_t perG = (size_t)D.rp0 * D.rp1 * D.rp2;
   const size_t perS1 = pl.want_vx ? (size_t)D.n0 * D.rp2 * D.rp1 : 0;
   size_t off = 0;
+  if (pl.pair_bases) {  // FP64 regions of the per-pair decomposition and tables
+    const size_t RP = D.rp0, nmax = std::max(D.n0, std::max(D.n1, D.n2));
+    pl.ldS = (int)nmax;
+    pl.pb_X = (size_t)D.n0 * D.n1 * D.n2;
+    pl.pb_X1 = std::max((size_t)D.r0 * D.n1 * D.n2, (size_t)D.n0 * D.n2 * RP);
+    pl.pb_X2 = (size_t)D.r0 * D.r1 * D.n2;
+    pl.pb_X3 = (size_t)D.r0 * D.r1 * D.r2;
+    pl.pb_S = nmax * nmax;
+    pl.pb_B = pl.pb_X;
+    pl.pb_U[0] = (size_t)D.n0 * D.r0; pl.pb_U[1] = (size_t)D.n1 * D.r1; pl.pb_U[2] = (size_t)D.n2 * D.r2;
+    pl.pb_ah = (size_t)D.r0 * D.Kp * RP;
+    pl.pb_c1 = (size_t)D.Kp * RP * RP;
+    pl.pb_c2 = (size_t)D.Kp * D.MT2 * D.MT2 * 256;
+    pl.pb_u0 = (size_t)(D.na0 / 16) * D.MT0 * 256;
+    const size_t sizes[15] = {pl.pb_X,    pl.pb_X1,   pl.pb_X2,   pl.pb_X3, pl.pb_S,  pl.pb_B,  pl.pb_S, pl.pb_S,
+                              pl.pb_U[0], pl.pb_U[1], pl.pb_U[2], pl.pb_ah, pl.pb_c1, pl.pb_c2, pl.pb_u0};
+    size_t *offs[15] = {&pl.off_X,    &pl.off_X1,   &pl.off_X2,   &pl.off_X3, &pl.off_S,  &pl.off_B,  &pl.off_V, &pl.off_Wr,
+                        &pl.off_U[0], &pl.off_U[1], &pl.off_U[2], &pl.off_ah, &pl.off_c1, &pl.off_c2, &pl.off_u0};
+    for (int i = 0; i < 15; ++i) {
+      *offs[i] = off;
+      off = align256(off + P * sizes[i] * sizeof(double));
+    }
+  }
   pl.off_T2 = off; off = align256(off + P * perT2 * pl.elt);
   pl.off_G = off; off = align256(off + P * perG * pl.elt);
   pl.off_S1 = off; off = align256(off + P * perS1 * pl.elt);
@@ -679,7 +774,7 @@ static long long max_pairs(const Dims &D, Plan &pl, size_t limit) {
   const size_t fixed = pl.total;
   pl.Pmax = 1;
   plan_sizes(D, pl);
-  const size_t per = pl.total - fixed + 256 * 4;  // + alignment slack of the four per-pair regions
+  const size_t per = pl.total - fixed + 256 * 24;  // + alignment slack of the per-pair regions (21 of them)
   if (pl.total > limit) return 0;
   return (long long)((limit - fixed) / per);
 }
@@ -782,6 +877,7 @@ static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, cons
   pl.f64 = a->compute == TXE_COMPUTE_F64;
   pl.symmetric = a->symmetric != 0;
   pl.want_vx = a->vxpsi != nullptr;
+  pl.pair_bases = a->pair_bases != 0;
   pl.elt = pl.f64 ? sizeof(double) : sizeof(float);
   // the reduced-precision forms project FP64 orbitals from an FP32 copy
   // (half the bytes of the projection's orbital reads) when it fits beside
@@ -806,9 +902,9 @@ static std::string plan_key(const txe_context *ctx, const txe_system *sys, const
   static const char *cname[] = {"f64", "f32", "bf16x3", "bf16x6"};
   const Dims &D = sys->D;
   char buf[256];
-  snprintf(buf, sizeof buf, "%s|n=%d,%d,%d|r=%d,%d,%d|K=%d|N=%d|Ni=%d|%s|%s|%s", ctx->arch.c_str(), D.n0, D.n1, D.n2,
-           D.r0, D.r1, D.r2, D.K, a->N, a->symmetric ? a->N : a->Ni, cname[a->compute & 3],
-           a->symmetric ? "sym" : "block", a->vxpsi ? "vx" : "energy");
+  snprintf(buf, sizeof buf, "%s|n=%d,%d,%d|r=%d,%d,%d|K=%d|N=%d|Ni=%d|%s|%s|%s%s", ctx->arch.c_str(), D.n0, D.n1,
+           D.n2, D.r0, D.r1, D.r2, D.K, a->N, a->symmetric ? a->N : a->Ni, cname[a->compute & 3],
+           a->symmetric ? "sym" : "block", a->vxpsi ? "vx" : "energy", a->pair_bases ? "|pair-bases" : "");
   return buf;
 }
 
@@ -842,6 +938,14 @@ static txe_status validate_args(const txe_context *ctx, const txe_system *sys, c
       return fail(TXE_ERR_SHAPE, "target block [%d, %d) not inside [0, %d)", a->i0, a->i0 + a->Ni, a->N);
   }
   if (a->out_weighted != 0 && a->out_weighted != 1) return fail(TXE_ERR_ARG, "out_weighted must be 0 or 1");
+  if (a->pair_bases != 0 && a->pair_bases != 1) return fail(TXE_ERR_ARG, "pair_bases must be 0 or 1");
+  if (a->pair_bases) {
+    if (a->compute != TXE_COMPUTE_F64)
+      return fail(TXE_ERR_UNSUPPORTED, "per-pair bases are implemented in FP64 compute only");
+    if (std::max(sys->n[0], std::max(sys->n[1], sys->n[2])) > PB_MAX_N)
+      return fail(TXE_ERR_UNSUPPORTED, "per-pair bases need n[d] <= %d (the Jacobi eigensolver works in LDS)",
+                  PB_MAX_N);
+  }
   if (!a->vxpsi && !a->ex && !a->e_pairs && !a->e_orb)
     return fail(TXE_ERR_ARG, "nothing to compute (vxpsi, ex, e_pairs and e_orb are null)");
   const size_t elt = a->dtype == TXE_DTYPE_F64 ? 8 : 4;
@@ -911,7 +1015,30 @@ static hipError_t run_plan(const txe_system *sys, const txe_apply_args *args, co
   const bool psi64 = args->dtype == TXE_DTYPE_F64;
   for (size_t ci = 0; ci < pl.chunks.size() && e == hipSuccess; ++ci) {
     const Chunk &ch = pl.chunks[ci];
-    if (pl.f64) {
+    if (pl.pair_bases) {
+      ChunkArgs<double> c = chunk_args<double>(sys, args, pl, ws);
+      c.pm = ch.pm; c.P = (int)ch.P; c.nbr = ch.nbr; c.br[0] = ch.br[0]; c.br[1] = ch.br[1];
+      Tables<double> tb = sys->t64.t;  // the per-pair regions replace the shared term tables
+      tb.Ahat = (double *)(ws + pl.off_ah);
+      tb.C1f = (double *)(ws + pl.off_c1);
+      tb.C2chain = (double *)(ws + pl.off_c2);
+      tb.U0chain = (double *)(ws + pl.off_u0);
+      tb.ps_ah = (long long)pl.pb_ah; tb.ps_c1 = (long long)pl.pb_c1;
+      tb.ps_c2 = (long long)pl.pb_c2; tb.ps_u0 = (long long)pl.pb_u0;
+      PairBasesArgs pb{};
+      pb.X = (double *)(ws + pl.off_X); pb.X1 = (double *)(ws + pl.off_X1);
+      pb.X2 = (double *)(ws + pl.off_X2); pb.X3 = (double *)(ws + pl.off_X3);
+      pb.S = (double *)(ws + pl.off_S); pb.ldS = pl.ldS;
+      pb.B = (double *)(ws + pl.off_B);
+      pb.V = (double *)(ws + pl.off_V); pb.Wr = (double *)(ws + pl.off_Wr);
+      for (int d = 0; d < 3; ++d) {
+        pb.Ut[d] = (double *)(ws + pl.off_U[d]);
+        pb.Cs[d] = sys->csdev[d];
+      }
+      pb.w = sys->wdev;
+      pb.ps_ah = tb.ps_ah; pb.ps_c1 = tb.ps_c1; pb.ps_c2 = tb.ps_c2; pb.ps_u0 = tb.ps_u0;
+      e = run_chunk_pp(tb, pb, c, pl.want_vx, s, prof);
+    } else if (pl.f64) {
       ChunkArgs<double> c = chunk_args<double>(sys, args, pl, ws);
       c.pm = ch.pm; c.P = (int)ch.P; c.nbr = ch.nbr; c.br[0] = ch.br[0]; c.br[1] = ch.br[1];
       e = run_chunk_f64(sys->t64.t, c, pl.want_vx, s, prof);

@@ -140,6 +140,15 @@ int core_rows(bool f64, int nsplit, int mt) {
   return 8 * NGW32x8[mt];  // FP32 and two-part bf16 at up to three tiles
 }
 
+hipError_t launch_core_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s) {
+  return launch_core<double>(tb, a, want_vx, s);
+}
+
+hipError_t launch_epair(const double *epart, int P, int parts, const PairMap &pm, double *epair, hipStream_t s) {
+  hipLaunchKernelGGL(k_epair, dim3((P + 255) / 256), dim3(256), 0, s, epart, P, parts, pm, epair);
+  return hipGetLastError();
+}
+
 hipError_t run_chunk_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s,
                          Prof *prof) {
   return run_chunk_t<double, double>(tb, a, want_vx, s, prof);

@@ -138,6 +138,12 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   const int wg_hi = min(g_hi, wg_lo + gw);
   const int nrow = max(0, wg_hi - wg_lo);         // this wavefront's gamma' rows (uniform)
   const T *Gp = G + (size_t)p * RP * F;
+  if (tb.ps_c1 | tb.ps_c2 | tb.ps_ah | tb.ps_u0) {  // uniform: this pair's own tables
+    tb.C1f += (size_t)p * tb.ps_c1;
+    tb.C2chain += (size_t)p * tb.ps_c2;
+    tb.Ahat += (size_t)p * tb.ps_ah;
+    tb.U0chain += (size_t)p * tb.ps_u0;
+  }
 
   // Register plan per precision and rank tile:
   //   PF     Chat1 / Ahat fragments prefetched one step ahead
@@ -330,9 +336,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
         }
       }
     };
-    // the gamma' tiles this workgroup's split meets: mtb .. mtb + nz - 1 (<= TZ)
-    const int mtb = g_lo >> 4;
-    const int nz = min(TZ, ((max(g_hi, g_lo + 1) - 1) >> 4) - mtb + 1);
+    // the gamma' tiles this workgroup's split meets: mtb .. mtb + nz - 1 (<= TZ);
+    // holding all MT tiles, the tile index is compile-time
+    constexpr bool ALLT = TZ == MT;
+    const int mtb = ALLT ? 0 : g_lo >> 4;
+    const int nz = ALLT ? MT : min(TZ, ((max(g_hi, g_lo + 1) - 1) >> 4) - mtb + 1);
     T tcb[4 * MT];
     T c2s[TZ][MT][4];
     AF afa, afb;
@@ -435,7 +443,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
 #pragma unroll
         for (int z = 0; z < TZ; ++z)
 #pragma unroll
-          for (int mg = 0; mg < MT; ++mg) load_c2(k, min(mtb + z, MT - 1), mg, c2s[z][mg]);
+          for (int mg = 0; mg < MT; ++mg) load_c2(k, ALLT ? z : min(mtb + z, MT - 1), mg, c2s[z][mg]);
       }
       int alpha = 0;
       for (; alpha + 1 < D.r0; alpha += 2, step += 2) {

@@ -55,7 +55,7 @@ __device__ __forceinline__ bf8 ld_bf8(const unsigned short *p) {
 // its fragments with 16-byte LDS loads.  Chat1 fragments and the phase-B
 // Ahat columns of the next step are prefetched.
 // -------------------------------------------------------------------------------------
-template <int MT, int NGW, int NS, int NW, bool WRITE_S1>
+template <int MT, int NGW, int NS, int NW, bool WRITE_S1, int TZ>
 __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict__ G, Dims D, int P, int NGS,
                                                          Tables<float> tb, BfTables bft, float *__restrict__ S1,
                                                          double *__restrict__ epart) {
@@ -161,11 +161,21 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
       for (int c = 0; c < NC; ++c) f.cb[c][sp] = ld_bf8(c1 + ((size_t)sp * NC + c) * 512);
   };
 
-  // eight wavefronts (two-part splits): term-major order as in the FP32 core,
-  // the term's split Chat1/Chat2 fragments held for all slabs
-  constexpr bool KM = NW == 8;
+  // term-major order as in the FP32 core (eight wavefronts for two-part
+  // splits at up to three tiles, and every form at four and five tiles):
+  // each wavefront holds its term's split Chat1 fragments and the split
+  // Chat2 fragments of the TZ gamma' tiles of its workgroup's split for all
+  // slabs; the next slab arrives in 16-byte pieces, EPS per thread and step
+  // (the three-part form at five tiles keeps slab-major order: its held
+  // fragments would not fit beside the Phi accumulators)
+  constexpr bool KM = NW == 8 || MT == 4 || (MT == 5 && NS == 2);
   if constexpr (KM) {
-    constexpr int EPS = (int)((F + CHT - 1) / CHT);  // slab elements per thread and step
+    // pieces of PW consecutive gamma values: 16 bytes with four wavefronts,
+    // single values with eight (fewer registers in flight)
+    constexpr int PW = NW == 8 ? 1 : 4;
+    typedef typename std::conditional<PW == 4, float4, float>::type VP;
+    constexpr int FP = (int)(F / PW);
+    constexpr int EPS = (FP + CHT - 1) / CHT;
     typedef float AF[NTG][MT];
     auto load_af = [&](int alpha_, int kq_, AF &af) {
 #pragma unroll
@@ -175,37 +185,49 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
         for (int mt = 0; mt < MT; ++mt) af[tg][mt] = ah[16 * mt];
       }
     };
-    auto kslab_load = [&](int a_, float (&v)[EPS]) {
+    auto kslab_load = [&](int a_, VP (&v)[EPS]) {
+      const VP *src = reinterpret_cast<const VP *>(Gp + (size_t)a_ * F);
 #pragma unroll
-      for (int j = 0; j < EPS; ++j) v[j] = Gp[(size_t)a_ * F + min(j * CHT + tid, (int)F - 1)];
+      for (int j = 0; j < EPS; ++j) v[j] = src[min(j * CHT + tid, FP - 1)];
     };
-    auto kslab_store = [&](int buf, const float (&v)[EPS]) {
+    auto kslab_store = [&](int buf, const VP (&v)[EPS]) {
 #pragma unroll
       for (int j = 0; j < EPS; ++j) {
-        const int e = j * CHT + tid;
-        if (e < (int)F) {
-          const int beta = e / RP, gamma = e % RP;
-          const int ln = ((beta >> 3) & 3) * 16 + (gamma & 15);
-          const int base = ((((gamma >> 4) * NC + (beta >> 5)) * 64 + ln) * 8) + (beta & 7);
-          float r = v[j];
+        const int e4 = j * CHT + tid;
+        if (e4 < FP) {
+          const int beta = (PW * e4) / RP, g0 = (PW * e4) % RP;
+          const float *x4 = reinterpret_cast<const float *>(&v[j]);
 #pragma unroll
-          for (int sp = 0; sp < NS; ++sp) {
-            const __bf16 h = (__bf16)r;
-            Gs[buf * FRAG + sp * (MT * NC * 512) + base] = __builtin_bit_cast(unsigned short, h);
-            if (sp + 1 < NS) r -= (float)h;
+          for (int q = 0; q < PW; ++q) {
+            const int gamma = g0 + q;
+            const int ln = ((beta >> 3) & 3) * 16 + (gamma & 15);
+            const int base = ((((gamma >> 4) * NC + (beta >> 5)) * 64 + ln) * 8) + (beta & 7);
+            float r = x4[q];
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) {
+              const __bf16 h = (__bf16)r;
+              Gs[buf * FRAG + sp * (MT * NC * 512) + base] = __builtin_bit_cast(unsigned short, h);
+              if (sp + 1 < NS) r -= (float)h;
+            }
           }
         }
       }
     };
+    // the gamma' tiles this workgroup's split meets: mtb .. mtb + nz - 1 (<= TZ);
+    // holding all MT tiles, the tile index is compile-time and the tiles
+    // outside the split are skipped
+    constexpr bool ALLT = TZ == MT;
+    const int mtb = ALLT ? 0 : g_lo >> 4;
+    const int nz = ALLT ? MT : min(TZ, ((max(g_hi, g_lo + 1) - 1) >> 4) - mtb + 1);
     bf8 hcb[NC][NS];
-    bf8 hc2[MT][NC][NS];
+    bf8 hc2[TZ][NC][NS];
     AF afa, afb;
     load_af(0, 0, afa);
     auto kstep = [&](const int kq, const int alpha, const int step, AF &cur, AF &nxt) __attribute__((always_inline)) {
       const int k = NW * kq + wave;
       const bool last_a = alpha + 1 == D.r0;
       const bool more = !last_a || kq + 1 < nkq;  // uniform
-      float gnext[EPS];
+      VP gnext[EPS];
       kslab_load(last_a ? 0 : alpha + 1, gnext);
       if (more) load_af(last_a ? 0 : alpha + 1, last_a ? kq + 1 : kq, nxt);
       float *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * ZSS;
@@ -235,13 +257,14 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
           split8<NS>(x, wsp[c]);
         }
 #pragma unroll
-        for (int mtp = 0; mtp < MT; ++mtp) {
-          if (16 * mtp >= g_hi || 16 * mtp + 16 <= g_lo) continue;  // uniform: tile outside the split
+        for (int z = 0; z < TZ; ++z) {
+          if (z >= nz) break;  // uniform
+          if (ALLT && (16 * z >= g_hi || 16 * z + 16 <= g_lo)) continue;  // uniform: tile outside the split
           acc Z = zero4<acc>();
 #pragma unroll
-          for (int c = 0; c < NC; ++c) Z = mma_split<NS>(hc2[mtp][c], wsp[c], Z);
+          for (int c = 0; c < NC; ++c) Z = mma_split<NS>(hc2[z][c], wsp[c], Z);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Zw[(16 * mtp + 4 * lg + v) * ZRS + lr] = Z[v];
+          for (int v = 0; v < 4; ++v) Zw[(16 * (mtb + z) + 4 * lg + v) * ZRS + lr] = Z[v];
         }
       } else {
         for (int idx = lane; idx < (g_hi - g_lo) * 16; idx += 64) Zw[(g_lo + (idx >> 4)) * ZRS + (idx & 15)] = 0.f;
@@ -275,7 +298,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
           for (int c = 0; c < NC; ++c) {
             hcb[c][sp] = ld_bf8(c1 + ((size_t)sp * NC + c) * 512);
 #pragma unroll
-            for (int mtp = 0; mtp < MT; ++mtp) hc2[mtp][c][sp] = ld_bf8(c2 + (((size_t)sp * MT + mtp) * NC + c) * 512);
+            for (int z = 0; z < TZ; ++z)
+              hc2[z][c][sp] = ld_bf8(c2 + (((size_t)sp * MT + (ALLT ? z : min(mtb + z, MT - 1))) * NC + c) * 512);
           }
       }
       int alpha = 0;
@@ -395,8 +419,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
                                               epart);
 }
 
-template <int MT, int NGW, int NS, int NW>
-hipError_t launch_core_bf2_mt(const Tables<float> &tb, const BfTables &bft, const ChunkArgs<float> &a, bool want_vx,
+template <int MT, int NGW, int NS, int NW, int TZ>
+hipError_t launch_core_bf2_tz(const Tables<float> &tb, const BfTables &bft, const ChunkArgs<float> &a, bool want_vx,
                               hipStream_t s) {
   const int gper = (a.D.r2 + a.NGS - 1) / a.NGS;
   if ((gper + NW - 1) / NW > NGW) return hipErrorInvalidValue;
@@ -405,18 +429,28 @@ hipError_t launch_core_bf2_mt(const Tables<float> &tb, const BfTables &bft, cons
   const size_t lds = 2 * frag * sizeof(unsigned short) + (2 * NW * ((size_t)RP * 20 + 16)) * sizeof(float);
   const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
   if (lds > 64 * 1024) {
-    const void *fn = want_vx ? (const void *)k_core_bf2<MT, NGW, NS, NW, true>
-                             : (const void *)k_core_bf2<MT, NGW, NS, NW, false>;
+    const void *fn = want_vx ? (const void *)k_core_bf2<MT, NGW, NS, NW, true, TZ>
+                             : (const void *)k_core_bf2<MT, NGW, NS, NW, false, TZ>;
     const hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
   }
   if (want_vx)
-    hipLaunchKernelGGL((k_core_bf2<MT, NGW, NS, NW, true>), dim3(nb), dim3(64 * NW), lds, s, (const float *)a.G, a.D,
+    hipLaunchKernelGGL((k_core_bf2<MT, NGW, NS, NW, true, TZ>), dim3(nb), dim3(64 * NW), lds, s, (const float *)a.G, a.D,
                        a.P, a.NGS, tb, bft, a.S1, a.epart);
   else
-    hipLaunchKernelGGL((k_core_bf2<MT, NGW, NS, NW, false>), dim3(nb), dim3(64 * NW), lds, s, (const float *)a.G,
+    hipLaunchKernelGGL((k_core_bf2<MT, NGW, NS, NW, false, TZ>), dim3(nb), dim3(64 * NW), lds, s, (const float *)a.G,
                        a.D, a.P, a.NGS, tb, bft, a.S1, a.epart);
   return hipGetLastError();
+}
+
+// held gamma' tiles: 3 when the plan's widest split meets at most three (at
+// four and five tiles), else every tile
+template <int MT, int NGW, int NS, int NW>
+hipError_t launch_core_bf2_mt(const Tables<float> &tb, const BfTables &bft, const ChunkArgs<float> &a, bool want_vx,
+                              hipStream_t s) {
+  constexpr int TZ3 = MT <= 3 ? MT : 3;
+  if (split_tiles(a.D, a.NGS) <= TZ3) return launch_core_bf2_tz<MT, NGW, NS, NW, TZ3>(tb, bft, a, want_vx, s);
+  return launch_core_bf2_tz<MT, NGW, NS, NW, MT>(tb, bft, a, want_vx, s);
 }
 
 template <int NS>

@@ -12,11 +12,17 @@ namespace txe {
 // ---- FP64 host setup (txe_setup.cpp) ------------------------------------------------
 void conv_matrix_1d(int n, const double *x, double alpha, double *C);
 void core_matrix(int n, int r, const double *q, const double *U, const double *C, double *Chat);
+// ---- order-p Lagrange elements (txe_fe.cpp) ------------------------------------------
+void gll_points(int p, double *s, double *w);
+void fe_mesh_1d(const double *edges, int ncells, int p, double *x, double *q);
+void fe_conv_matrix(const double *edges, int ncells, int p, double alpha, double *C);
+constexpr int FE_MAX_ORDER = 10;
 
 inline int rup(int v, int m) { return (v + m - 1) / m * m; }
 
 constexpr int KCHUNK = 8;     // Gaussian terms staged per LDS round in the core kernel
 constexpr int MAX_MT = 5;     // rank tiles of 16: r <= 80
+constexpr int PB_MAX_N = 96;  // per-pair bases: largest grid extent (two n x n FP64 matrices in LDS)
 
 // Sizes of one system, with the paddings the kernels use.
 struct Dims {
@@ -78,6 +84,25 @@ struct Tables {
   T *U0chain;   // [na0/16][MT0][4][64]  U0[a][alpha']
   T *U2T;       // [rp2][nc2]            U2[c][gamma] at [gamma][c]
   T *U1chain;   // [nb1/16][MT1][4][64]  U1[b][beta]
+  // per-pair tables (bases of each pair): element strides between the pairs'
+  // C1f, C2chain, Ahat and U0chain, indexed by the chunk's local pair; 0 =
+  // one table shared by every pair
+  long long ps_c1, ps_c2, ps_ah, ps_u0;
+};
+
+// Workspace and per-system data of a chunk with per-pair bases (FP64).
+struct PairBasesArgs {
+  double *X, *X1, *X2, *X3;   // scaled pair densities and the truncated tensors (per-pair strides:
+                              // n0 n1 n2, max(r0 n1 n2, n0 n2 rp), r0 r1 n2, r0 r1 r2)
+  double *S;                  // Gram matrices, ldS x ldS per pair
+  int ldS;
+  double *B;                  // the current tensor in its first-stage eigenbasis along the mode (n0 n1 n2)
+  double *V, *Wr;             // first-stage eigenvectors (n_d x n_d) and the second-stage leading ones
+                              // (n_d x r_d), ldS x ldS per pair
+  double *Ut[3];              // leading left singular vectors per mode, n_d x r_d per pair
+  const double *Cs[3];        // D C_k^d D^-1 of the system ([K][n][n] per mode, D = diag(sqrt(q_d)))
+  const double *w;            // the K term weights (device)
+  long long ps_c1, ps_c2, ps_ah, ps_u0;
 };
 
 // Split-bf16 copies of the core kernel's term matrices (bf16 bit patterns).
@@ -199,6 +224,18 @@ hipError_t launch_core_bf(const Tables<float> &tb, const BfTables &bft, const Ch
                           hipStream_t s);
 template <typename T, typename Tin>
 hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s);
+
+// FP64 core kernel of the system's rank tiles, and the pair-energy sums of a
+// chunk (txe_chunk.hip)
+hipError_t launch_core_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s);
+hipError_t launch_epair(const double *epart, int P, int parts, const PairMap &pm, double *epair, hipStream_t s);
+
+// One chunk with per-pair bases: sequentially truncated HOSVD of every pair
+// density, the pair's tables, the core kernel on them, the back-projection
+// in the pair's bases (txe_pairbases.hip).  tb holds the per-pair table
+// regions (C1f, C2chain, Ahat, U0chain) with their strides.
+hipError_t run_chunk_pp(const Tables<double> &tb, const PairBasesArgs &pb, const ChunkArgs<double> &a, bool want_vx,
+                        hipStream_t s, Prof *prof);
 
 // Runs one chunk (projection, core sum, back-projection, pair energies).
 // Returns hipSuccess or the first launch error.

@@ -51,6 +51,7 @@ class ApplyArgs(ctypes.Structure):
         ("ex", ctypes.c_void_p),
         ("e_pairs", ctypes.c_void_p),
         ("e_orb", ctypes.c_void_p),
+        ("pair_bases", _c_int),
     ]
 
 
@@ -68,6 +69,8 @@ SIGNATURES = {
     "txe_system_create": (_c_int, [ctypes.c_void_p, ctypes.POINTER(SystemDesc), ctypes.POINTER(ctypes.c_void_p)]),
     "txe_system_destroy": (_c_int, [ctypes.c_void_p]),
     "txe_system_conv": (_c_int, [ctypes.c_void_p, _c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "txe_fe_mesh_1d": (_c_int, [ctypes.c_void_p, _c_int, _c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "txe_fe_conv_matrices": (_c_int, [ctypes.c_void_p, _c_int, _c_int, ctypes.c_void_p, _c_int, ctypes.c_void_p]),
     "txe_workspace_query": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs),
                                      ctypes.POINTER(ctypes.c_size_t)]),
     "txe_apply": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs)]),
@@ -132,6 +135,29 @@ def conv_matrix_1d(x, alpha):
     x = np.ascontiguousarray(x, dtype=np.float64)
     C = np.empty((len(x), len(x)), dtype=np.float64)
     _check(lib().txe_conv_matrix_1d(len(x), x.ctypes.data, float(alpha), C.ctypes.data))
+    return C
+
+
+def fe_mesh_1d(edges, p):
+    """Host FP64 nodes x and weights q of order-p Lagrange elements on the
+    cells between `edges` (the domain ends held at zero; no GPU needed)."""
+    edges = np.ascontiguousarray(edges, dtype=np.float64)
+    n = (len(edges) - 1) * int(p) - 1
+    x = np.empty(max(n, 0), dtype=np.float64)
+    q = np.empty(max(n, 0), dtype=np.float64)
+    _check(lib().txe_fe_mesh_1d(edges.ctypes.data, len(edges) - 1, int(p), x.ctypes.data, q.ctypes.data))
+    return x, q
+
+
+def fe_conv_matrices(edges, p, alpha):
+    """Host FP64 convolution matrices [K][n][n] of the Gaussian terms with
+    exponents `alpha` for order-p Lagrange elements (no GPU needed)."""
+    edges = np.ascontiguousarray(edges, dtype=np.float64)
+    alpha = np.ascontiguousarray(np.atleast_1d(alpha), dtype=np.float64)
+    n = (len(edges) - 1) * int(p) - 1
+    C = np.empty((len(alpha), max(n, 0), max(n, 0)), dtype=np.float64)
+    _check(lib().txe_fe_conv_matrices(edges.ctypes.data, len(edges) - 1, int(p), alpha.ctypes.data, len(alpha),
+                                      C.ctypes.data))
     return C
 
 
@@ -261,7 +287,7 @@ class System:
 
 
 def make_args(psi, compute="f64", symmetric=True, i0=0, Ni=None, vx=None, ex=None, e_pairs=None,
-              out_scale=None, out_weighted=False, e_orb=None):
+              out_scale=None, out_weighted=False, e_orb=None, pair_bases=False):
     import torch
 
     a = ApplyArgs()
@@ -278,11 +304,12 @@ def make_args(psi, compute="f64", symmetric=True, i0=0, Ni=None, vx=None, ex=Non
     a.ex = ex.data_ptr() if ex is not None else None
     a.e_pairs = e_pairs.data_ptr() if e_pairs is not None else None
     a.e_orb = e_orb.data_ptr() if e_orb is not None else None
+    a.pair_bases = 1 if pair_bases else 0
     return a
 
 
 def _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_scale=None, out_weighted=False,
-             vx_out=None, want_orb=False):
+             vx_out=None, want_orb=False, pair_bases=False):
     """ApplyArgs for one problem with freshly allocated outputs."""
     import torch
 
@@ -300,24 +327,26 @@ def _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_sca
     npairs = N * (N + 1) // 2 if symmetric else Ni * N
     ep = torch.empty(npairs, dtype=torch.float64, device=psi.device) if want_pairs else None
     eo = torch.empty(Ni, dtype=torch.float64, device=psi.device) if want_orb else None
-    a = make_args(psi, compute, symmetric, i0, Ni, vx, ex, ep, out_scale, out_weighted, eo)
+    a = make_args(psi, compute, symmetric, i0, Ni, vx, ex, ep, out_scale, out_weighted, eo, pair_bases)
     if want_orb:
         return a, vx, ex, ep, eo
     return a, vx, ex, ep
 
 
 def apply(ctx: Context, sysm: System, psi, compute="f64", symmetric=True, i0=0, Ni=None, want_vx=True,
-          want_pairs=False, out_scale=None, out_weighted=False, vx_out=None, want_orb=False):
+          want_pairs=False, out_scale=None, out_weighted=False, vx_out=None, want_orb=False, pair_bases=False):
     """Vx psi (targets) and E_x for the orbitals `psi` (a CUDA tensor N x n0 x n1 x n2).
 
     Returns (vx, ex, e_pairs): vx is None when want_vx is False; ex is a
     0-d float64 CUDA tensor; e_pairs is None unless want_pairs.  With
     want_orb a fourth entry holds the exchange-matrix diagonal
-    <psi_i, Vx psi_i>_W of each target (FP64, from the library)."""
+    <psi_i, Vx psi_i>_W of each target (FP64, from the library).  With
+    pair_bases every pair uses its own Tucker bases (the sequentially
+    truncated HOSVD of its density at the system's ranks)."""
     import torch
 
     out = _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_scale, out_weighted, vx_out,
-                   want_orb)
+                   want_orb, pair_bases)
     ctx.set_stream(torch.cuda.current_stream(psi.device))
     _check(lib().txe_apply(ctx.h, sysm.h, ctypes.byref(out[0])))
     return tuple(out[1:])

@@ -89,6 +89,52 @@ def uniform_grid(n, L) -> Grid:
     return Grid(n=n, L=L, x=xs, q=qs)
 
 
+def adaptive_edges(L, bms, msna, centres, ball, p):
+    """Cell edges of a 1-D mesh on [-L, L] made the way the paper builds its
+    structured FE mesh (section "Creation of Structured FE basis"): start
+    from uniform cells no larger than the base mesh size `bms`, then bisect
+    every cell that reaches within `ball` of an atom coordinate in `centres`
+    until those cells are no larger than the mesh size near the atoms `msna`.
+    Two steps are this generator's own: neighbouring cells are balanced to a
+    width ratio of at most 2 (the coarser one is bisected), and the widest
+    cells are bisected until the mesh has n = ncells p - 1 unknowns with n a
+    multiple of 4 (the library's grid extents), which needs p odd."""
+    if p % 2 == 0:
+        raise ValueError("n = ncells * p - 1 is odd for even p; use an odd order")
+    nc = max(1, int(math.ceil(2.0 * L / bms - 1e-12)))
+    edges = list(np.linspace(-L, L, nc + 1))
+    near = lambda lo, hi: any(lo <= c + ball and hi >= c - ball for c in centres)  # noqa: E731
+    changed = True
+    while changed:
+        changed, out = False, [edges[0]]
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            if hi - lo > msna and near(lo, hi):
+                out.append(0.5 * (lo + hi))
+                changed = True
+            out.append(hi)
+        edges = out
+    while True:
+        w = np.diff(edges)
+        split = [i for i in range(len(w)) if (i > 0 and w[i] > 2.0 * w[i - 1] * (1 + 1e-12))
+                 or (i + 1 < len(w) and w[i] > 2.0 * w[i + 1] * (1 + 1e-12))]
+        if not split:
+            break
+        for i in sorted(split, reverse=True):
+            edges.insert(i + 1, 0.5 * (edges[i] + edges[i + 1]))
+    while ((len(edges) - 1) * p - 1) % 4 != 0:
+        w = np.diff(edges)
+        i = int(np.argmax(w))
+        edges.insert(i + 1, 0.5 * (edges[i] + edges[i + 1]))
+    return np.array(edges)
+
+
+def grid_from_nodes(xs, qs) -> Grid:
+    """A grid from given per-mode nodes and weights (e.g. of an FE mesh)."""
+    xs = [np.asarray(v, dtype=np.float64) for v in xs]
+    qs = [np.asarray(v, dtype=np.float64) for v in qs]
+    return Grid(n=tuple(len(v) for v in xs), L=tuple(float(max(abs(v[0]), abs(v[-1]))) for v in xs), x=xs, q=qs)
+
+
 def exp_sum(K, s_lo=-8.0, s_hi=4.0):
     """Coefficients of 1/r ~ sum_k w_k exp(-alpha_k r^2).
 
