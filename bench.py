@@ -24,7 +24,6 @@ records on its own stream around every launch (txe_profile_*).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -35,9 +34,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pair convolutions/s for Vx psi, MFMA-FP32 vs FP64 at dE_x<=1e-5 Ha; % roofline"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.0}
-CSRC = os.path.join(ROOT, "paper_2401_04189_amd", "csrc")
-# the sources the core kernel is compiled from (the traffic counters are tied to them)
-KERNEL_SRC = [os.path.join(CSRC, f) for f in ("txe_core.h", "txe_dev.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_core.json")
 TUNE_CACHE = os.path.join(ROOT, "paper_2401_04189_amd", "tuned_shapes.json")
 
@@ -61,19 +57,14 @@ def core_kernel_flops_per_pair(n, r, K):
     return 2.0 * (K * r0 * r1 * r2 * (r0 + r1 + r2) + r0 * r1 * r2 + n[0] * r0 * r1 * r2)
 
 
-def source_sha():
-    h = hashlib.sha256()
-    for f in KERNEL_SRC:
-        h.update(open(f, "rb").read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(compute, cfg):
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     ent = t.get(f"{cfg}/{compute}")
+    from paper_2401_04189_amd.profsum import source_sha
+
     if not ent or ent.get("kernel_source_sha") != source_sha():
         return None
     return ent.get("bytes_per_launch")
@@ -113,6 +104,17 @@ def load_cache(args, txe, ctx):
     # with --retune the file's other entries are kept (merged) and rewritten
     if not args.no_tune and os.path.exists(TUNE_CACHE):
         txe.tune_load(ctx, TUNE_CACHE)
+
+
+def copy_calibration(torch):
+    """One elementwise kernel of known traffic (reads 512 MiB, writes 512 MiB):
+    the reference for scaling the HBM byte counters of a profile."""
+    src = torch.empty(64 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    print(f"copy calibration: {src.numel() * 8} bytes read and written", file=sys.stderr, flush=True)
+    del src, dst
 
 
 def cpu_model():
@@ -166,6 +168,8 @@ def bench_block(args, txe, torch, W):
     compared with FP64 on the batches both timed (|dE_batch|) and on batch 0
     (Vx psi per orbital in the W-norm, exchange-matrix diagonal from the
     library)."""
+    if args.copy_calibration:
+        copy_calibration(torch)
     t0 = time.perf_counter()
     s = W.build_config("cfg4", device="cuda")
     torch.cuda.empty_cache()
@@ -237,7 +241,10 @@ def bench_block(args, txe, torch, W):
             e["within_1e-5_Ha"] = e["dE_batch_Ha_max"] <= 1e-5
             e["over_fp64"] = round(legs["f64"]["sec"] / L["sec"], 3)
         out_legs[comp] = e
-    use = "f32" if out_legs.get("f32", {}).get("within_1e-5_Ha") else "f64"
+    # the FP32 leg is the value when its energies pass the gate against FP64
+    # (or, when FP64 is not timed in this run, ungated: say so in the line)
+    gated = "f64" in out_legs
+    use = "f32" if "f32" in out_legs and (not gated or out_legs["f32"].get("within_1e-5_Ha")) else "f64"
     U = out_legs[use]
     roof = {"bound": "mfma", "kernel": "core", "achieved": U["core_tflops"], "peak": PEAK_TFLOPS[use],
             "unit": "TFLOP/s", "frac": round(U["core_tflops"] / PEAK_TFLOPS[use], 4),
@@ -255,6 +262,7 @@ def bench_block(args, txe, torch, W):
                    f"against all {N} sources ({npairs} pairs)", "grid": list(n), "orbitals": N, "rank": list(r),
                    "terms": K, "batch_targets": B, "pairs_per_step": npairs, "mode": "block (targets x all sources)"},
         "legs": out_legs,
+        "energy_gate_evaluated": gated,
         "fp32_over_fp64": out_legs.get("f32", {}).get("over_fp64"),
         "whole_path_tflops": round(flops_per_pair(n, r, K) * npairs / (U["ms_per_step"] * 1e-3) / 1e12, 3),
         "roofline": roof,
@@ -464,13 +472,7 @@ def main():
     vx = torch.empty_like(psi)
 
     if args.copy_calibration:
-        # one elementwise kernel of known traffic: reads 512 MiB, writes 512 MiB
-        src = torch.empty(64 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.mul(src, 2.0, out=dst)
-        torch.cuda.synchronize()
-        print(f"copy calibration: {src.numel() * 8} bytes read and written", file=sys.stderr)
-        del src, dst
+        copy_calibration(torch)
 
     legs = {}
     tuned = {}

@@ -1,14 +1,16 @@
 """Summaries of rocprofv3 output for profiles/ (text) and bench.py (traffic).
 
-    python -m paper_2401_04189_amd.profsum ktrace  <run_kernel_stats.csv> <out.md> "<command>"
-    python -m paper_2401_04189_amd.profsum traffic <fetch.csv> <write.csv> <out.md> "<fetch cmd>" "<write cmd>"
+    python -m paper_2401_04189_amd.profsum ktrace  <run_kernel_stats.csv> <out.md> "<title>" "<command>"
+    python -m paper_2401_04189_amd.profsum traffic <fetch.csv> <write.csv> <out.md> "<title>" <key> \
+        "<fetch cmd>" "<write cmd>" [<algorithmic core bytes per launch>]
 
 `traffic` scales the per-dispatch FETCH_SIZE / WRITE_SIZE counters (KiB) by
-what the same counters read for bench.py's calibration kernel (an
-elementwise dst = 2*src over 512 MiB: 512 MiB read, 512 MiB written), and
-records the per-launch HBM bytes of each exchange kernel in
-profiles/traffic_core.json together with the hash of the kernel source they
-were taken from (bench.py reports them only while the source is unchanged).
+what the same counters read for bench.py's calibration kernel (torch.mul of
+a 512 MiB FP64 tensor by 2: 512 MiB read, 512 MiB written; the first
+AUnaryFunctor dispatch of the run), and records the per-launch HBM bytes of
+the core kernel in profiles/traffic_core.json under <key> (e.g. "cfg4/f32")
+together with the hash of the kernel source they were taken from (bench.py
+reports them only while that source is unchanged).
 """
 from __future__ import annotations
 
@@ -21,20 +23,34 @@ import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SRC = os.path.join(ROOT, "paper_2401_04189_amd", "csrc", "txe_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2401_04189_amd", "csrc")
+# the sources the core kernel is compiled from (the traffic counters are tied to them)
+KERNEL_SRC = [os.path.join(CSRC, f) for f in ("txe_core.h", "txe_dev.h")]
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_core.json")
 CAL_BYTES = 512 << 20
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def short(name):
     name = name.replace("(anonymous namespace)::", "")
     name = re.sub(r"\(.*", "", name)
-    return name.replace("txe::", "").replace("void ", "") or "(torch / runtime kernel)"
+    name = name.replace("txe::", "").replace("void ", "")
+    if name.startswith("Cijk_"):
+        return "rocBLAS GEMM (input generation)"
+    if name.startswith("at::native::"):
+        return "torch elementwise (input generation)"
+    return name or "(torch / runtime kernel)"
 
 
-def ktrace(stats_csv, out_md, cmd):
+def ktrace(stats_csv, out_md, title, cmd):
     rows = list(csv.DictReader(open(stats_csv)))
-    lines = ["# Kernel trace: 64^3 exchange apply (2080 unique pairs, r = 40, K = 40)", "",
+    lines = [f"# Kernel trace: {title}", "",
              "Command (from the repository root, on the machine with the GPU):", "", "```", cmd, "```", "",
              "| Kernel | Calls | Average (ms) | Min (ms) | Max (ms) | Share |", "|---|---|---|---|---|---|"]
     for r in rows:
@@ -45,39 +61,44 @@ def ktrace(stats_csv, out_md, cmd):
 
 def _per_kernel(path, counter):
     agg = collections.defaultdict(list)
+    first = {}
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] == counter:
             agg[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)
-    return agg
+            d = int(r["Dispatch_Id"])
+            if "AUnaryFunctor" in r["Kernel_Name"] and ("cal" not in first or d < first["cal"][0]):
+                first["cal"] = (d, float(r["Counter_Value"]) * 1024.0)
+    return agg, first.get("cal", (None, None))[1]
 
 
-def traffic(fetch_csv, write_csv, out_md, cmd_f, cmd_w):
-    fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
-    write = _per_kernel(write_csv, "WRITE_SIZE")
-    # calibration kernel: the elementwise kernel with the largest fetch
-    cal_f = max((max(v) for k, v in fetch.items() if "elementwise" in k), default=None)
-    cal_w = max((max(v) for k, v in write.items() if "elementwise" in k), default=None)
+def traffic(fetch_csv, write_csv, out_md, title, key, cmd_f, cmd_w, alg_bytes=None):
+    fetch, cal_f = _per_kernel(fetch_csv, "FETCH_SIZE")
+    write, cal_w = _per_kernel(write_csv, "WRITE_SIZE")
     sf = CAL_BYTES / cal_f if cal_f else None
     sw = CAL_BYTES / cal_w if cal_w else None
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
-    lines = ["# HBM traffic per launch: 64^3 exchange apply, FP32 MFMA form", "",
+    sha = source_sha()
+    lines = [f"# HBM traffic per launch: {title}", "",
              "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two separate rocprofv3 runs, scaled",
-             "by the counters of a calibration kernel of known size (elementwise dst = 2*src over",
-             f"512 MiB): fetch scale {sf:.4f}, write scale {sw:.4f}.", "",
-             f"Kernel source hash: `{sha}`", "", "Commands:", "", "```", cmd_f, cmd_w, "```", "",
-             "| Kernel | Fetch (MB) | Write (MB) |", "|---|---|---|"]
+             "by the counters of a calibration kernel of known size (torch.mul of 512 MiB of FP64 by 2:",
+             f"512 MiB read, 512 MiB written): fetch scale {sf:.4f}, write scale {sw:.4f}.", "",
+             f"Core kernel source hash (txe_core.h, txe_dev.h): `{sha}`", "", "Commands:", "", "```", cmd_f, cmd_w,
+             "```", "", "| Kernel | Launches | Fetch (GB) | Write (GB) |", "|---|---|---|---|"]
     rec = {}
     for k in fetch:
         if "txe::" not in k:
             continue
         f = sum(fetch[k]) / len(fetch[k]) * (sf or 1.0)
         w = sum(write.get(k, [0.0])) / max(len(write.get(k, [1])), 1) * (sw or 1.0)
-        lines.append(f"| `{short(k)}` | {f / 1e6:.1f} | {w / 1e6:.1f} |")
-        m = re.search(r"k_core<(float|double)", k)
-        if m:
-            rec[f"cfg2/{'f32' if m.group(1) == 'float' else 'f64'}"] = {
-                "kernel_source_sha": sha, "bytes_per_launch": round(f + w), "fetch_bytes": round(f),
-                "write_bytes": round(w), "fetch_scale": sf, "write_scale": sw}
+        lines.append(f"| `{short(k)}` | {len(fetch[k])} | {f / 1e9:.2f} | {w / 1e9:.2f} |")
+        if re.search(r"k_core<", k):
+            rec[key] = {"kernel_source_sha": sha, "kernel": short(k), "bytes_per_launch": round(f + w),
+                        "fetch_bytes": round(f), "write_bytes": round(w), "fetch_scale": sf, "write_scale": sw}
+            if alg_bytes:
+                rec[key]["algorithmic_bytes"] = float(alg_bytes)
+                lines_alg = (f"Core kernel: {(f + w) / 1e9:.1f} GB moved per launch against "
+                             f"{float(alg_bytes) / 1e9:.1f} GB algorithmic ({(f + w) / float(alg_bytes):.1f}x).")
+    if alg_bytes and key in rec:
+        lines += ["", lines_alg]
     open(out_md, "w").write("\n".join(lines) + "\n")
     old = {}
     if os.path.exists(TRAFFIC_JSON):
@@ -88,8 +109,8 @@ def traffic(fetch_csv, write_csv, out_md, cmd_f, cmd_w):
 
 if __name__ == "__main__":
     if sys.argv[1] == "ktrace":
-        ktrace(sys.argv[2], sys.argv[3], sys.argv[4])
+        ktrace(*sys.argv[2:6])
     elif sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6])
+        traffic(*sys.argv[2:10])
     else:
         raise SystemExit(__doc__)
