@@ -41,6 +41,12 @@ time, in the order the paper gives the steps:
         evaluated at every 1-D node and reconstructed (eq. `final`):
         phi_ij = sum_k w_k G x0 (C_k^0 U0) x1 (C_k^1 U1) x2 (C_k^2 U2), with
         e_ij = <rho_ij, phi_ij>_W on the grid.
+  * O10 Bases shared by all pairs (eq. `TuckerDecompField` with one set of
+        factors for every pair): per mode, the leading left singular vectors
+        of the mode-d unfolding of all pair densities rho_ij (i over the
+        targets, j over all orbitals) stacked side by side, in the W inner
+        product -- a higher-order SVD of the stack, each mode from the whole
+        stack (not truncated sequentially).
   * O8  Per-pair bases (section "Convolution operation", eq.
         `TuckerDecompField` with factors f_ij, g_ij, h_ij of each pair): the
         sequentially truncated HOSVD of each pair density (modes 0, 1, 2 in
@@ -317,6 +323,30 @@ def apply_sthosvd(psi, st: Setup, ranks, mode="symmetric", i0=0, Ni=None, pairs_
             vx[t] -= psi[j] * phi
             ex += -0.5 * e
     return vx, ex
+
+
+# ---------------------------------------------------------------------------------------
+# O10: shared bases, the HOSVD of the stacked pair densities
+# ---------------------------------------------------------------------------------------
+def shared_hosvd(psi, q, ranks, targets=None):
+    """(U, sv): q-orthonormal bases U_d (n_d x r_d, U_d^T diag(q_d) U_d = I)
+    spanning the leading left singular vectors of the mode-d unfolding of the
+    stack of every sqrt(w)-scaled pair density psi_i psi_j, i over `targets`
+    (all orbitals when None), j over all orbitals; sv[d] holds all singular
+    values of that unfolding, descending.  Each pair density is formed
+    explicitly: small cases only."""
+    psi = np.asarray(psi, dtype=np.float64)
+    N = psi.shape[0]
+    tg = range(N) if targets is None else list(targets)
+    sq = [np.sqrt(np.asarray(v, dtype=np.float64)) for v in q]
+    scale = sq[0][:, None, None] * sq[1][None, :, None] * sq[2][None, None, :]
+    U, sv = [], []
+    for d in range(3):
+        cols = [unfold(scale * psi[i] * psi[j], d) for i in tg for j in range(N)]
+        W_, s_, _ = np.linalg.svd(np.concatenate(cols, axis=1), full_matrices=False)
+        U.append(W_[:, :ranks[d]] / sq[d][:, None])
+        sv.append(s_)
+    return U, sv
 
 
 # ---------------------------------------------------------------------------------------

@@ -233,3 +233,57 @@ def _collocation_without_kernel(psi_i, psi_j, st):   # reconstruction forgets C_
 def test_fe_mistakes_are_caught(monkeypatch, name, fn):
     monkeypatch.setattr(O, name, fn)
     assert _fe_pins_fail(), f"planted mistake in {name} went unnoticed"
+
+
+# ---------------------------------------------------------------------------------------
+# shared bases: the HOSVD of the stacked pair densities
+# ---------------------------------------------------------------------------------------
+import tests.test_oracle_hosvd as HO  # noqa: E402
+
+
+def _hosvd_pins_fail():
+    checks = [HO.test_bases_are_q_orthonormal, HO.test_separable_orbitals_span_the_products,
+              HO.test_gram_identity_gives_the_singular_values_and_subspaces,
+              HO.test_orbital_rotation_leaves_the_bases]
+    for c in checks:
+        try:
+            c()
+        except (AssertionError, ValueError, IndexError, np.linalg.LinAlgError):
+            return True
+    return False
+
+
+def test_unmutated_hosvd_passes():
+    assert not _hosvd_pins_fail()
+
+
+def _hosvd_mutant(mistake):
+    """One plausible mistake in the shared decomposition."""
+    def shared_hosvd(psi, q, ranks, targets=None):
+        psi = np.asarray(psi, dtype=np.float64)
+        N = psi.shape[0]
+        tg = range(N) if targets is None else list(targets)
+        sq = [np.sqrt(np.asarray(v, dtype=np.float64)) for v in q]
+        scale = sq[0][:, None, None] * sq[1][None, :, None] * sq[2][None, None, :]
+        if mistake == "unweighted":
+            scale = np.ones_like(scale)
+        U, sv = [], []
+        for d in range(3):
+            dd = (d + 1) % 3 if mistake == "wrong_mode" else d
+            if mistake == "unique_pairs_only":
+                cols = [O.unfold(scale * psi[i] * psi[j], dd) for i in tg for j in range(N) if j >= i]
+            else:
+                cols = [O.unfold(scale * psi[i] * psi[j], dd) for i in tg for j in range(N)]
+            W_, s_, _ = np.linalg.svd(np.concatenate(cols, axis=1), full_matrices=False)
+            if W_.shape[0] != len(q[d]):
+                raise ValueError("mode extent")
+            U.append(W_[:, :ranks[d]] / sq[d][:, None])
+            sv.append(s_)
+        return U, sv
+    return shared_hosvd
+
+
+@pytest.mark.parametrize("mistake", ["unweighted", "wrong_mode", "unique_pairs_only"])
+def test_hosvd_mistakes_are_caught(monkeypatch, mistake):
+    monkeypatch.setattr(O, "shared_hosvd", _hosvd_mutant(mistake))
+    assert _hosvd_pins_fail(), f"planted mistake {mistake} in the shared decomposition went unnoticed"
