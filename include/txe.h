@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define TXE_ABI_VERSION 3
+#define TXE_ABI_VERSION 4
 
 typedef enum {
   TXE_OK = 0,
@@ -134,7 +134,18 @@ typedef struct {
                             /* pair), its own Chat_k^d = V_ij,d^T C_k^d U_ij,d and its own  */
                             /* back-projection.  Requires FP64 compute and n[d] <= 96       */
                             /* (TXE_ERR_UNSUPPORTED otherwise).                             */
+  int32_t form;             /* TXE_FORM_CORE (0): phi_ij = P C P rho_ij, the kernel sum in   */
+                            /* the Tucker core, then back-projected (eqs. `gauss`, `final`   */
+                            /* evaluated in core space).  TXE_FORM_COLLOCATION (1): the 1-D  */
+                            /* convolutions evaluated at every node and the 3-D field        */
+                            /* reconstructed, phi_ij = sum_k w_k G_ij x_d (C_k^d U_d), with  */
+                            /* e_ij = <rho_ij, phi_ij>_W on the grid (section "Convolution   */
+                            /* operation", eqs. `quadVal`, `discInteg`, `final`).  The       */
+                            /* collocation form needs FP64 compute and shared bases          */
+                            /* (TXE_ERR_UNSUPPORTED otherwise).                              */
 } txe_apply_args;
+
+enum { TXE_FORM_CORE = 0, TXE_FORM_COLLOCATION = 1 };
 
 /* ABI version (TXE_ABI_VERSION). */
 int32_t txe_abi_version(void);
@@ -222,6 +233,28 @@ txe_status txe_system_conv(const txe_system *sys, int32_t mode, double *C_out, d
 txe_status txe_fe_mesh_1d(const double *edges, int32_t ncells, int32_t p, double *x, double *q);
 txe_status txe_fe_conv_matrices(const double *edges, int32_t ncells, int32_t p, const double *alpha, int32_t K,
                                 double *C);
+
+/* Bases shared by all pairs (eq. `TuckerDecompField` with one set of
+ * factors for every pair): per mode d the leading r[d] left singular vectors
+ * of the mode-d unfolding of all pair densities psi_i psi_j (i over the
+ * targets [i0, i0 + Ni), j over all N orbitals) in the W inner product -- a
+ * higher-order SVD of the stacked pair densities, computed on the device
+ * without forming any pair density: the Gram matrix of each unfolding from
+ * the orbitals' own products (sum over pairs factorised over i and j, FP64
+ * MFMA), then its eigenvectors by cyclic Jacobi rotations.
+ *   n: the grid extents (multiples of 4 in [4, 512]); q: host, the 1-D
+ *   weights per mode (finite, > 0); psi: device, N x n0 x n1 x n2 orbitals,
+ *   dtype TXE_DTYPE_F64 or _F32; r: the ranks, 1 <= r[d] <= n[d].
+ *   U_out[d]: host, n[d] x r[d] row-major, the q-orthonormal bases
+ *   (U^T diag(q) U = I), columns by decreasing singular value, each signed so
+ *   that its largest-magnitude entry is positive.  sv_out (may be NULL, as
+ *   may each sv_out[d]): host, n[d] singular values per mode, descending.
+ * Setup call: allocates its device workspace for the call's duration (up to
+ * ~0.5 GiB of staging), runs on the context stream and synchronises it.
+ * Errors: TXE_ERR_ARG / _SHAPE (nothing run), TXE_ERR_NOMEM, TXE_ERR_DEVICE. */
+txe_status txe_hosvd_bases(txe_context *ctx, const int32_t n[3], const double *const q[3], const void *psi,
+                           int32_t dtype, int32_t N, int32_t i0, int32_t Ni, const int32_t r[3],
+                           double *const U_out[3], double *const sv_out[3]);
 
 /* Workspace bytes one apply with these arguments needs. */
 txe_status txe_workspace_query(txe_context *ctx, const txe_system *sys, const txe_apply_args *args,

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libtxe.so")
 
 SOURCES = ["txe_core_f32_5.hip", "txe_core_f32_4.hip", "txe_core_f32.hip", "txe_core_f64.hip",
            "txe_core_f64_45.hip", "txe_core_bf16.hip", "txe_back.hip", "txe_proj.hip", "txe_chunk.hip", "txe_pairbases.hip",
-           "txe_ace.hip", "txe_ceiling.hip", "txe_scratch.hip", "txe_api.cpp", "txe_setup.cpp", "txe_fe.cpp"]
+           "txe_ace.hip", "txe_ceiling.hip", "txe_scratch.hip", "txe_modes.hip", "txe_colloc.hip", "txe_hosvd.hip", "txe_api.cpp", "txe_setup.cpp", "txe_fe.cpp"]
 ARCH = "gfx950"
 
 

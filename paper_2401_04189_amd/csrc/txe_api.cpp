@@ -90,6 +90,8 @@ struct txe_system {
   // per-pair bases: D C_k^d D^-1 (D = diag(sqrt(q_d)), [K][n][n] per mode) and w_k
   double *csdev[3] = {nullptr, nullptr, nullptr};
   double *wdev = nullptr;
+  // collocation form: A_k^d = C_k^d U_d ([K][n][r] per mode)
+  double *acol[3] = {nullptr, nullptr, nullptr};
 };
 
 #define HIP_TRY(expr)                                                                        \
@@ -486,6 +488,7 @@ extern "C" txe_status txe_system_destroy(txe_system *sys) {
   for (int d = 0; d < 3; ++d) {
     if (sys->qdev[d]) hipFree(sys->qdev[d]);
     if (sys->csdev[d]) hipFree(sys->csdev[d]);
+    if (sys->acol[d]) hipFree(sys->acol[d]);
   }
   if (sys->wdev) hipFree(sys->wdev);
   delete sys;
@@ -636,6 +639,28 @@ extern "C" txe_status txe_system_create(txe_context *ctx, const txe_system_desc 
     }
     S->csdev[d] = (double *)p;
   }
+  // tables of the collocation form: A_k^d = C_k^d U_d (long double sums)
+  for (int d = 0; d < 3; ++d) {
+    const int n = S->n[d], r = S->r[d];
+    std::vector<double> A((size_t)S->K * n * r);
+    for (int k = 0; k < S->K; ++k)
+      for (int a = 0; a < n; ++a) {
+        const double *Crow = S->C[d].data() + ((size_t)k * n + a) * n;
+        for (int s2 = 0; s2 < r; ++s2) {
+          long double acc = 0.0L;
+          for (int b = 0; b < n; ++b) acc += (long double)Crow[b] * S->U[d][(size_t)b * r + s2];
+          A[((size_t)k * n + a) * r + s2] = (double)acc;
+        }
+      }
+    void *p = nullptr;
+    if (hipMalloc(&p, A.size() * sizeof(double)) != hipSuccess ||
+        hipMemcpy(p, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      if (p) hipFree(p);
+      txe_system_destroy(S);
+      return fail(TXE_ERR_DEVICE, "upload of the collocation tables failed");
+    }
+    S->acol[d] = (double *)p;
+  }
   {
     void *p = nullptr;
     if (hipMalloc(&p, S->K * sizeof(double)) != hipSuccess ||
@@ -682,6 +707,99 @@ extern "C" txe_status txe_fe_conv_matrices(const double *edges, int32_t ncells, 
   return ok();
 }
 
+static txe_status device_failed(txe_context *ctx, hipError_t e);
+
+extern "C" txe_status txe_hosvd_bases(txe_context *ctx, const int32_t n[3], const double *const q[3], const void *psi,
+                                      int32_t dtype, int32_t N, int32_t i0, int32_t Ni, const int32_t r[3],
+                                      double *const U_out[3], double *const sv_out[3]) {
+  if (!ctx || !n || !q || !psi || !r || !U_out) return fail(TXE_ERR_ARG, "null argument");
+  if (dtype != TXE_DTYPE_F64 && dtype != TXE_DTYPE_F32) return fail(TXE_ERR_ARG, "dtype must be F64 or F32");
+  if (N < 1 || i0 < 0 || Ni < 1 || (long long)i0 + Ni > N)
+    return fail(TXE_ERR_SHAPE, "targets [%d, %d) not inside [0, %d)", i0, i0 + Ni, N);
+  for (int d = 0; d < 3; ++d) {
+    if (n[d] < 4 || n[d] > 512 || n[d] % 4 != 0)
+      return fail(TXE_ERR_SHAPE, "n[%d] = %d must be a multiple of 4 in [4, 512]", d, n[d]);
+    if (r[d] < 1 || r[d] > n[d]) return fail(TXE_ERR_SHAPE, "r[%d] = %d must be in [1, n[%d]]", d, r[d], d);
+    if (!q[d] || !U_out[d]) return fail(TXE_ERR_ARG, "q[%d] or U_out[%d] is null", d, d);
+    for (int a = 0; a < n[d]; ++a)
+      if (!std::isfinite(q[d][a]) || !(q[d][a] > 0)) return fail(TXE_ERR_ARG, "q[%d] must be finite and > 0", d);
+  }
+  if (ctx->sticky) return fail(TXE_ERR_DEVICE, "context is in a failed state: %s", ctx->sticky_msg.c_str());
+  HIP_TRY(hipSetDevice(ctx->device));
+  Dims D{};
+  D.n0 = n[0]; D.n1 = n[1]; D.n2 = n[2];
+  const long long ng = (long long)n[0] * n[1] * n[2];
+  const int nmax = std::max(n[0], std::max(n[1], n[2]));
+  long long mmax = 0, per_m_max = 0;
+  for (int d = 0; d < 3; ++d) {
+    mmax = std::max(mmax, ng / n[d]);
+    per_m_max = std::max(per_m_max, (long long)N * n[d]);
+  }
+  // staging of the orbitals: up to 64 Mi doubles (512 MiB), at least one m value
+  const long long tcap = std::max(per_m_max, std::min<long long>(64LL << 20, per_m_max * mmax));
+  const int ntile_max = (nmax + 15) / 16;
+  const int tile_pairs_min = 1;
+  const int ngroups = std::max(1, std::min(1024, 4096 / std::max(tile_pairs_min, ntile_max * (ntile_max + 1) / 2)));
+  std::vector<void *> bufs;
+  auto alloc = [&](size_t bytes) -> double * {
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+    bufs.push_back(p);
+    return (double *)p;
+  };
+  auto release = [&]() {
+    for (void *p : bufs) hipFree(p);
+    bufs.clear();
+  };
+  double *T = alloc((size_t)tcap * 8), *Spart = alloc((size_t)ngroups * ntile_max * ntile_max * 256 * 8);
+  double *S = alloc((size_t)nmax * nmax * 8), *V = alloc((size_t)nmax * nmax * 8);
+  double *qm = alloc((size_t)mmax * 8), *qd = alloc((size_t)nmax * 8), *tr = alloc(8);
+  if (!T || !Spart || !S || !V || !qm || !qd || !tr) {
+    release();
+    return fail(TXE_ERR_NOMEM, "device allocation of the decomposition's workspace failed");
+  }
+  hipStream_t s = ctx->stream;
+  std::vector<double> hS((size_t)nmax * nmax), hV((size_t)nmax * nmax), hq;
+  for (int d = 0; d < 3; ++d) {
+    const int nd = n[d];
+    const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+    hq.resize((size_t)n[e1] * n[e2]);
+    for (int u = 0; u < n[e1]; ++u)
+      for (int v = 0; v < n[e2]; ++v) hq[(size_t)u * n[e2] + v] = q[e1][u] * q[e2][v];
+    hipError_t e = hipMemcpyAsync(qm, hq.data(), hq.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(qd, q[d], (size_t)nd * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hosvd_mode_gram(psi, dtype == TXE_DTYPE_F64, D, d, N, i0, Ni, qm, qd, T, tcap, Spart, ngroups, S, s);
+    if (e == hipSuccess) e = hosvd_eigen(S, V, nd, tr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hS.data(), S, (size_t)nd * nd * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hV.data(), V, (size_t)nd * nd * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      release();
+      return device_failed(ctx, e);
+    }
+    // eigenvalues descending (ties by index); the leading r columns, each
+    // signed so that its largest-magnitude entry is positive, scaled by
+    // 1/sqrt(q) (q-orthonormal)
+    std::vector<int> order(nd);
+    for (int k = 0; k < nd; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return hS[(size_t)x * nd + x] > hS[(size_t)y * nd + y]; });
+    for (int k = 0; k < r[d]; ++k) {
+      const int c = order[k];
+      int imax = 0;
+      for (int a = 1; a < nd; ++a)
+        if (std::fabs(hV[(size_t)a * nd + c]) > std::fabs(hV[(size_t)imax * nd + c])) imax = a;
+      const double sg = hV[(size_t)imax * nd + c] < 0 ? -1.0 : 1.0;
+      for (int a = 0; a < nd; ++a) U_out[d][(size_t)a * r[d] + k] = sg * hV[(size_t)a * nd + c] / std::sqrt(q[d][a]);
+    }
+    if (sv_out && sv_out[d])
+      for (int k = 0; k < nd; ++k) sv_out[d][k] = std::sqrt(std::max(0.0, hS[(size_t)order[k] * nd + order[k]]));
+  }
+  release();
+  return ok();
+}
+
 extern "C" txe_status txe_system_conv(const txe_system *sys, int32_t mode, double *C_out, double *Chat_out) {
   if (!sys) return fail(TXE_ERR_ARG, "sys is null");
   if (mode < 0 || mode > 2) return fail(TXE_ERR_ARG, "mode must be 0, 1 or 2");
@@ -714,6 +832,8 @@ struct Plan {
   size_t off_T2, off_G, off_S1, off_epart, off_epair, off_psi32, total;
   std::vector<Chunk> chunks;
   // per-pair bases: per-pair element counts and offsets of its regions
+  bool colloc = false;  // collocation form: Y0, Y1 and phi per pair (FP64)
+  size_t off_Y0 = 0, off_Y1 = 0, off_phi = 0;
   bool pair_bases = false;
   size_t pb_X, pb_X1, pb_X2, pb_X3, pb_S, pb_B, pb_U[3], pb_ah, pb_c1, pb_c2, pb_u0;
   size_t off_X, off_X1, off_X2, off_X3, off_S, off_B, off_V, off_Wr, off_U[3], off_ah, off_c1, off_c2, off_u0;
@@ -732,8 +852,14 @@ static void plan_sizes(const Dims &D, Plan &pl) {
   const size_t P = (size_t)pl.Pmax;
   const size_t perT2 = pl.pair_bases ? 0 : (size_t)D.n0 * D.rp1 * D.rp2;
   const size_t perG = (size_t)D.rp0 * D.rp1 * D.rp2;
-  const size_t perS1 = pl.want_vx ? (size_t)D.n0 * D.rp2 * D.rp1 : 0;
+  const size_t perS1 = pl.want_vx && !pl.colloc ? (size_t)D.n0 * D.rp2 * D.rp1 : 0;
   size_t off = 0;
+  if (pl.colloc) {  // FP64 intermediates of the term-by-term reconstruction
+    const size_t P8 = P * sizeof(double);
+    pl.off_Y0 = off; off = align256(off + P8 * D.n0 * D.rp1 * D.rp2);
+    pl.off_Y1 = off; off = align256(off + P8 * D.n0 * D.n1 * D.rp2);
+    pl.off_phi = off; off = align256(off + P8 * D.n0 * D.n1 * D.n2);
+  }
   if (pl.pair_bases) {  // FP64 regions of the per-pair decomposition and tables
     const size_t RP = D.rp0, nmax = std::max(D.n0, std::max(D.n1, D.n2));
     pl.ldS = (int)nmax;
@@ -878,6 +1004,7 @@ static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, cons
   pl.symmetric = a->symmetric != 0;
   pl.want_vx = a->vxpsi != nullptr;
   pl.pair_bases = a->pair_bases != 0;
+  pl.colloc = a->form == TXE_FORM_COLLOCATION;
   pl.elt = pl.f64 ? sizeof(double) : sizeof(float);
   // the reduced-precision forms project FP64 orbitals from an FP32 copy
   // (half the bytes of the projection's orbital reads) when it fits beside
@@ -902,9 +1029,10 @@ static std::string plan_key(const txe_context *ctx, const txe_system *sys, const
   static const char *cname[] = {"f64", "f32", "bf16x3", "bf16x6"};
   const Dims &D = sys->D;
   char buf[256];
-  snprintf(buf, sizeof buf, "%s|n=%d,%d,%d|r=%d,%d,%d|K=%d|N=%d|Ni=%d|%s|%s|%s%s", ctx->arch.c_str(), D.n0, D.n1,
+  snprintf(buf, sizeof buf, "%s|n=%d,%d,%d|r=%d,%d,%d|K=%d|N=%d|Ni=%d|%s|%s|%s%s%s", ctx->arch.c_str(), D.n0, D.n1,
            D.n2, D.r0, D.r1, D.r2, D.K, a->N, a->symmetric ? a->N : a->Ni, cname[a->compute & 3],
-           a->symmetric ? "sym" : "block", a->vxpsi ? "vx" : "energy", a->pair_bases ? "|pair-bases" : "");
+           a->symmetric ? "sym" : "block", a->vxpsi ? "vx" : "energy", a->pair_bases ? "|pair-bases" : "",
+           a->form == TXE_FORM_COLLOCATION ? "|collocation" : "");
   return buf;
 }
 
@@ -939,6 +1067,13 @@ static txe_status validate_args(const txe_context *ctx, const txe_system *sys, c
   }
   if (a->out_weighted != 0 && a->out_weighted != 1) return fail(TXE_ERR_ARG, "out_weighted must be 0 or 1");
   if (a->pair_bases != 0 && a->pair_bases != 1) return fail(TXE_ERR_ARG, "pair_bases must be 0 or 1");
+  if (a->form != TXE_FORM_CORE && a->form != TXE_FORM_COLLOCATION)
+    return fail(TXE_ERR_ARG, "form must be TXE_FORM_CORE or TXE_FORM_COLLOCATION");
+  if (a->form == TXE_FORM_COLLOCATION) {
+    if (a->compute != TXE_COMPUTE_F64)
+      return fail(TXE_ERR_UNSUPPORTED, "the collocation form is implemented in FP64 compute only");
+    if (a->pair_bases) return fail(TXE_ERR_UNSUPPORTED, "the collocation form uses the system's shared bases");
+  }
   if (a->pair_bases) {
     if (a->compute != TXE_COMPUTE_F64)
       return fail(TXE_ERR_UNSUPPORTED, "per-pair bases are implemented in FP64 compute only");
@@ -1038,6 +1173,16 @@ static hipError_t run_plan(const txe_system *sys, const txe_apply_args *args, co
       pb.w = sys->wdev;
       pb.ps_ah = tb.ps_ah; pb.ps_c1 = tb.ps_c1; pb.ps_c2 = tb.ps_c2; pb.ps_u0 = tb.ps_u0;
       e = run_chunk_pp(tb, pb, c, pl.want_vx, s, prof);
+    } else if (pl.colloc) {
+      ChunkArgs<double> c = chunk_args<double>(sys, args, pl, ws);
+      c.pm = ch.pm; c.P = (int)ch.P; c.nbr = ch.nbr; c.br[0] = ch.br[0]; c.br[1] = ch.br[1];
+      CollocArgs cl{};
+      for (int d = 0; d < 3; ++d) cl.A[d] = sys->acol[d];
+      cl.w_host = sys->w.data();
+      cl.Y0 = (double *)(ws + pl.off_Y0);
+      cl.Y1 = (double *)(ws + pl.off_Y1);
+      cl.phi = (double *)(ws + pl.off_phi);
+      e = run_chunk_colloc(sys->t64.t, cl, c, pl.want_vx, s, prof);
     } else if (pl.f64) {
       ChunkArgs<double> c = chunk_args<double>(sys, args, pl, ws);
       c.pm = ch.pm; c.P = (int)ch.P; c.nbr = ch.nbr; c.br[0] = ch.br[0]; c.br[1] = ch.br[1];

@@ -105,6 +105,14 @@ struct PairBasesArgs {
   long long ps_c1, ps_c2, ps_ah, ps_u0;
 };
 
+// Workspace and per-system data of a chunk in the collocation form (FP64).
+struct CollocArgs {
+  const double *A[3];         // A_k^d = C_k^d U_d per mode, [K][n_d][r_d] (device)
+  const double *w_host;       // the K term weights (host)
+  double *Y0, *Y1;            // per pair: G x0 A0_k (n0 rp rp) and that x1 A1_k (n0 n1 rp)
+  double *phi;                // per pair: phi_ij (n0 n1 n2)
+};
+
 // Split-bf16 copies of the core kernel's term matrices (bf16 bit patterns).
 // Each FP64 value x is split into up to three bf16 parts, x ~ p0 + p1 + p2
 // (p0 = bf16(x), p1 = bf16(x - p0), p2 = bf16(x - p0 - p1)); a two-part
@@ -236,6 +244,11 @@ hipError_t launch_epair(const double *epart, int P, int parts, const PairMap &pm
 // regions (C1f, C2chain, Ahat, U0chain) with their strides.
 hipError_t run_chunk_pp(const Tables<double> &tb, const PairBasesArgs &pb, const ChunkArgs<double> &a, bool want_vx,
                         hipStream_t s, Prof *prof);
+// One chunk in the collocation form: projection onto the shared bases, the
+// term-by-term reconstruction phi = sum_k w_k G x_d (C_k^d U_d), the pair
+// energies on the grid and the accumulation of Vx psi (txe_colloc.hip).
+hipError_t run_chunk_colloc(const Tables<double> &tb, const CollocArgs &cl, const ChunkArgs<double> &a, bool want_vx,
+                            hipStream_t s, Prof *prof);
 
 // Runs one chunk (projection, core sum, back-projection, pair energies).
 // Returns hipSuccess or the first launch error.
@@ -266,6 +279,18 @@ hipError_t ace_comb(bool x64, bool o64, const double *A, int MR, int K, const vo
 // Device address of the allocation-free apply's scratch array on `device`
 // (txe_scratch.hip; the current device must be `device`).
 hipError_t scratch_address(int device, void **ptr);
+
+// Shared bases (txe_hosvd.hip): the mode-d Gram matrix S (n_d x n_d, FP64) of
+// the stacked sqrt(w)-scaled pair densities by the Gram identity (targets
+// [t0, t0 + nt), sources all N orbitals), staged through T (tcap doubles,
+// at least N n_d) and the per-group partial tiles Spart (ngroups * ceil(n_d /
+// 16)^2 * 256 doubles); qm_dev: the weights of the other two indices (C
+// order), qd_dev: q_d.  Then its eigen-decomposition S = V diag V^T (S
+// overwritten, its diagonal the eigenvalues), n_d even and <= 512.
+hipError_t hosvd_mode_gram(const void *psi, bool psi64, const Dims &D, int d, int N, int t0, int nt,
+                           const double *qm_dev, const double *qd_dev, double *T, long long tcap, double *Spart,
+                           int ngroups, double *S, hipStream_t s);
+hipError_t hosvd_eigen(double *S, double *V, int n, double *trace_tmp, hipStream_t s);
 
 // Ceiling microbenchmarks (txe_ceiling.hip): kind 0 f64, 1 f32, 2 bf16 MFMA
 // in TFLOP/s; 3 HBM stream in GB/s.  Allocates, synchronises the stream.

@@ -1,0 +1,133 @@
+// Generic FP64 tensor-mode products on 16x16x4 FP64 MFMA and the Hadamard
+// accumulation of Vx psi over sources (see txe_modes.h).
+#include <algorithm>
+
+#include "txe_dev.h"
+#include "txe_modes.h"
+
+namespace txe {
+
+namespace {
+
+constexpr int NJ = 4;  // 16-column tiles of the unfolding per wavefront (they share the M fragment)
+
+// One wavefront per (pair, 16-row tile of o, NJ 16-column tiles of the other
+// two indices); K = 4 MFMA steps over i.
+__global__ __launch_bounds__(256) void k_mode(const double *__restrict__ X, long long xs, int A, int B, int C, int d,
+                                              int nin, const double *__restrict__ Mm, long long ms, int ldm, int Mt,
+                                              int nout, const double *__restrict__ qout, double yscale, int accum,
+                                              double *__restrict__ Y, long long ys, int P) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int ext = d == 0 ? A : d == 1 ? B : C;
+  const long long J = (long long)A * B * C / ext;  // columns of the unfolding
+  const int Bo = d == 1 ? nout : B, Co = d == 2 ? nout : C;
+  const int nto = (nout + 15) >> 4;
+  const long long ntj = (J + 16 * NJ - 1) / (16 * NJ);
+  const long long item = (long long)blockIdx.x * 4 + wave;
+  if (item >= (long long)P * nto * ntj) return;  // whole wavefront (item is uniform)
+  const long long tj = item % ntj;
+  const int to = (int)((item / ntj) % nto);
+  const int p = (int)(item / (ntj * nto));
+  const double *Xp = X + (size_t)p * xs;
+  const double *Mp = Mm + (size_t)p * ms;
+  const int o = 16 * to + lr;
+  const bool vo = o < nout;
+  const int oc = vo ? o : nout - 1;
+  long long jc[NJ];
+  bool vj[NJ];
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const long long j = 16 * (NJ * tj + u) + lr;
+    vj[u] = j < J;
+    jc[u] = vj[u] ? j : J - 1;
+  }
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc[NJ];
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) acc[u] = (d4){0.0, 0.0, 0.0, 0.0};
+  for (int i0 = 0; i0 < nin; i0 += 4) {
+    const int i = i0 + lg;
+    const bool vi = i < nin;
+    const int ic = vi ? i : nin - 1;
+    const double mv = Mt ? Mp[(size_t)oc * ldm + ic] : Mp[(size_t)ic * ldm + oc];
+    double xv[NJ];
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) xv[u] = Xp[unfold_at(d, B, C, ic, jc[u])];
+    const double a = (vo && vi) ? mv : 0.0;
+#pragma unroll
+    for (int u = 0; u < NJ; ++u)
+      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (vj[u] && vi) ? xv[u] : 0.0, acc[u], 0, 0, 0);
+  }
+  double *Yp = Y + (size_t)p * ys;
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const long long j = 16 * (NJ * tj + u) + lr;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int orow = 16 * to + 4 * v + lg;  // FP64 accumulator row order
+      if (orow < nout && vj[u]) {
+        double val = yscale * (qout ? acc[u][v] / sqrt(qout[orow]) : acc[u][v]);
+        double *y = Yp + unfold_at(d, Bo, Co, orow, j);
+        if (accum) val += *y;
+        *y = val;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_accum(const double *__restrict__ phi, int phi_acb,
+                                               const double *__restrict__ psi, Dims D, PairMap pm, BackRange br,
+                                               double *__restrict__ vx, const double *__restrict__ out_scale,
+                                               int weighted, const double *__restrict__ q0,
+                                               const double *__restrict__ q1, const double *__restrict__ q2) {
+  const long long ng = (long long)D.n0 * D.n1 * D.n2;
+  const long long total = (long long)br.nt * ng;
+  const double scale = out_scale ? *out_scale : 1.0;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
+    const int tl = (int)(e / ng);
+    const long long g = e - (long long)tl * ng;
+    const int c = (int)(g % D.n2), b = (int)((g / D.n2) % D.n1), a = (int)(g / ((long long)D.n1 * D.n2));
+    const int t = br.t0 + tl;
+    double *out = vx + (size_t)(t - br.out0) * ng + g;
+    double acc = br.acc_in ? *out : 0.0;
+    const long long pg = phi_acb ? ((long long)a * D.n2 + c) * D.n1 + b : g;
+    for (int s = br.s0; s < br.s0 + br.ns; ++s) {
+      const long long pl = local_pair(pm, br, t, s);
+      acc += psi[(size_t)s * ng + g] * phi[(size_t)pl * ng + pg];
+    }
+    if (br.finish) {
+      double val = -scale * acc;
+      if (weighted) val *= q0[a] * q1[b] * q2[c];
+      *out = val;
+    } else {
+      *out = acc;
+    }
+  }
+}
+
+inline unsigned grid_for(long long n) { return (unsigned)std::min<long long>((n + 255) / 256, 65536); }
+
+}  // namespace
+
+hipError_t launch_mode_f64(const double *X, long long xs, int A, int B, int C, int d, int nin, const double *M,
+                           long long ms, int ldm, int Mt, int nout, const double *qout, double yscale, int accum,
+                           double *Y, long long ys, int P, hipStream_t s) {
+  const int ext = d == 0 ? A : d == 1 ? B : C;
+  const long long J = (long long)A * B * C / ext;
+  const long long waves = (long long)P * ((nout + 15) / 16) * ((J + 16 * NJ - 1) / (16 * NJ));
+  hipLaunchKernelGGL(k_mode, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, X, xs, A, B, C, d, nin, M, ms, ldm, Mt,
+                     nout, qout, yscale, accum, Y, ys, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_accum_f64(const double *phi, int phi_acb, const double *psi, const Dims &D, const PairMap &pm,
+                            const BackRange &br, double *vx, const double *out_scale, int weighted,
+                            const double *const q[3], hipStream_t s) {
+  const long long ng = (long long)D.n0 * D.n1 * D.n2;
+  hipLaunchKernelGGL(k_accum, dim3(grid_for((long long)br.nt * ng)), dim3(256), 0, s, phi, phi_acb, psi, D, pm, br, vx,
+                     out_scale, weighted, q[0], q[1], q[2]);
+  return hipGetLastError();
+}
+
+}  // namespace txe

@@ -10,11 +10,11 @@
 //                  mode-d unfolding
 //     k_pp_jacobi  S = V diag(lambda) V^T by cyclic Jacobi rotations in LDS
 //                  (one workgroup per pair)
-//     k_pp_mode    B = X x_d V^T, the unfolding in that eigenbasis
+//     mode product B = X x_d V^T, the unfolding in that eigenbasis
 //     k_pp_gram    S = B_(d) B_(d)^T, nearly diagonal
 //     k_pp_jacobi  its r_d leading eigenvectors Wr
 //     k_pp_rotate  Ut_d = V Wr, the leading left singular vectors of X_(d)
-//     k_pp_mode    X <- B x_d Wr^T = X x_d Ut_d^T, the truncation of mode d
+//     mode product X <- B x_d Wr^T = X x_d Ut_d^T, the truncation of mode d
 //   The second stage recovers the accuracy the Gram matrix loses: one
 //   eigen-decomposition of X X^T fixes a singular vector only to about
 //   eps sigma_1^2 / (sigma_i^2 - sigma_j^2), while the rows of B carry their
@@ -26,22 +26,15 @@
 //                (D = diag(sqrt(q_d))) written in the core kernel's FP64
 //                table layouts, plus the U0 fragments of its epilogue
 //   core kernel  (the shared-basis kernel, tables offset per pair)
-//   k_pp_mode    S1 x U2, then x U1: phi of every pair
-//   k_pp_accum   Vx psi_t -= sum_s psi_s phi_ts, sources ascending
+//   mode products S1 x U2, then x U1: phi of every pair
+//   accumulation Vx psi_t -= sum_s psi_s phi_ts, sources ascending
 //
 // U_d = Ut_d / sqrt(q_d) is q-orthonormal, V_d = diag(q_d) U_d, so G, Phi and
 // e_ij = <G, Phi> keep the meaning they have with shared bases.
 #include "txe_dev.h"
+#include "txe_modes.h"
 
 namespace txe {
-
-// element of the mode-d unfolding of a tensor with extents (A, B, C): row
-// `row` (index along mode d), column m (the other two indices, C order)
-__device__ __forceinline__ long long unfold_at(int d, int B, int C, int row, long long m) {
-  if (d == 0) return (long long)row * B * C + m;
-  if (d == 1) return ((m / C) * B + row) * (long long)C + (m % C);
-  return m * C + row;
-}
 
 // X[p] = sqrt(q0[a] q1[b] q2[c]) psi_i[a,b,c] psi_j[a,b,c] for every pair of the chunk
 __global__ __launch_bounds__(256) void k_pp_rho(const double *__restrict__ psi, Dims D, PairMap pm, int P,
@@ -192,54 +185,6 @@ __global__ __launch_bounds__(256) void k_pp_jacobi(const double *__restrict__ S,
   }
 }
 
-// Y[p] = X[p] x_d M_p: Y(.., o, ..) = f_o sum_{i < nin} M_p(i, o) X(.., i, ..),
-// with M_p(i, o) = Mt ? Mm[p][o][i] : Mm[p][i][o] (row-major, leading
-// dimension ldm, pair stride mstride) and f_o = 1 / sqrt(qout[o]) (1 when
-// qout is null).  X has extents (A, B, C) (pair stride xs), Y the same with
-// the mode-d extent replaced by nout (pair stride ys).  One wavefront per
-// (pair, 16-row tile of o, 16-column tile of the other two indices); K = 4
-// MFMA steps over i.
-__global__ __launch_bounds__(256) void k_pp_mode(const double *__restrict__ X, long long xs, int A, int B, int C,
-                                                 int d, int nin, const double *__restrict__ Mm, long long mstride,
-                                                 int ldm, int Mt, int nout, const double *__restrict__ qout,
-                                                 double *__restrict__ Y, long long ys, int P) {
-  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int ext = d == 0 ? A : d == 1 ? B : C;
-  const long long J = (long long)A * B * C / ext;  // columns of the unfolding
-  const int Bo = d == 1 ? nout : B, Co = d == 2 ? nout : C;
-  const int nto = (nout + 15) >> 4;
-  const long long ntj = (J + 15) >> 4;
-  const long long item = (long long)blockIdx.x * 4 + wave;
-  if (item >= (long long)P * nto * ntj) return;  // whole wavefront
-  const long long tj = item % ntj;
-  const int to = (int)((item / ntj) % nto);
-  const int p = (int)(item / (ntj * nto));
-  const double *Xp = X + (size_t)p * xs;
-  const double *Mp = Mm + (size_t)p * mstride;
-  const int o = 16 * to + lr;
-  const long long j = 16 * tj + lr;
-  const bool vo = o < nout, vj = j < J;
-  const int oc = vo ? o : nout - 1;
-  const long long jc = vj ? j : J - 1;
-  typedef double d4 __attribute__((ext_vector_type(4)));
-  d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int i0 = 0; i0 < nin; i0 += 4) {
-    const int i = i0 + lg;
-    const bool vi = i < nin;
-    const int ic = vi ? i : nin - 1;
-    const double mv = Mt ? Mp[(size_t)oc * ldm + ic] : Mp[(size_t)ic * ldm + oc];
-    const double xv = Xp[unfold_at(d, B, C, ic, jc)];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64((vo && vi) ? mv : 0.0, (vj && vi) ? xv : 0.0, acc, 0, 0, 0);
-  }
-  double *Yp = Y + (size_t)p * ys;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int orow = 16 * to + 4 * v + lg;  // FP64 accumulator row order
-    if (orow < nout && vj) Yp[unfold_at(d, Bo, Co, orow, j)] = qout ? acc[v] / sqrt(qout[orow]) : acc[v];
-  }
-}
-
 // Ut[p] = V[p] Wr[p]: V n x n (row-major), Wr n x r (row-major), both with
 // pair stride vs; Ut n x r with pair stride us
 __global__ __launch_bounds__(256) void k_pp_rotate(const double *__restrict__ V, const double *__restrict__ Wr,
@@ -343,40 +288,6 @@ __global__ __launch_bounds__(256) void k_pp_u0chain(const double *__restrict__ U
   }
 }
 
-// Vx psi_t (+)= -sum_s psi_s(a,b,c) phi_ts(a,b,c) over the sources of a
-// back-projection range, ascending, with phi stored [a][c][b] per pair;
-// acc_in / finish as in the shared-basis back-projection (raw sums in vx
-// between chunks; the last one writes -scale * sum, times w if weighted).
-__global__ __launch_bounds__(256) void k_pp_accum(const double *__restrict__ phi, const double *__restrict__ psi,
-                                                  Dims D, PairMap pm, BackRange br, double *__restrict__ vx,
-                                                  const double *__restrict__ out_scale, int weighted,
-                                                  const double *__restrict__ q0, const double *__restrict__ q1,
-                                                  const double *__restrict__ q2) {
-  const long long ng = (long long)D.n0 * D.n1 * D.n2;
-  const long long total = (long long)br.nt * ng;
-  const double scale = out_scale ? *out_scale : 1.0;
-  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total; e += (long long)gridDim.x * 256) {
-    const int tl = (int)(e / ng);
-    const long long g = e - (long long)tl * ng;
-    const int c = (int)(g % D.n2), b = (int)((g / D.n2) % D.n1), a = (int)(g / ((long long)D.n1 * D.n2));
-    const int t = br.t0 + tl;
-    double *out = vx + (size_t)(t - br.out0) * ng + g;
-    double acc = br.acc_in ? *out : 0.0;
-    const long long pg = ((long long)a * D.n2 + c) * D.n1 + b;  // phi's [a][c][b] order
-    for (int s = br.s0; s < br.s0 + br.ns; ++s) {
-      const long long pl = local_pair(pm, br, t, s);
-      acc += psi[(size_t)s * ng + g] * phi[(size_t)pl * ng + pg];
-    }
-    if (br.finish) {
-      double val = -scale * acc;
-      if (weighted) val *= q0[a] * q1[b] * q2[c];
-      *out = val;
-    } else {
-      *out = acc;
-    }
-  }
-}
-
 // ------------------------------------------------------------------------------------
 // one chunk with per-pair bases
 // ------------------------------------------------------------------------------------
@@ -404,7 +315,6 @@ hipError_t run_chunk_pp(const Tables<double> &tb, const PairBasesArgs &pb, const
   for (int d = 0; d < 3; ++d) {
     const long long vol = (long long)ext[0] * ext[1] * ext[2];
     const int nt = (n[d] + 15) / 16;
-    const long long ntj = (vol / ext[d] + 15) / 16;  // 16-column tiles of the unfolding
     const size_t lds = (size_t)2 * n[d] * n[d] * sizeof(double);
     if (lds > 64 * 1024) {
       if ((e = hipFuncSetAttribute((const void *)k_pp_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
@@ -415,9 +325,9 @@ hipError_t run_chunk_pp(const Tables<double> &tb, const PairBasesArgs &pb, const
     hipLaunchKernelGGL(k_pp_gram, dim3(waves_grid((long long)P * nt * nt)), dim3(256), 0, s, cur, P, d, ext[0],
                        ext[1], ext[2], pb.ldS, pb.S);
     hipLaunchKernelGGL(k_pp_jacobi, dim3(P), dim3(256), lds, s, (const double *)pb.S, n[d], pb.ldS, n[d], pb.V, ss);
-    hipLaunchKernelGGL(k_pp_mode, dim3(waves_grid((long long)P * nt * ntj)), dim3(256), 0, s, cur, vol, ext[0],
-                       ext[1], ext[2], d, n[d], (const double *)pb.V, ss, n[d], 0, n[d], (const double *)nullptr,
-                       pb.B, vol, P);
+    if ((e = launch_mode_f64(cur, vol, ext[0], ext[1], ext[2], d, n[d], pb.V, ss, n[d], 0, n[d], nullptr, 1.0, 0, pb.B,
+                             vol, P, s)) != hipSuccess)
+      return e;
     // second stage: the r_d leading eigenvectors Wr of B_(d) B_(d)^T, Ut_d = V Wr
     hipLaunchKernelGGL(k_pp_gram, dim3(waves_grid((long long)P * nt * nt)), dim3(256), 0, s, (const double *)pb.B, P,
                        d, ext[0], ext[1], ext[2], pb.ldS, pb.S);
@@ -425,13 +335,12 @@ hipError_t run_chunk_pp(const Tables<double> &tb, const PairBasesArgs &pb, const
     hipLaunchKernelGGL(k_pp_rotate, dim3(grid_for((long long)P * n[d] * r[d])), dim3(256), 0, s, (const double *)pb.V,
                        (const double *)pb.Wr, ss, n[d], r[d], pb.Ut[d], (long long)n[d] * r[d], P);
     // truncation: X <- B x_d Wr^T
-    const int nto = (r[d] + 15) / 16;
     int oext[3] = {ext[0], ext[1], ext[2]};
     oext[d] = r[d];
     const long long ovol = (long long)oext[0] * oext[1] * oext[2];
-    hipLaunchKernelGGL(k_pp_mode, dim3(waves_grid((long long)P * nto * ntj)), dim3(256), 0, s, (const double *)pb.B,
-                       vol, ext[0], ext[1], ext[2], d, n[d], (const double *)pb.Wr, ss, r[d], 0, r[d],
-                       (const double *)nullptr, nxt[d], ovol, P);
+    if ((e = launch_mode_f64(pb.B, vol, ext[0], ext[1], ext[2], d, n[d], pb.Wr, ss, r[d], 0, r[d], nullptr, 1.0, 0,
+                             nxt[d], ovol, P, s)) != hipSuccess)
+      return e;
     cur = nxt[d];
     ext[d] = r[d];
   }
@@ -475,22 +384,15 @@ hipError_t run_chunk_pp(const Tables<double> &tb, const PairBasesArgs &pb, const
   // S1[p] (n0 x RP(gamma') x RP(beta'), rows gamma' < r2) x_gamma' U2 -> (n0, n2, RP), then x_beta' U1 -> phi [a][c][b]
   {
     const int RP = D.rp0;
-    const long long J1 = (long long)D.n0 * RP;
-    hipLaunchKernelGGL(k_pp_mode, dim3(waves_grid((long long)P * ((D.n2 + 15) / 16) * ((J1 + 15) / 16))), dim3(256),
-                       0, s, (const double *)a.S1, (long long)D.n0 * RP * RP, D.n0, RP, RP, 1, D.r2,
-                       (const double *)pb.Ut[2], (long long)D.n2 * D.r2, D.r2, 1, D.n2, a.qdev[2], pb.X1,
-                       (long long)D.n0 * D.n2 * RP, P);
-    const long long J2 = (long long)D.n0 * D.n2;
-    hipLaunchKernelGGL(k_pp_mode, dim3(waves_grid((long long)P * ((D.n1 + 15) / 16) * ((J2 + 15) / 16))), dim3(256),
-                       0, s, (const double *)pb.X1, (long long)D.n0 * D.n2 * RP, D.n0, D.n2, RP, 2, D.r1,
-                       (const double *)pb.Ut[1], (long long)D.n1 * D.r1, D.r1, 1, D.n1, a.qdev[1], pb.X, ng, P);
+    e = launch_mode_f64(a.S1, (long long)D.n0 * RP * RP, D.n0, RP, RP, 1, D.r2, pb.Ut[2], (long long)D.n2 * D.r2,
+                        D.r2, 1, D.n2, a.qdev[2], 1.0, 0, pb.X1, (long long)D.n0 * D.n2 * RP, P, s);
+    if (e == hipSuccess)
+      e = launch_mode_f64(pb.X1, (long long)D.n0 * D.n2 * RP, D.n0, D.n2, RP, 2, D.r1, pb.Ut[1],
+                          (long long)D.n1 * D.r1, D.r1, 1, D.n1, a.qdev[1], 1.0, 0, pb.X, ng, P, s);
   }
-  for (int b = 0; b < a.nbr && e == hipSuccess; ++b) {
-    hipLaunchKernelGGL(k_pp_accum, dim3(grid_for((long long)a.br[b].nt * ng)), dim3(256), 0, s, (const double *)pb.X,
-                       (const double *)a.psi, D, a.pm, a.br[b], (double *)a.vx, a.out_scale, a.weighted, a.qdev[0],
-                       a.qdev[1], a.qdev[2]);
-    e = hipGetLastError();
-  }
+  for (int b = 0; b < a.nbr && e == hipSuccess; ++b)
+    e = launch_accum_f64(pb.X, 1, (const double *)a.psi, D, a.pm, a.br[b], (double *)a.vx, a.out_scale, a.weighted,
+                         a.qdev, s);
   prof->end(s);
   return e;
 }

@@ -90,7 +90,8 @@ def traffic(fetch_csv, write_csv, out_md, title, key, cmd_f, cmd_w, alg_bytes=No
         f = sum(fetch[k]) / len(fetch[k]) * (sf or 1.0)
         w = sum(write.get(k, [0.0])) / max(len(write.get(k, [1])), 1) * (sw or 1.0)
         lines.append(f"| `{short(k)}` | {len(fetch[k])} | {f / 1e9:.2f} | {w / 1e9:.2f} |")
-        if re.search(r"k_core<", k):
+        want = "double" if key.endswith("f64") else "float"
+        if re.search(r"k_core<" + want, k):
             rec[key] = {"kernel_source_sha": sha, "kernel": short(k), "bytes_per_launch": round(f + w),
                         "fetch_bytes": round(f), "write_bytes": round(w), "fetch_scale": sf, "write_scale": sw}
             if alg_bytes:

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libtxe.so")
 
 COMPUTE = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16x6": 3}
 DTYPE = {"f64": 0, "f32": 1}
+FORM = {"core": 0, "collocation": 1}
 
 _c_int = ctypes.c_int32
 _c_dp = ctypes.POINTER(ctypes.c_double)
@@ -52,6 +53,7 @@ class ApplyArgs(ctypes.Structure):
         ("e_pairs", ctypes.c_void_p),
         ("e_orb", ctypes.c_void_p),
         ("pair_bases", _c_int),
+        ("form", _c_int),
     ]
 
 
@@ -70,6 +72,9 @@ SIGNATURES = {
     "txe_system_destroy": (_c_int, [ctypes.c_void_p]),
     "txe_system_conv": (_c_int, [ctypes.c_void_p, _c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "txe_fe_mesh_1d": (_c_int, [ctypes.c_void_p, _c_int, _c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "txe_hosvd_bases": (_c_int, [ctypes.c_void_p, ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_void_p),
+                                 ctypes.c_void_p, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_c_int),
+                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
     "txe_fe_conv_matrices": (_c_int, [ctypes.c_void_p, _c_int, _c_int, ctypes.c_void_p, _c_int, ctypes.c_void_p]),
     "txe_workspace_query": (_c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ApplyArgs),
                                      ctypes.POINTER(ctypes.c_size_t)]),
@@ -159,6 +164,29 @@ def fe_conv_matrices(edges, p, alpha):
     _check(lib().txe_fe_conv_matrices(edges.ctypes.data, len(edges) - 1, int(p), alpha.ctypes.data, len(alpha),
                                       C.ctypes.data))
     return C
+
+
+def hosvd_bases(ctx, psi, q, r, i0=0, Ni=None):
+    """Shared q-orthonormal bases U_d (n_d x r_d) of the stacked pair densities
+    of the orbitals `psi` (CUDA tensor N x n0 x n1 x n2), targets [i0, i0+Ni)
+    against all orbitals, from the library's device HOSVD; returns (U, sv)."""
+    import torch
+
+    if not psi.is_cuda or not psi.is_contiguous():
+        raise ValueError("psi must be a contiguous CUDA tensor")
+    N = psi.shape[0]
+    Ni = N - i0 if Ni is None else Ni
+    n = tuple(psi.shape[1:])
+    rr = tuple(r) if isinstance(r, (tuple, list)) else (r, r, r)
+    qs = [np.ascontiguousarray(v, dtype=np.float64) for v in q]
+    U = [np.empty((n[d], rr[d]), dtype=np.float64) for d in range(3)]
+    sv = [np.empty(n[d], dtype=np.float64) for d in range(3)]
+    ctx.set_stream(torch.cuda.current_stream(psi.device))
+    _check(lib().txe_hosvd_bases(ctx.h, (_c_int * 3)(*n), (ctypes.c_void_p * 3)(*[v.ctypes.data for v in qs]),
+                                 psi.data_ptr(), DTYPE["f64" if psi.dtype == torch.float64 else "f32"], N, int(i0),
+                                 int(Ni), (_c_int * 3)(*rr), (ctypes.c_void_p * 3)(*[u.ctypes.data for u in U]),
+                                 (ctypes.c_void_p * 3)(*[v.ctypes.data for v in sv])))
+    return U, sv
 
 
 def _stream_ptr(stream):
@@ -287,7 +315,7 @@ class System:
 
 
 def make_args(psi, compute="f64", symmetric=True, i0=0, Ni=None, vx=None, ex=None, e_pairs=None,
-              out_scale=None, out_weighted=False, e_orb=None, pair_bases=False):
+              out_scale=None, out_weighted=False, e_orb=None, pair_bases=False, form="core"):
     import torch
 
     a = ApplyArgs()
@@ -305,11 +333,12 @@ def make_args(psi, compute="f64", symmetric=True, i0=0, Ni=None, vx=None, ex=Non
     a.e_pairs = e_pairs.data_ptr() if e_pairs is not None else None
     a.e_orb = e_orb.data_ptr() if e_orb is not None else None
     a.pair_bases = 1 if pair_bases else 0
+    a.form = FORM[form]
     return a
 
 
 def _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_scale=None, out_weighted=False,
-             vx_out=None, want_orb=False, pair_bases=False):
+             vx_out=None, want_orb=False, pair_bases=False, form="core"):
     """ApplyArgs for one problem with freshly allocated outputs."""
     import torch
 
@@ -327,14 +356,15 @@ def _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_sca
     npairs = N * (N + 1) // 2 if symmetric else Ni * N
     ep = torch.empty(npairs, dtype=torch.float64, device=psi.device) if want_pairs else None
     eo = torch.empty(Ni, dtype=torch.float64, device=psi.device) if want_orb else None
-    a = make_args(psi, compute, symmetric, i0, Ni, vx, ex, ep, out_scale, out_weighted, eo, pair_bases)
+    a = make_args(psi, compute, symmetric, i0, Ni, vx, ex, ep, out_scale, out_weighted, eo, pair_bases, form)
     if want_orb:
         return a, vx, ex, ep, eo
     return a, vx, ex, ep
 
 
 def apply(ctx: Context, sysm: System, psi, compute="f64", symmetric=True, i0=0, Ni=None, want_vx=True,
-          want_pairs=False, out_scale=None, out_weighted=False, vx_out=None, want_orb=False, pair_bases=False):
+          want_pairs=False, out_scale=None, out_weighted=False, vx_out=None, want_orb=False, pair_bases=False,
+          form="core"):
     """Vx psi (targets) and E_x for the orbitals `psi` (a CUDA tensor N x n0 x n1 x n2).
 
     Returns (vx, ex, e_pairs): vx is None when want_vx is False; ex is a
@@ -342,11 +372,14 @@ def apply(ctx: Context, sysm: System, psi, compute="f64", symmetric=True, i0=0, 
     want_orb a fourth entry holds the exchange-matrix diagonal
     <psi_i, Vx psi_i>_W of each target (FP64, from the library).  With
     pair_bases every pair uses its own Tucker bases (the sequentially
-    truncated HOSVD of its density at the system's ranks)."""
+    truncated HOSVD of its density at the system's ranks).  form "core"
+    evaluates the kernel sum in the Tucker core and back-projects it;
+    "collocation" evaluates the 1-D convolutions at every node and
+    reconstructs phi on the grid (FP64)."""
     import torch
 
     out = _prepare(sysm, psi, compute, symmetric, i0, Ni, want_vx, want_pairs, out_scale, out_weighted, vx_out,
-                   want_orb, pair_bases)
+                   want_orb, pair_bases, form)
     ctx.set_stream(torch.cuda.current_stream(psi.device))
     _check(lib().txe_apply(ctx.h, sysm.h, ctypes.byref(out[0])))
     return tuple(out[1:])

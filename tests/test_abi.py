@@ -35,7 +35,7 @@ def test_abi_version_and_status_strings():
     L = txe.lib()
     hdr = open(HEADER).read()
     ver = int(re.search(r"#define TXE_ABI_VERSION (\d+)", hdr).group(1))
-    assert L.txe_abi_version() == ver == 3
+    assert L.txe_abi_version() == ver == 4
     for st in range(7):
         assert len(L.txe_status_string(st)) > 0
 
