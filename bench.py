@@ -397,15 +397,17 @@ def bench_fe(args, txe, torch, W):
     legs = {}
     load_cache(args, txe, ctx)
     side = max(1, min(args.steps, args.side_steps))
-    for name, compute, form, steps in (("f32", "f32", "core", args.steps), ("f64", "f64", "core", side),
-                                       ("f64_collocation", "f64", "collocation", side)):
+    for name, compute, form, pb, steps in (("f32", "f32", "core", False, args.steps),
+                                           ("f64", "f64", "core", False, side),
+                                           ("f64_collocation", "f64", "collocation", False, side),
+                                           ("f64_pair_bases", "f64", "core", True, side)):
         for _ in range(1 if name != "f32" else args.warmup):
-            txe.apply(ctx, sysm, psi, compute=compute, vx_out=vx, form=form)
+            txe.apply(ctx, sysm, psi, compute=compute, vx_out=vx, form=form, pair_bases=pb)
         torch.cuda.synchronize()
         ctx.profile(True)
         t0 = time.perf_counter()
         for _ in range(steps):
-            _, ex, _ = txe.apply(ctx, sysm, psi, compute=compute, vx_out=vx, form=form)
+            _, ex, _ = txe.apply(ctx, sysm, psi, compute=compute, vx_out=vx, form=form, pair_bases=pb)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
         kt = ctx.kernel_times()
@@ -425,6 +427,11 @@ def bench_fe(args, txe, torch, W):
                              "unit": "TFLOP/s", "frac": round(col_tf / PEAK_TFLOPS["f64"], 4),
                              "ms_per_apply": round(rec_ms, 3), "measured_peak": round(ctx.ceiling("f64"), 1)}
     col["dE_x_vs_core_form_Ha"] = abs(col["E_x"] - f64["E_x"])
+    ppb = legs["f64_pair_bases"]
+    ppb["dE_x_vs_shared_bases_Ha"] = abs(ppb["E_x"] - f64["E_x"])
+    ppb["note"] = ("kernel_ms: proj12 = the per-pair decompositions (two Gram/Jacobi stages and the truncation "
+                   "per mode), proj3 = the per-pair core matrices, core = the shared core kernel on them, "
+                   "back = the back-projection in the pair's bases")
     out = {
         "metric": METRIC, "value": f32["value"], "unit": "pair-convolutions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": f32["ms_per_step"], "higher_is_better": True,

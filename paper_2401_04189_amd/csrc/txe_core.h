@@ -158,7 +158,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   //          Chat2 fragments of the TZ gamma' tiles this workgroup's split
   //          meets, with the slab in LDS
   constexpr bool F32 = sizeof(T) == 4;
-  constexpr bool KM = F32 || MT <= 3;
+  constexpr bool KM = F32 || MT <= 3 || TZ < MT;
   constexpr bool PF = F32 || MT <= 2;
   constexpr bool C2S = F32 ? MT <= 3 : MT <= 2;
   constexpr bool HOLD_G = !KM && !F32 && C2S && (NW == 4 || MT <= 2);
@@ -170,8 +170,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
   constexpr int NKT = 4 * (MT - 1) + TL;  // K = 4 steps of the beta contraction
   // LDS slab row beta: for each of the 16 lanes of a fragment its MT gamma
   // values (gamma = 16 mg + lane) side by side, padded to LPL, so a lane
-  // reads all of its A fragments of one beta row with 16-byte loads
-  constexpr int LPL = MT <= 4 ? 4 : 8;
+  // reads all of its A fragments of one beta row with 16-byte loads (five
+  // FP64 values take three 16-byte pieces: LPL = 6 keeps the FP64 slab's
+  // double buffer within the LDS)
+  constexpr int LPL = MT <= 4 ? 4 : (F32 ? 8 : 6);
   constexpr int SROW = 16 * LPL;
   constexpr int SLAB = LDS_G ? RP * SROW : 0;
   T *Gs = reinterpret_cast<T *>(smem_raw);        // [2][RP][16][LPL] (LDS_G)
@@ -353,15 +355,43 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
         else if (gp >= g_lo && gp < g_hi) Zw[(gp - g_lo) * 16 + lr] = Zt[v];
       }
     };
+    // FP64 at four or five tiles (registers): the next slab arrives in two
+    // halves (the first during the W chain, the second during the Z chain)
+    // and the phase-B columns are loaded in the step that uses them
+    constexpr bool SPLIT = !F32 && MT >= 4;
+    constexpr int EPS1 = SPLIT ? (EPS + 1) / 2 : EPS;
+    auto kslab_load_part = [&](int a_, int j0, V16 (&v)[EPS1]) {
+      const V16 *src = reinterpret_cast<const V16 *>(Gp + (size_t)a_ * F);
+#pragma unroll
+      for (int j = 0; j < EPS1; ++j) v[j] = src[min((j0 + j) * CHT + tid, FP - 1)];
+    };
+    auto kslab_store_part = [&](int buf, int j0, const V16 (&v)[EPS1]) {
+#pragma unroll
+      for (int j = 0; j < EPS1; ++j) {
+        const int e4 = (j0 + j) * CHT + tid;
+        if (j0 + j < EPS && e4 < FP) {
+          const int beta = (PE * e4) / RP, g0 = (PE * e4) % RP;
+          const T *x = reinterpret_cast<const T *>(&v[j]);
+#pragma unroll
+          for (int q = 0; q < PE; ++q) {
+            const int gamma = g0 + q;
+            Gs[buf * SLAB + beta * SROW + lane_of(gamma & 15) * LPL + (gamma >> 4)] = x[q];
+          }
+        }
+      }
+    };
     auto kstep = [&](const int kq, const int alpha, const int step, AF &cur, AF &nxt) __attribute__((always_inline)) {
       const int k = NW * kq + wave;
       // the next step's slab (alpha + 1, or alpha 0 of the next term group)
       // and phase-B columns, issued before this step's work
       const bool last_a = alpha + 1 == D.r0;
       const bool more = !last_a || kq + 1 < nkq;  // uniform
-      V16 gnext[EPS];
-      kslab_load(last_a ? 0 : alpha + 1, gnext);
-      if (more) load_af(last_a ? 0 : alpha + 1, last_a ? kq + 1 : kq, nxt);
+      const int a_next = last_a ? 0 : alpha + 1;
+      V16 gnext[EPS1];
+      if constexpr (SPLIT) kslab_load_part(a_next, 0, gnext);
+      else kslab_load(a_next, gnext);
+      if constexpr (!SPLIT)
+        if (more) load_af(last_a ? 0 : alpha + 1, last_a ? kq + 1 : kq, nxt);
       T *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * ZSS;
       if (k < D.K) {
         acc W[MT];
@@ -382,6 +412,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
 #pragma unroll
           for (int mg = 0; mg < MT; ++mg) W[mg] = M::mma(gl[mg], tcb[kt], W[mg]);
         }
+        if constexpr (SPLIT) {  // first half stored, second half issued
+          if (more) kslab_store_part((step + 1) & 1, 0, gnext);
+          kslab_load_part(a_next, EPS1, gnext);
+        }
         acc Z[TZ];
 #pragma unroll
         for (int z = 0; z < TZ; ++z) Z[z] = zero4<acc>();
@@ -401,8 +435,17 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
           for (int idx = lane; idx < (g_hi - g_lo) * 16; idx += 64) Zw[(g_lo + (idx >> 4)) * ZRS + (idx & 15)] = (T)0;
         else
           for (int idx = lane; idx < gper * 16; idx += 64) Zw[idx] = (T)0;
+        if constexpr (SPLIT) {
+          if (more) kslab_store_part((step + 1) & 1, 0, gnext);
+          kslab_load_part(a_next, EPS1, gnext);
+        }
       }
-      if (more) kslab_store((step + 1) & 1, gnext);
+      if constexpr (SPLIT) {
+        if (more) kslab_store_part((step + 1) & 1, EPS1, gnext);
+        load_af(alpha, kq, cur);  // this step's phase-B columns, waited for after the barrier
+      } else {
+        if (more) kslab_store((step + 1) & 1, gnext);
+      }
       __syncthreads();
       const T *zb = Zs + (size_t)(step & 1) * zsz + lr;
       if constexpr (F32) {
@@ -665,9 +708,9 @@ hipError_t launch_core_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_
   const int gper = (a.D.r2 + a.NGS - 1) / a.NGS;
   if ((gper + NW - 1) / NW > NGW) return hipErrorInvalidValue;  // the plan gives every wavefront <= NGW rows
   constexpr int RP = 16 * MT;
-  constexpr bool km = sizeof(T) == 4 || MT <= 3;   // k_core's term-major forms (slab in LDS)
+  constexpr bool km = sizeof(T) == 4 || MT <= 3 || TZ < MT;   // k_core's term-major forms (slab in LDS)
   constexpr bool lds_g = km || sizeof(T) == 4;
-  constexpr size_t slab = lds_g ? (size_t)RP * 16 * (MT <= 4 ? 4 : 8) : 0;
+  constexpr size_t slab = lds_g ? (size_t)RP * 16 * (MT <= 4 ? 4 : (sizeof(T) == 4 ? 8 : 6)) : 0;
   const size_t zslot = sizeof(T) == 4 ? (size_t)RP * 20 + 16 : (size_t)gper * 16;  // k_core's Z slot
   const size_t lds = (2 * slab + 2 * NW * zslot) * sizeof(T);
   const unsigned nb = (unsigned)((size_t)a.P * a.D.MT1 * a.NGS);
@@ -698,21 +741,29 @@ inline int split_tiles(const Dims &D, int NGS) {
 }
 
 // One rank-tile count: the live chunks TL of the last tile of modes 1 and 2
-// and the held gamma' tiles TZ (3 when the split meets at most three tiles,
-// else all MT) select the instance.
+// and the held gamma' tiles TZ select the instance.  FP32 and FP64 at up to
+// three tiles: TZ = 3 when the split meets at most three tiles, else all MT.
+// FP64 at four or five tiles: splits of at most 16 rows (four per wavefront),
+// so a split meets one or two tiles and TZ is that count (term-major order);
+// TZ = MT (slab-major) only if a plan ever gave wider splits.
 template <typename T, int MT>
 hipError_t launch_core_for_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
   constexpr bool f64 = sizeof(T) == 8;
   constexpr int NW = f64 ? 4 : NW32[MT];
   constexpr int NGW = f64 ? NGW64[MT] : (NW == 8 ? NGW32x8[MT] : NGW32[MT]);
-  constexpr int TZ3 = MT <= 3 ? MT : 3;
-  const bool narrow = split_tiles(a.D, a.NGS) <= TZ3;
+  constexpr bool F64W = f64 && MT >= 4;
+  constexpr int TZA = F64W ? 1 : (MT <= 3 ? MT : 3);
+  constexpr int TZB = F64W ? 2 : TZA;
+  const int st = split_tiles(a.D, a.NGS);
+  const int pick = st <= TZA ? 0 : st <= TZB ? 1 : 2;
   const int rt = std::max(a.D.r1, a.D.r2) - 16 * (MT - 1);
   const int tl = std::min(4, std::max(1, (rt + 3) / 4));
-#define TXE_CORE_TL(TLV)                                                               \
-  case TLV:                                                                            \
-    return narrow ? launch_core_mt<T, MT, NGW, NW, TLV, TZ3>(tb, a, want_vx, s)        \
-                  : launch_core_mt<T, MT, NGW, NW, TLV, MT>(tb, a, want_vx, s);
+#define TXE_CORE_TL(TLV)                                                                  \
+  case TLV:                                                                               \
+    if (pick == 0) return launch_core_mt<T, MT, NGW, NW, TLV, TZA>(tb, a, want_vx, s);    \
+    if constexpr (TZB != TZA)                                                             \
+      if (pick == 1) return launch_core_mt<T, MT, NGW, NW, TLV, TZB>(tb, a, want_vx, s);  \
+    return launch_core_mt<T, MT, NGW, NW, TLV, MT>(tb, a, want_vx, s);
   switch (tl) {
     TXE_CORE_TL(1)
     TXE_CORE_TL(2)

@@ -150,7 +150,7 @@ inline unsigned blocks_for(long long waves) { return (unsigned)((waves + 3) / 4)
 // Register plans of the core kernels: gamma' rows per wavefront (the Phi
 // accumulators take MT * NGW * 4 values per lane) and wavefronts per
 // workgroup, per rank-tile count MT.
-constexpr int NGW64[MAX_MT + 1] = {0, 4, 8, 10, 8, 6};
+constexpr int NGW64[MAX_MT + 1] = {0, 4, 8, 10, 4, 4};
 constexpr int NGW32[MAX_MT + 1] = {0, 4, 8, 10, 12, 10};
 // FP32 core at small ranks: eight wavefronts per workgroup (two per SIMD, so
 // one hides the other's latencies), each with fewer Phi rows

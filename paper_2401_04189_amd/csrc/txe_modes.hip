@@ -46,6 +46,8 @@ __global__ __launch_bounds__(256) void k_mode(const double *__restrict__ X, long
   d4 acc[NJ];
 #pragma unroll
   for (int u = 0; u < NJ; ++u) acc[u] = (d4){0.0, 0.0, 0.0, 0.0};
+  // unrolled so that the loads of several K = 4 steps are in flight together
+#pragma unroll 4
   for (int i0 = 0; i0 < nin; i0 += 4) {
     const int i = i0 + lg;
     const bool vi = i < nin;
