@@ -325,6 +325,19 @@ def bench_batched(args, txe, torch, W):
     torch.cuda.synchronize()
     kt = ctx.kernel_times()
     ctx.profile(False)
+    # each system's core time on its own (where the batch's time goes)
+    per_system = []
+    for (h, p), v, s in zip(items, vxs, systems):
+        ctx.profile(True)
+        txe.apply(ctx, h, p, compute="f32", vx_out=v)
+        torch.cuda.synchronize()
+        ks = ctx.kernel_times()
+        ctx.profile(False)
+        np_ = s.N * (s.N + 1) // 2
+        per_system.append({"n": s.grid.n[0], "N": s.N, "r": s.r[0], "pairs": np_,
+                           "core_ms": round(ks["core"][0], 3),
+                           "core_tflops": round(core_kernel_flops_per_pair(s.grid.n, s.r, s.K) * np_
+                                                / (ks["core"][0] * 1e-3) / 1e12, 1)})
     # concurrency of the batch: the lane count with the fastest eager batch
     lane_ms = {}
     for ln in (1, 2, 4):
@@ -339,6 +352,10 @@ def bench_batched(args, txe, torch, W):
     core_ms = kt["core"][0]
     core_flops = sum(core_kernel_flops_per_pair(s.grid.n, s.r, s.K) * s.N * (s.N + 1) // 2 for s in systems)
     achieved = core_flops / (core_ms * 1e-3) / 1e12
+    # the same with every rank rounded up to the 16-row MFMA tiles it occupies
+    # (the kernels' M and N dimensions run over the padded rows)
+    pad = lambda r: [16 * ((v + 15) // 16) for v in r]  # noqa: E731
+    padded_flops = sum(core_kernel_flops_per_pair(s.grid.n, pad(s.r), s.K) * s.N * (s.N + 1) // 2 for s in systems)
     out = {
         "metric": METRIC,
         "value": round(npairs / graph_s, 1),
@@ -353,13 +370,15 @@ def bench_batched(args, txe, torch, W):
         "batched_eager": {"value": round(npairs / bat_s, 1), "ms_per_step": round(1e3 * bat_s, 4),
                           "ms_by_lanes": {str(k): round(v, 3) for k, v in lane_ms.items()}},
         "graph_over_separate": round(sep_s / graph_s, 3),
+        "per_system_core": per_system,
         "max_dE_x_fp32_vs_fp64_Ha": max(dE),
         "all_within_1e-5_Ha": max(dE) <= 1e-5,
         "launch_shapes": "defaults" if args.no_tune else
         {"from_cache": sum(t["source"] == "cache" for t in tuned), "tuned_live": sum(t["source"] != "cache" for t in tuned)},
         "roofline": {"bound": "mfma", "kernel": "core", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f32"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f32"], 4), "traffic": None,
-                     "launch_ms": round(core_ms / max(kt["core"][1], 1), 4)},
+                     "launch_ms": round(core_ms / max(kt["core"][1], 1), 4),
+                     "frac_on_padded_ranks": round(padded_flops / (core_ms * 1e-3) / 1e12 / PEAK_TFLOPS["f32"], 4)},
     }
     for h in handles:
         h.close()

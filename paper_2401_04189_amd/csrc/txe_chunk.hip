@@ -136,8 +136,8 @@ hipError_t run_chunk_t(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx,
 
 int core_rows(bool f64, int nsplit, int mt) {
   if (f64) return 4 * NGW64[mt];
-  if (nsplit == 3 || NW32[mt] == 4) return 4 * NGW32[mt];
-  return 8 * NGW32x8[mt];  // FP32 and two-part bf16 at up to three tiles
+  if (nsplit == 3 || (nsplit == 2 && mt >= 4) || NW32[mt] == 4) return 4 * NGW32[mt];  // four wavefronts
+  return 8 * NGW32x8[mt];  // eight: FP32 up to four tiles, two-part bf16 up to three
 }
 
 hipError_t launch_core_f64(const Tables<double> &tb, const ChunkArgs<double> &a, bool want_vx, hipStream_t s) {

@@ -741,19 +741,20 @@ inline int split_tiles(const Dims &D, int NGS) {
 }
 
 // One rank-tile count: the live chunks TL of the last tile of modes 1 and 2
-// and the held gamma' tiles TZ select the instance.  FP32 and FP64 at up to
-// three tiles: TZ = 3 when the split meets at most three tiles, else all MT.
-// FP64 at four or five tiles: splits of at most 16 rows (four per wavefront),
-// so a split meets one or two tiles and TZ is that count (term-major order);
-// TZ = MT (slab-major) only if a plan ever gave wider splits.
+// and the held gamma' tiles TZ select the instance: the fewest of the
+// instance's TZ choices that cover the gamma' tiles the widest split meets,
+// else all MT.  Up to three tiles TZ = MT.  FP32 at four tiles: TZ 2 or 3
+// (splits of at most 32 rows), at five: 3.  FP64 at four or five tiles:
+// splits of at most 16 rows (four per wavefront), TZ 1 or 2 (term-major
+// order); TZ = MT (slab-major for FP64) only if a plan ever gave wider splits.
 template <typename T, int MT>
 hipError_t launch_core_for_mt(const Tables<T> &tb, const ChunkArgs<T> &a, bool want_vx, hipStream_t s) {
   constexpr bool f64 = sizeof(T) == 8;
   constexpr int NW = f64 ? 4 : NW32[MT];
   constexpr int NGW = f64 ? NGW64[MT] : (NW == 8 ? NGW32x8[MT] : NGW32[MT]);
   constexpr bool F64W = f64 && MT >= 4;
-  constexpr int TZA = F64W ? 1 : (MT <= 3 ? MT : 3);
-  constexpr int TZB = F64W ? 2 : TZA;
+  constexpr int TZA = F64W ? 1 : (MT <= 3 ? MT : MT == 4 ? 2 : 3);
+  constexpr int TZB = F64W ? 2 : (MT == 4 ? 3 : TZA);
   const int st = split_tiles(a.D, a.NGS);
   const int pick = st <= TZA ? 0 : st <= TZB ? 1 : 2;
   const int rt = std::max(a.D.r1, a.D.r2) - 16 * (MT - 1);

@@ -152,9 +152,9 @@ inline unsigned blocks_for(long long waves) { return (unsigned)((waves + 3) / 4)
 // workgroup, per rank-tile count MT.
 constexpr int NGW64[MAX_MT + 1] = {0, 4, 8, 10, 4, 4};
 constexpr int NGW32[MAX_MT + 1] = {0, 4, 8, 10, 12, 10};
-// FP32 core at small ranks: eight wavefronts per workgroup (two per SIMD, so
-// one hides the other's latencies), each with fewer Phi rows
-constexpr int NW32[MAX_MT + 1] = {0, 8, 8, 8, 4, 4};
-constexpr int NGW32x8[MAX_MT + 1] = {0, 2, 4, 6, 0, 0};
+// FP32 core up to four tiles: eight wavefronts per workgroup (two per SIMD,
+// so one hides the other's latencies), each with fewer Phi rows
+constexpr int NW32[MAX_MT + 1] = {0, 8, 8, 8, 8, 4};
+constexpr int NGW32x8[MAX_MT + 1] = {0, 2, 4, 6, 4, 0};
 
 }  // namespace txe

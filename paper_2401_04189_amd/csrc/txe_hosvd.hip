@@ -182,7 +182,7 @@ __global__ __launch_bounds__(1024) void k_hv_jacobi(double *__restrict__ A, doub
       }
       __syncthreads();
       for (int e = tid; e < h * n; e += nth) {  // columns a, b of A and of V
-        const int k = e / n, i = e % n;
+        const int i = e / h, k = e % h;           // lanes along one row: nearby addresses
         if (sn[k] == 0.0) continue;
         const int a = pp[k], b = qq[k];
         const double c = cs[k], s = sn[k];

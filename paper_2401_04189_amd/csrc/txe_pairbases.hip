@@ -153,9 +153,10 @@ __global__ __launch_bounds__(256) void k_pp_jacobi(const double *__restrict__ S,
         As[b * n + j] = s * xa + c * xb;
       }
       __syncthreads();
-      // columns a, b of S and of V (right factor J)
+      // columns a, b of S and of V (right factor J); consecutive lanes take
+      // consecutive rotations of one row (distinct columns, distinct banks)
       for (int e = tid; e < h * n; e += 256) {
-        const int k = e / n, i = e % n;
+        const int i = e / h, k = e % h;
         const int a = pp[k], b = qq[k];
         const double c = cs[k], s = sn[k];
         const double xa = As[i * n + a], xb = As[i * n + b];
