@@ -171,3 +171,56 @@ def test_capture_needs_reserved_workspace_and_replays_match():
     del g
     sysm.close()
     c.close()
+
+
+GUARD = 4096  # guard elements on each side of every output
+
+
+def guarded(n, dtype, fill=0.0):
+    """(whole buffer, middle view of n elements); the guards hold a sentinel."""
+    buf = torch.full((n + 2 * GUARD,), -123456.75, dtype=dtype, device="cuda")
+    mid = buf[GUARD:GUARD + n]
+    mid.fill_(fill)
+    return buf, mid
+
+
+def guards_intact(buf, n):
+    return bool((buf[:GUARD] == -123456.75).all()) and bool((buf[GUARD + n:] == -123456.75).all())
+
+
+@pytest.mark.parametrize("variant", ["f64 sym", "f32 sym", "bf16x3 sym", "f64 block", "f32 block chunked",
+                                     "f64 collocation", "f64 pair bases", "f64 sym chunked"])
+def test_outputs_stay_inside_their_buffers(ctx, variant, monkeypatch):
+    """Every output written through the ABI lands inside its own buffer: each
+    sits between guard bands of a sentinel value, which must come back
+    unchanged, and psi is read-only."""
+    s = W.small_system(n=20, L=5.0, N=7, r=10, K=8, seed=52)
+    sysm = txe.System.from_workload(ctx, s)
+    comp = variant.split()[0]
+    symmetric = "block" not in variant
+    N = s.N
+    i0, Ni = (0, N) if symmetric else (2, 4)
+    ng = s.psi[0].numel()
+    pbuf, pmid = guarded(N * ng, torch.float64)
+    pmid.copy_(s.psi.reshape(-1).cuda())
+    psi = pmid.view(s.psi.shape)
+    keep = psi.clone()
+    npairs = N * (N + 1) // 2 if symmetric else Ni * N
+    vbuf, vmid = guarded(Ni * ng, torch.float64)
+    xbuf, xmid = guarded(1, torch.float64)
+    ebuf, emid = guarded(npairs, torch.float64)
+    obuf, omid = guarded(Ni, torch.float64)
+    if "chunked" in variant:
+        monkeypatch.setenv("TXE_TEST_MAX_WORKSPACE", str(txe.workspace_bytes(ctx, sysm, psi) // 3))
+    a = txe.make_args(psi, comp, symmetric, i0, Ni, vx=vmid.view((Ni,) + tuple(s.psi.shape[1:])), ex=xmid[0],
+                      e_pairs=emid, e_orb=omid, pair_bases="pair bases" in variant,
+                      form="collocation" if "collocation" in variant else "core")
+    assert raw_apply(ctx, sysm, a) == 0, txe.lib().txe_last_error().decode()
+    torch.cuda.synchronize()
+    print(f"[{variant}] E_x {float(xmid[0]):.12f}", flush=True)
+    for name, buf, n in (("psi", pbuf, N * ng), ("vxpsi", vbuf, Ni * ng), ("ex", xbuf, 1), ("e_pairs", ebuf, npairs),
+                         ("e_orb", obuf, Ni)):
+        assert guards_intact(buf, n), f"{variant}: write outside {name}"
+    assert torch.equal(psi, keep)
+    assert bool(torch.isfinite(vmid).all()) and bool(torch.isfinite(emid).all()) and float(xmid[0]) < 0
+    sysm.close()
