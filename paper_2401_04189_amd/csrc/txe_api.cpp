@@ -92,6 +92,7 @@ struct txe_system {
   double *wdev = nullptr;
   // collocation form: A_k^d = C_k^d U_d ([K][n][r] per mode)
   double *acol[3] = {nullptr, nullptr, nullptr};
+  double *acol0s = nullptr;  // the grouped, weighted A_k^0 of the collocation form (see CollocArgs)
 };
 
 #define HIP_TRY(expr)                                                                        \
@@ -490,6 +491,7 @@ extern "C" txe_status txe_system_destroy(txe_system *sys) {
     if (sys->csdev[d]) hipFree(sys->csdev[d]);
     if (sys->acol[d]) hipFree(sys->acol[d]);
   }
+  if (sys->acol0s) hipFree(sys->acol0s);
   if (sys->wdev) hipFree(sys->wdev);
   delete sys;
   return ok();
@@ -660,6 +662,22 @@ extern "C" txe_status txe_system_create(txe_context *ctx, const txe_system_desc 
       return fail(TXE_ERR_DEVICE, "upload of the collocation tables failed");
     }
     S->acol[d] = (double *)p;
+    if (d == 0) {  // grouped and weighted: [group][a][t rp0 + alpha]
+      const int G = COLLOC_GROUP, RP = S->D.rp0, ng = (S->K + G - 1) / G;
+      std::vector<double> A0s((size_t)ng * n * G * RP, 0.0);
+      for (int k = 0; k < S->K; ++k)
+        for (int a = 0; a < n; ++a)
+          for (int al = 0; al < r; ++al)
+            A0s[(((size_t)(k / G) * n + a) * G + k % G) * RP + al] = S->w[k] * A[((size_t)k * n + a) * r + al];
+      void *q = nullptr;
+      if (hipMalloc(&q, A0s.size() * sizeof(double)) != hipSuccess ||
+          hipMemcpy(q, A0s.data(), A0s.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        if (q) hipFree(q);
+        txe_system_destroy(S);
+        return fail(TXE_ERR_DEVICE, "upload of the collocation tables failed");
+      }
+      S->acol0s = (double *)q;
+    }
   }
   {
     void *p = nullptr;
@@ -833,7 +851,7 @@ struct Plan {
   std::vector<Chunk> chunks;
   // per-pair bases: per-pair element counts and offsets of its regions
   bool colloc = false;  // collocation form: Y0, Y1 and phi per pair (FP64)
-  size_t off_Y0 = 0, off_Y1 = 0, off_phi = 0;
+  size_t off_Y0 = 0, off_Ys = 0, off_phi = 0;
   bool pair_bases = false;
   size_t pb_X, pb_X1, pb_X2, pb_X3, pb_S, pb_B, pb_U[3], pb_ah, pb_c1, pb_c2, pb_u0;
   size_t off_X, off_X1, off_X2, off_X3, off_S, off_B, off_V, off_Wr, off_U[3], off_ah, off_c1, off_c2, off_u0;
@@ -856,8 +874,8 @@ static void plan_sizes(const Dims &D, Plan &pl) {
   size_t off = 0;
   if (pl.colloc) {  // FP64 intermediates of the term-by-term reconstruction
     const size_t P8 = P * sizeof(double);
-    pl.off_Y0 = off; off = align256(off + P8 * D.n0 * D.rp1 * D.rp2);
-    pl.off_Y1 = off; off = align256(off + P8 * D.n0 * D.n1 * D.rp2);
+    pl.off_Y0 = off; off = align256(off + P8 * D.rp0 * D.rp1 * D.n2);
+    pl.off_Ys = off; off = align256(off + P8 * COLLOC_GROUP * D.rp0 * D.n1 * D.n2);
     pl.off_phi = off; off = align256(off + P8 * D.n0 * D.n1 * D.n2);
   }
   if (pl.pair_bases) {  // FP64 regions of the per-pair decomposition and tables
@@ -1146,6 +1164,10 @@ static ChunkArgs<T> chunk_args(const txe_system *sys, const txe_apply_args *a, c
 // its chunks in order, then the energy reductions over all pair energies.
 static hipError_t run_plan(const txe_system *sys, const txe_apply_args *args, const Plan &pl, char *ws,
                            hipStream_t s, Prof *prof) {
+  // launch errors are read back with hipGetLastError, which also returns the
+  // failure of any earlier runtime call of this thread (each of those was
+  // reported by its own return code): clear it so it is not taken for a launch's
+  (void)hipGetLastError();
   hipError_t e = hipSuccess;
   const bool psi64 = args->dtype == TXE_DTYPE_F64;
   for (size_t ci = 0; ci < pl.chunks.size() && e == hipSuccess; ++ci) {
@@ -1178,9 +1200,9 @@ static hipError_t run_plan(const txe_system *sys, const txe_apply_args *args, co
       c.pm = ch.pm; c.P = (int)ch.P; c.nbr = ch.nbr; c.br[0] = ch.br[0]; c.br[1] = ch.br[1];
       CollocArgs cl{};
       for (int d = 0; d < 3; ++d) cl.A[d] = sys->acol[d];
-      cl.w_host = sys->w.data();
+      cl.A0s = sys->acol0s;
       cl.Y0 = (double *)(ws + pl.off_Y0);
-      cl.Y1 = (double *)(ws + pl.off_Y1);
+      cl.Ys = (double *)(ws + pl.off_Ys);
       cl.phi = (double *)(ws + pl.off_phi);
       e = run_chunk_colloc(sys->t64.t, cl, c, pl.want_vx, s, prof);
     } else if (pl.f64) {

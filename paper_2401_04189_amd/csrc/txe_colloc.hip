@@ -8,8 +8,13 @@
 // with G_ij the projection of rho_ij onto the shared bases (the same
 // projection kernels as the core-space form).  FP64 throughout.  Per chunk:
 //   projection       G (k_proj12m / k_proj3)
-//   for each term k  Y0 = G x0 A0_k, Y1 = Y0 x1 A1_k, phi (+)= w_k Y1 x2 A2_k
-//                    (A_k^d = C_k^d U_d, n_d x r_d, built on the host in FP64)
+//   per group of COLLOC_GROUP terms:
+//     for each term  Y0 = G x2 A2_k, Ys[t] = Y0 x1 A1_k   (A_k^d = C_k^d U_d,
+//                    n_d x r_d, built on the host in FP64)
+//     phi (+)= Ys x0 A0s   one contraction over (t, alpha), the weights w_k
+//                    folded into the stacked A0s, so that phi is read and
+//                    written once per group rather than once per term
+//   (G is zero past the ranks, so the stack's padding rows are zero)
 //   k_col_epair      e_ij, one workgroup per pair, fixed order
 //   accumulation     Vx psi_t -= sum_s psi_s phi_ts, sources ascending
 #include <algorithm>
@@ -56,18 +61,24 @@ hipError_t run_chunk_colloc(const Tables<double> &tb, const CollocArgs &cl, cons
   const long long ng = (long long)D.n0 * D.n1 * D.n2;
   hipError_t e = launch_projection<double, double>(tb, a, s, prof);
   if (e != hipSuccess) return e;
-  // G: (RP, RP, RP) per pair, rows past the ranks never read (nin = r_d below)
+  // G: (RP, RP, RP) per pair, zero past the ranks
   prof->begin(K_CORE, s);
-  const long long s0 = (long long)RP * RP * RP, s1 = (long long)D.n0 * RP * RP, s2 = (long long)D.n0 * D.n1 * RP;
-  for (int k = 0; k < D.K && e == hipSuccess; ++k) {
-    e = launch_mode_f64(a.G, s0, RP, RP, RP, 0, D.r0, cl.A[0] + (size_t)k * D.n0 * D.r0, 0, D.r0, 1, D.n0, nullptr, 1.0,
-                        0, cl.Y0, s1, P, s);
+  const int GR = COLLOC_GROUP;
+  const long long s0 = (long long)RP * RP * RP, s1 = (long long)RP * RP * D.n2;
+  const long long st = (long long)RP * D.n1 * D.n2, ss = (long long)GR * st;  // one term's block of the stack
+  for (int g = 0; g * GR < D.K && e == hipSuccess; ++g) {
+    const int nt = std::min(GR, D.K - g * GR);
+    for (int t = 0; t < nt && e == hipSuccess; ++t) {
+      const int k = g * GR + t;
+      e = launch_mode_f64(a.G, s0, RP, RP, RP, 2, D.r2, cl.A[2] + (size_t)k * D.n2 * D.r2, 0, D.r2, 1, D.n2, nullptr,
+                          1.0, 0, cl.Y0, s1, P, s);
+      if (e == hipSuccess)
+        e = launch_mode_f64(cl.Y0, s1, RP, RP, D.n2, 1, D.r1, cl.A[1] + (size_t)k * D.n1 * D.r1, 0, D.r1, 1, D.n1,
+                            nullptr, 1.0, 0, cl.Ys + (size_t)t * st, ss, P, s);
+    }
     if (e == hipSuccess)
-      e = launch_mode_f64(cl.Y0, s1, D.n0, RP, RP, 1, D.r1, cl.A[1] + (size_t)k * D.n1 * D.r1, 0, D.r1, 1, D.n1,
-                          nullptr, 1.0, 0, cl.Y1, s2, P, s);
-    if (e == hipSuccess)
-      e = launch_mode_f64(cl.Y1, s2, D.n0, D.n1, RP, 2, D.r2, cl.A[2] + (size_t)k * D.n2 * D.r2, 0, D.r2, 1, D.n2,
-                          nullptr, cl.w_host[k], k > 0 ? 1 : 0, cl.phi, ng, P, s);
+      e = launch_mode_f64(cl.Ys, ss, nt * RP, D.n1, D.n2, 0, nt * RP, cl.A0s + (size_t)g * D.n0 * GR * RP, 0, GR * RP,
+                          1, D.n0, nullptr, 1.0, g > 0 ? 1 : 0, cl.phi, ng, P, s);
   }
   prof->end(s);
   if (e != hipSuccess) return e;

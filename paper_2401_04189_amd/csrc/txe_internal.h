@@ -106,10 +106,16 @@ struct PairBasesArgs {
 };
 
 // Workspace and per-system data of a chunk in the collocation form (FP64).
+// Terms are taken in groups of COLLOC_GROUP: modes 2 and 1 per term into a
+// stack, then one mode-0 product over the whole group (weights folded into
+// the stacked matrix), so phi is read and written once per group.
+constexpr int COLLOC_GROUP = 8;
 struct CollocArgs {
   const double *A[3];         // A_k^d = C_k^d U_d per mode, [K][n_d][r_d] (device)
-  const double *w_host;       // the K term weights (host)
-  double *Y0, *Y1;            // per pair: G x0 A0_k (n0 rp rp) and that x1 A1_k (n0 n1 rp)
+  const double *A0s;          // per group g: [n0][COLLOC_GROUP * rp0], column t rp0 + alpha =
+                              // w_k A0_k[a][alpha] (k = g COLLOC_GROUP + t; zero past r0 and past K)
+  double *Y0;                 // per pair: G x2 A2_k (rp0, rp1, n2)
+  double *Ys;                 // per pair: the group's (G x2 A2_k) x1 A1_k stacked, (COLLOC_GROUP rp0, n1, n2)
   double *phi;                // per pair: phi_ij (n0 n1 n2)
 };
 

@@ -9,92 +9,24 @@ namespace txe {
 
 namespace {
 
-constexpr int NJ = 4;  // 16-column tiles of the unfolding per wavefront (they share the M fragment)
-
-// One wavefront per (pair, 16-row tile of o, NJ 16-column tiles of the other
-// two indices); K = 4 MFMA steps over i.
-__global__ __launch_bounds__(256) void k_mode(const double *__restrict__ X, long long xs, int A, int B, int C, int d,
-                                              int nin, const double *__restrict__ Mm, long long ms, int ldm, int Mt,
-                                              int nout, const double *__restrict__ qout, double yscale, int accum,
-                                              double *__restrict__ Y, long long ys, int P) {
-  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int ext = d == 0 ? A : d == 1 ? B : C;
-  const long long J = (long long)A * B * C / ext;  // columns of the unfolding
-  const int Bo = d == 1 ? nout : B, Co = d == 2 ? nout : C;
-  const int nto = (nout + 15) >> 4;
-  const long long ntj = (J + 16 * NJ - 1) / (16 * NJ);
-  const long long item = (long long)blockIdx.x * 4 + wave;
-  if (item >= (long long)P * nto * ntj) return;  // whole wavefront (item is uniform)
-  const long long tj = item % ntj;
-  const int to = (int)((item / ntj) % nto);
-  const int p = (int)(item / (ntj * nto));
-  const double *Xp = X + (size_t)p * xs;
-  const double *Mp = Mm + (size_t)p * ms;
-  const int o = 16 * to + lr;
-  const bool vo = o < nout;
-  const int oc = vo ? o : nout - 1;
-  long long jc[NJ];
-  bool vj[NJ];
-#pragma unroll
-  for (int u = 0; u < NJ; ++u) {
-    const long long j = 16 * (NJ * tj + u) + lr;
-    vj[u] = j < J;
-    jc[u] = vj[u] ? j : J - 1;
-  }
-  typedef double d4 __attribute__((ext_vector_type(4)));
-  d4 acc[NJ];
-#pragma unroll
-  for (int u = 0; u < NJ; ++u) acc[u] = (d4){0.0, 0.0, 0.0, 0.0};
-  // unrolled so that the loads of several K = 4 steps are in flight together
-#pragma unroll 4
-  for (int i0 = 0; i0 < nin; i0 += 4) {
-    const int i = i0 + lg;
-    const bool vi = i < nin;
-    const int ic = vi ? i : nin - 1;
-    const double mv = Mt ? Mp[(size_t)oc * ldm + ic] : Mp[(size_t)ic * ldm + oc];
-    double xv[NJ];
-#pragma unroll
-    for (int u = 0; u < NJ; ++u) xv[u] = Xp[unfold_at(d, B, C, ic, jc[u])];
-    const double a = (vo && vi) ? mv : 0.0;
-#pragma unroll
-    for (int u = 0; u < NJ; ++u)
-      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (vj[u] && vi) ? xv[u] : 0.0, acc[u], 0, 0, 0);
-  }
-  double *Yp = Y + (size_t)p * ys;
-#pragma unroll
-  for (int u = 0; u < NJ; ++u) {
-    const long long j = 16 * (NJ * tj + u) + lr;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int orow = 16 * to + 4 * v + lg;  // FP64 accumulator row order
-      if (orow < nout && vj[u]) {
-        double val = yscale * (qout ? acc[u][v] / sqrt(qout[orow]) : acc[u][v]);
-        double *y = Yp + unfold_at(d, Bo, Co, orow, j);
-        if (accum) val += *y;
-        *y = val;
-      }
-    }
-  }
-}
-
-// LDS-staged form for nin <= 96 (every mode product of the per-pair and
-// collocation paths): one workgroup per (pair, 64 rows of o, 64 columns of
-// the unfolding); the 64 x nin block of M and the nin x 64 block of X are
-// loaded once with coalesced reads (along the operand's contiguous index)
-// and each wavefront computes a 32 x 32 corner from LDS (2 x 2 MFMA tiles).
+// One workgroup per (pair, 64 rows of o, 64 columns of the unfolding): the
+// contraction runs over chunks of KC values of i; per chunk the 64 x KC block
+// of M and the KC x 64 block of X are loaded into LDS with coalesced reads
+// (along each operand's contiguous index) and each wavefront accumulates a
+// 32 x 32 corner (2 x 2 MFMA tiles) from LDS.  For mode 2, whose output is
+// contiguous along o, X is the A operand so that the lanes of an accumulator
+// row run along o.
 constexpr int LT = 64;      // output tile edge
-constexpr int MPAD = 2;     // row padding of the M block (doubles)
-constexpr int XPAD = 2;     // row padding of the X block
+constexpr int KC = 64;      // contraction chunk
+constexpr int MS = KC + 2;  // padded row of the M block (doubles)
+constexpr int XS = LT + 2;  // padded row of the X block
 __global__ __launch_bounds__(256) void k_mode_lds(const double *__restrict__ X, long long xs, int A, int B, int C,
                                                   int d, int nin, const double *__restrict__ Mm, long long ms, int ldm,
                                                   int Mt, int nout, const double *__restrict__ qout, double yscale,
                                                   int accum, double *__restrict__ Y, long long ys) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int NI = (nin + 3) & ~3;
-  const int MS = NI + MPAD, XS = LT + XPAD;
-  double *Ms = reinterpret_cast<double *>(smem_raw);   // [LT][MS]: M(o, i) at [o][i]
-  double *Xs = Ms + LT * MS;                           // [NI][XS]: X(i, j) at [i][j]
+  double *Ms = reinterpret_cast<double *>(smem_raw);  // [LT][MS]: M(i, o) at [o][i - c0]
+  double *Xs = Ms + LT * MS;                          // [KC][XS]: X(i, j) at [i - c0][j - j0]
   const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int ext = d == 0 ? A : d == 1 ? B : C;
@@ -110,90 +42,85 @@ __global__ __launch_bounds__(256) void k_mode_lds(const double *__restrict__ X, 
   const double *Mp = Mm + (size_t)p * ms;
   const int o0 = LT * to;
   const long long j0 = LT * tj;
-  // M block, read along its contiguous index
-  for (int e = tid; e < LT * NI; e += 256) {
-    int o, i;
-    if (Mt) { o = e / NI; i = e % NI; } else { i = e / LT; o = e % LT; }
-    const int og = o0 + o;
-    Ms[o * MS + i] = (og < nout && i < nin) ? (Mt ? Mp[(size_t)og * ldm + i] : Mp[(size_t)i * ldm + og]) : 0.0;
-  }
-  // X block, read along its contiguous index (j for modes 0 and 1, i for mode 2)
-  for (int e = tid; e < LT * NI; e += 256) {
-    int i, jl;
-    if (d == 2) { jl = e / NI; i = e % NI; } else { i = e / LT; jl = e % LT; }
-    const long long j = j0 + jl;
-    Xs[i * XS + jl] = (j < J && i < nin) ? Xp[unfold_at(d, B, C, i, j)] : 0.0;
-  }
-  __syncthreads();
+  const int ob = 32 * (wave >> 1), jb = 32 * (wave & 1);
   typedef double d4 __attribute__((ext_vector_type(4)));
   d4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (d4){0.0, 0.0, 0.0, 0.0};
-  const int ob = 32 * (wave >> 1), jb = 32 * (wave & 1);
-  double *Yp = Y + (size_t)p * ys;
-  if (d == 2) {
-    // the output's contiguous index is o: X as the A operand, M as the B
-    // operand, so that the lanes of an accumulator row run along o
-#pragma unroll 2
-    for (int i0 = 0; i0 < NI; i0 += 4) {
-      double xv[2], mv[2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) xv[a] = Xs[(i0 + lg) * XS + jb + 16 * a + lr];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) mv[b] = Ms[(ob + 16 * b + lr) * MS + i0 + lg];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[a], mv[b], acc[a][b], 0, 0, 0);
+  for (int c0 = 0; c0 < nin; c0 += KC) {
+    const int nc = min(KC, nin - c0), NI = (nc + 3) & ~3;
+    // M block, read along its contiguous index
+    for (int e = tid; e < LT * NI; e += 256) {
+      int o, i;
+      if (Mt) { o = e / NI; i = e % NI; } else { i = e / LT; o = e % LT; }
+      const int og = o0 + o, ig = c0 + i;
+      Ms[o * MS + i] = (og < nout && i < nc) ? (Mt ? Mp[(size_t)og * ldm + ig] : Mp[(size_t)ig * ldm + og]) : 0.0;
     }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int o = o0 + ob + 16 * b + lr;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const long long j = j0 + jb + 16 * a + 4 * v + lg;  // FP64 accumulator row order
-          if (o < nout && j < J) {
-            double val = yscale * (qout ? acc[a][b][v] / sqrt(qout[o]) : acc[a][b][v]);
-            double *y = Yp + (size_t)j * Co + o;
-            if (accum) val += *y;
-            *y = val;
-          }
-        }
-      }
-    return;
-  }
+    // X block, read along its contiguous index (j for modes 0 and 1, i for mode 2)
+    for (int e = tid; e < LT * NI; e += 256) {
+      int i, jl;
+      if (d == 2) { jl = e / NI; i = e % NI; } else { i = e / LT; jl = e % LT; }
+      const long long j = j0 + jl;
+      Xs[i * XS + jl] = (j < J && i < nc) ? Xp[unfold_at(d, B, C, c0 + i, j)] : 0.0;
+    }
+    __syncthreads();
+    if (d == 2) {
 #pragma unroll 2
-  for (int i0 = 0; i0 < NI; i0 += 4) {
-    double av[2], bv[2];
+      for (int i0 = 0; i0 < NI; i0 += 4) {
+        double xv[2], mv[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) av[a] = Ms[(ob + 16 * a + lr) * MS + i0 + lg];
+        for (int a = 0; a < 2; ++a) xv[a] = Xs[(i0 + lg) * XS + jb + 16 * a + lr];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) bv[b] = Xs[(i0 + lg) * XS + jb + 16 * b + lr];
+        for (int b = 0; b < 2; ++b) mv[b] = Ms[(ob + 16 * b + lr) * MS + i0 + lg];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[a], mv[b], acc[a][b], 0, 0, 0);
+      }
+    } else {
+#pragma unroll 2
+      for (int i0 = 0; i0 < NI; i0 += 4) {
+        double av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) av[a] = Ms[(ob + 16 * a + lr) * MS + i0 + lg];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = Xs[(i0 + lg) * XS + jb + 16 * b + lr];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // the next chunk overwrites the blocks
   }
+  double *Yp = Y + (size_t)p * ys;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const long long j = j0 + jb + 16 * b + lr;
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int orow = o0 + ob + 16 * a + 4 * v + lg;  // FP64 accumulator row order
-        if (orow < nout && j < J) {
-          double val = yscale * (qout ? acc[a][b][v] / sqrt(qout[orow]) : acc[a][b][v]);
-          double *y = Yp + unfold_at(d, Bo, Co, orow, j);
+        // FP64 accumulator row 4v + lg, column lr of tile (a, b)
+        int o;
+        long long j;
+        if (d == 2) {
+          o = o0 + ob + 16 * b + lr;
+          j = j0 + jb + 16 * a + 4 * v + lg;
+        } else {
+          o = o0 + ob + 16 * a + 4 * v + lg;
+          j = j0 + jb + 16 * b + lr;
+        }
+        if (o < nout && j < J) {
+          double val = yscale * (qout ? acc[a][b][v] / sqrt(qout[o]) : acc[a][b][v]);
+          double *y = Yp + unfold_at(d, Bo, Co, o, j);
           if (accum) val += *y;
           *y = val;
         }
       }
-    }
 }
 
 __global__ __launch_bounds__(256) void k_accum(const double *__restrict__ phi, int phi_acb,
@@ -235,22 +162,13 @@ hipError_t launch_mode_f64(const double *X, long long xs, int A, int B, int C, i
                            double *Y, long long ys, int P, hipStream_t s) {
   const int ext = d == 0 ? A : d == 1 ? B : C;
   const long long J = (long long)A * B * C / ext;
-  if (nin <= 96) {
-    const int NI = (nin + 3) & ~3;
-    const size_t lds = ((size_t)LT * (NI + MPAD) + (size_t)NI * (LT + XPAD)) * sizeof(double);
-    if (lds > 64 * 1024) {
-      const hipError_t ea = hipFuncSetAttribute((const void *)k_mode_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                (int)lds);
-      if (ea != hipSuccess) return ea;
-    }
-    const long long blocks = (long long)P * ((nout + LT - 1) / LT) * ((J + LT - 1) / LT);
-    hipLaunchKernelGGL(k_mode_lds, dim3((unsigned)blocks), dim3(256), lds, s, X, xs, A, B, C, d, nin, M, ms, ldm, Mt,
-                       nout, qout, yscale, accum, Y, ys);
-    return hipGetLastError();
-  }
-  const long long waves = (long long)P * ((nout + 15) / 16) * ((J + 16 * NJ - 1) / (16 * NJ));
-  hipLaunchKernelGGL(k_mode, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, X, xs, A, B, C, d, nin, M, ms, ldm, Mt,
-                     nout, qout, yscale, accum, Y, ys, P);
+  const long long blocks = (long long)P * ((nout + LT - 1) / LT) * ((J + LT - 1) / LT);
+  constexpr size_t lds = ((size_t)LT * MS + (size_t)KC * XS) * sizeof(double);  // 67.6 KB
+  const hipError_t ea = hipFuncSetAttribute((const void *)k_mode_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)lds);
+  if (ea != hipSuccess) return ea;
+  hipLaunchKernelGGL(k_mode_lds, dim3((unsigned)blocks), dim3(256), lds, s, X, xs, A, B, C, d, nin, M, ms, ldm, Mt,
+                     nout, qout, yscale, accum, Y, ys);
   return hipGetLastError();
 }
 

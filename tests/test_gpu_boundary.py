@@ -99,6 +99,22 @@ def test_exchange_diagonal_against_oracle(ctx, mode):
     sysm.close()
 
 
+def test_system_teardown_leaves_no_runtime_error(ctx):
+    """Creating and destroying systems (every device table, the collocation
+    tables included) frees each allocation once: a failed runtime call would
+    stay as the thread's last error and be reported by the next launch check,
+    torch's included."""
+    for k in range(2):
+        s = W.small_system(n=16, L=5.0, N=3, r=6, K=10, seed=54 + k)
+        sysm = txe.System.from_workload(ctx, s)
+        vx, ex, _ = txe.apply(ctx, sysm, s.psi.cuda(), compute="f64", form="collocation")
+        torch.cuda.synchronize()
+        sysm.close()
+        y = torch.arange(64, device="cuda", dtype=torch.float64) + 1.0  # raises on a stale error
+        torch.cuda.synchronize()
+        assert float(y.sum()) == 64 * 65 / 2 and bool(torch.isfinite(vx).all())
+
+
 def test_two_streams_on_one_context_are_ordered(ctx):
     s = W.small_system(n=48, L=6.0, N=8, r=24, K=20, seed=53)
     sysm = txe.System.from_workload(ctx, s)
