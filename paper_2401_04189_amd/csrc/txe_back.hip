@@ -211,11 +211,12 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
       for (int cg = 0; cg < NCG; ++cg) bu[kt][cg] = U2t[(unsigned)((4 * kt + lg) * D.nc2 + 16 * ct[cg] + lr)];
     // psi_j values of this wavefront's output points, clamped into the grid
     // (points past the edge are computed and never stored)
-    unsigned poff[NBT][4];  // within one plane (n1 n2 < 2^31)
+    // (b tile mbb adds 16 mbb rows to the first tile's rows; the last row
+    // clamps every offset into the plane)
+    unsigned poff0[4];  // within one plane (n1 n2 < 2^31)
 #pragma unroll
-    for (int mbb = 0; mbb < NBT; ++mbb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) poff[mbb][v] = (unsigned)(min(16 * (mb0 + mbb) + drow<T>(lg, v), D.n1 - 1) * D.n2);
+    for (int v = 0; v < 4; ++v) poff0[v] = (unsigned)((16 * mb0 + drow<T>(lg, v)) * D.n2);
+    const unsigned plast = (unsigned)((D.n1 - 1) * D.n2), prow16 = (unsigned)(16 * D.n2);
     unsigned pc[NCG];
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg) pc[cg] = (unsigned)min(16 * ct[cg] + lr, D.n2 - 1);
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
 #pragma unroll
         for (int cg = 0; cg < NCG; ++cg)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) pv[cg][v] = ps[poff[mbb][v] + pc[cg]];
+          for (int v = 0; v < 4; ++v) pv[cg][v] = ps[min(poff0[v] + (unsigned)mbb * prow16, plast) + pc[cg]];
         acc ph[NCG];
 #pragma unroll
         for (int cg = 0; cg < NCG; ++cg) ph[cg] = zero4<acc>();
@@ -381,7 +382,9 @@ hipError_t launch_back_b_mt(const Tables<T> &tb, const ChunkArgs<T> &a, const Ba
   const size_t lds = lds_tab ? tab : 0;
   // all b tiles in one launch up to six tiles (X computed once per source);
   // FP64 up to eight.  FP32 beyond six: launches over disjoint ranges of
-  // four b tiles, each recomputing X for its sources (registers)
+  // four b tiles, each recomputing X for its sources: one launch of eight
+  // tiles holds one wavefront per SIMD and measured twice as slow at 128^3
+  // (the kernel hides its load latency with a second wavefront)
   if (nbt > 8) return hipErrorInvalidValue;
 #define TXE_BACK(NBTV, MB0)                                                                                      \
   do {                                                                                                           \

@@ -112,28 +112,37 @@ __global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dim
 }
 
 // proj12, compile-time form: all MT gamma tiles per wavefront (MT = rank
-// tiles of every mode), so no per-MFMA guard; the psi loads use clamped
-// addresses and a select instead of a branch.
-template <typename T, typename Tin, int MT, bool LDS_TAB>
+// tiles of every mode), so no per-MFMA guard.  The psi loads run PD c steps
+// ahead of their MFMAs in a ring of registers, across the b tiles (slot u
+// serves the steps s = u mod PD of the flattened (b tile, c step) order, so
+// PD divides the c steps per b tile); addresses are clamped and points past
+// the grid are zeroed by a select.  TABS: the shared operands in LDS,
+// 2 = V2 and the chained V1 fragments, 1 = V2 only, 0 = neither.
+template <typename T, typename Tin, int MT, int TABS, int PD>
 __global__ __launch_bounds__(256) void k_proj12m(const Tin *__restrict__ psi, Dims D, PairMap pm, int P,
                                                  Tables<T> tb, T *__restrict__ T2) {
   using M = MF<T>;
   using acc = typename M::acc;
+  typedef typename std::conditional<sizeof(Tin) == 4, f4, d4>::type V4;
   constexpr int RP = 16 * MT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
   const int nbt = D.nb1 >> 4, nct = D.nc2 >> 4;
+  const int S = nbt * nct;
   const T *V2 = tb.V2B, *V1c = tb.V1chain;
-  if constexpr (LDS_TAB) {
+  if constexpr (TABS > 0) {
     T *s2 = reinterpret_cast<T *>(smem_raw);
-    T *s1 = s2 + (size_t)D.nc2 * RP;
-    const int m2 = D.nc2 * RP, m1 = MT * nbt * 256;
+    const int m2 = D.nc2 * RP;
     for (int idx = threadIdx.x; idx < m2; idx += 256) s2[idx] = tb.V2B[idx];
-    for (int idx = threadIdx.x; idx < m1; idx += 256) s1[idx] = tb.V1chain[idx];
-    __syncthreads();
     V2 = s2;
-    V1c = s1;
+    if constexpr (TABS > 1) {
+      T *s1 = s2 + m2;
+      const int m1 = MT * nbt * 256;
+      for (int idx = threadIdx.x; idx < m1; idx += 256) s1[idx] = tb.V1chain[idx];
+      V1c = s1;
+    }
+    __syncthreads();
   }
   const size_t plane = (size_t)D.n1 * D.n2;
   const long long total = (long long)P * D.n0;
@@ -144,6 +153,15 @@ __global__ __launch_bounds__(256) void k_proj12m(const Tin *__restrict__ psi, Di
     pair_ij(pm, p, i, j);
     const Tin *pi = psi + ((size_t)i * D.n0 + a) * plane;
     const Tin *pj = psi + ((size_t)j * D.n0 + a) * plane;
+    V4 xq[PD], yq[PD];
+    auto issue = [&](int s_, V4 &x, V4 &y) {
+      const int mb_ = s_ / nct, J_ = s_ - mb_ * nct;
+      const size_t off = (size_t)min(16 * mb_ + lr, D.n1 - 1) * D.n2 + min(16 * J_ + 4 * lg, D.n2 - 4);
+      x = *reinterpret_cast<const V4 *>(pi + off);
+      y = *reinterpret_cast<const V4 *>(pj + off);
+    };
+#pragma unroll
+    for (int u = 0; u < PD; ++u) issue(min(u, S - 1), xq[u], yq[u]);
     acc T2a[MT][MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -153,23 +171,24 @@ __global__ __launch_bounds__(256) void k_proj12m(const Tin *__restrict__ psi, Di
       acc T1[MT];
 #pragma unroll
       for (int gt = 0; gt < MT; ++gt) T1[gt] = zero4<acc>();
-      const int b = 16 * mb + lr;
-      const size_t rowoff = (size_t)min(b, D.n1 - 1) * D.n2;
-      for (int J = 0; J < nct; ++J) {
-        const int c = 16 * J + 4 * lg;
-        const bool in = b < D.n1 && c < D.n2;
-        const size_t off = rowoff + min(c, D.n2 - 4);
-        double x[4], y[4];
-        load4(pi + off, x);
-        load4(pj + off, y);
+      const bool bin = 16 * mb + lr < D.n1;
+      for (int J0 = 0; J0 < nct; J0 += PD) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) x[q] = in ? x[q] * y[q] : 0.0;
+        for (int u = 0; u < PD; ++u) {
+          const int J = J0 + u, s = mb * nct + J;
+          const int c = 16 * J + 4 * lg;
+          const bool in = bin && c < D.n2;
+          double x[4];
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const T *vrow = V2 + (size_t)(c + jj) * RP + lr;
-          const T rho = (T)x[jj];
+          for (int q = 0; q < 4; ++q) x[q] = in ? (double)xq[u][q] * (double)yq[u][q] : 0.0;
+          if (s + PD < S) issue(s + PD, xq[u], yq[u]);
 #pragma unroll
-          for (int gt = 0; gt < MT; ++gt) T1[gt] = M::mma(rho, vrow[16 * gt], T1[gt]);
+          for (int jj = 0; jj < 4; ++jj) {
+            const T *vrow = V2 + (size_t)(c + jj) * RP + lr;
+            const T rho = (T)x[jj];
+#pragma unroll
+            for (int gt = 0; gt < MT; ++gt) T1[gt] = M::mma(rho, vrow[16 * gt], T1[gt]);
+          }
         }
       }
 #pragma unroll
@@ -255,13 +274,35 @@ namespace {
 template <typename T, typename Tin, int MT>
 void launch_proj12m_mt(const Tables<T> &tb, const ChunkArgs<T> &a, hipStream_t s) {
   const unsigned nb = blocks_for((long long)a.P * a.D.n0);
-  const size_t tab = ((size_t)a.D.nc2 * 16 * MT + (size_t)MT * (a.D.nb1 >> 4) * 256) * sizeof(T);
-  if (tab <= 64 * 1024)
-    hipLaunchKernelGGL((k_proj12m<T, Tin, MT, true>), dim3(std::min(nb, (unsigned)a.grid_cap)), dim3(256), tab, s,
-                       (const Tin *)a.psi, a.D, a.pm, a.P, tb, a.T2);
-  else
-    hipLaunchKernelGGL((k_proj12m<T, Tin, MT, false>), dim3(nb), dim3(256), 0, s, (const Tin *)a.psi, a.D, a.pm,
-                       a.P, tb, a.T2);
+  // the tables in LDS up to 80 KiB (two workgroups per CU), else V2 alone,
+  // else neither; the grid is then capped and each workgroup walks several items
+  const size_t t2 = (size_t)a.D.nc2 * 16 * MT * sizeof(T);
+  const size_t t1 = (size_t)MT * (a.D.nb1 >> 4) * 256 * sizeof(T);
+  constexpr size_t LIM = 80 * 1024;
+  const unsigned nbl = std::min(nb, (unsigned)a.grid_cap);
+  // psi loads two c steps ahead where the c steps per b tile are even
+  const bool pd2 = ((a.D.nc2 >> 4) & 1) == 0;
+  auto go = [&](auto tabs, size_t lds) {
+    constexpr int TB = decltype(tabs)::value;
+    if (!pd2) {
+      if (lds > 64 * 1024 && hipFuncSetAttribute((const void *)k_proj12m<T, Tin, MT, TB, 1>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return;
+      hipLaunchKernelGGL((k_proj12m<T, Tin, MT, TB, 1>), dim3(TB ? nbl : nb), dim3(256), lds, s, (const Tin *)a.psi,
+                         a.D, a.pm, a.P, tb, a.T2);
+      return;
+    }
+    // above 64 KiB the kernel opts in; a refusal stays the thread's last
+    // error, which the caller's launch check reports
+    if (lds > 64 * 1024 && hipFuncSetAttribute((const void *)k_proj12m<T, Tin, MT, TB, 2>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return;
+    hipLaunchKernelGGL((k_proj12m<T, Tin, MT, TB, 2>), dim3(TB ? nbl : nb), dim3(256), lds, s, (const Tin *)a.psi, a.D,
+                       a.pm, a.P, tb, a.T2);
+  };
+  if (t2 + t1 <= LIM) go(std::integral_constant<int, 2>{}, t2 + t1);
+  else if (t2 <= LIM) go(std::integral_constant<int, 1>{}, t2);
+  else go(std::integral_constant<int, 0>{}, 0);
 }
 
 template <typename T, typename Tin>
