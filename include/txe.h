@@ -328,7 +328,9 @@ txe_status txe_graph_destroy(txe_graph *graph);
  * knobs[2] c tiles per wavefront of the back-projection kernel (1, 2;
  * 0 = chosen by size); knobs[3] workgroups of the persistent projection and
  * back-projection kernels; knobs[4] form of the back-projection kernel (1
- * streaming, 2 batched loads; 0 = default, batched).  Results do not depend on
+ * streaming, 2 batched loads, 3 each source's slab staged in LDS per
+ * workgroup, FP32 compute only; 0 = default: 3 where its LDS leaves room for
+ * two workgroups per CU, else 2).  Results do not depend on
  * knobs[1..4]; knobs[0] changes the summation order of the pair energies
  * only.
  *

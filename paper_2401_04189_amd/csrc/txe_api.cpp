@@ -43,7 +43,7 @@ struct Knobs {
   int proj_gt = 4;     // gamma tiles per wavefront in proj12 (1, 2, 3; 4 = all, compile-time form)
   int back_ncg = 0;    // c tiles per wavefront in back (1, 2; 0 = by size)
   int grid_cap = 2048; // workgroups of the persistent proj12 / back kernels
-  int back_form = 0;   // back kernel form (1 streaming, 2 batched; 0 = default, batched)
+  int back_form = 0;   // back kernel form (1 streaming, 2 batched, 3 LDS-staged; 0 = default by size)
 };
 
 struct txe_context {
@@ -1062,7 +1062,7 @@ static Knobs knobs_for(const txe_context *ctx, const txe_system *sys, const txe_
 static bool knobs_valid(const Knobs &k) {
   return (k.ngs_mul == 1 || k.ngs_mul == 2 || k.ngs_mul == 4) && k.proj_gt >= 1 && k.proj_gt <= 4 &&
          k.back_ncg >= 0 && k.back_ncg <= 2 && k.grid_cap >= 256 && k.grid_cap <= 16384 && k.back_form >= 0 &&
-         k.back_form <= 2;
+         k.back_form <= 3;
 }
 
 static txe_status validate_args(const txe_context *ctx, const txe_system *sys, const txe_apply_args *a) {
@@ -1524,7 +1524,7 @@ extern "C" txe_status txe_tune(txe_context *ctx, const txe_system *sys, const tx
   Knobs best{};
   double best_t = 0.0;
   txe_status st = time_apply(ctx, sys, args, best, reps, &best_t);
-  const std::vector<int> ngs = {1, 2, 4}, gt = {1, 2, 3, 4}, ncg = {1, 2}, cap = {1024, 2048, 4096}, form = {1, 2};
+  const std::vector<int> ngs = {1, 2, 4}, gt = {1, 2, 3, 4}, ncg = {1, 2}, cap = {1024, 2048, 4096}, form = {1, 2, 3};
   for (int sweep = 0; sweep < 2 && st == TXE_OK; ++sweep) {
     const Knobs start = best;
     for (int knob = 0; knob < 5 && st == TXE_OK; ++knob) {

@@ -17,6 +17,13 @@ namespace txe {
 //             fragments hoisted out of the source loop, each source's S1
 //             rows loaded in batches ahead of their MFMAs (clamped addresses
 //             and selects instead of branches); fewer, busier wavefronts
+//   k_back_l  LDS-staged (FP32): the four wavefronts of a workgroup share the
+//             target and slab a and take four c-tile groups; each source's
+//             S1 slab is loaded once per workgroup in 16-byte pieces one
+//             source ahead and read from LDS, the chained U1 fragments are
+//             staged in LDS once per workgroup, and every b tile is done in
+//             one pass, so X is computed once per source.  Same products in
+//             the same order as k_back_b.
 // -------------------------------------------------------------------------------------
 template <typename T, typename Tin, int NBT, int NCG, bool LDS_TAB>
 __global__ __launch_bounds__(256) void k_back_s(const T *__restrict__ S1, const Tin *__restrict__ psi, Dims D,
@@ -337,6 +344,252 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
   }
 }
 
+// row stride of the staged S1 slab: four rows 4 apart start in four
+// different quarters of the 64 LDS banks, so a fragment read (16 lanes per
+// row) is conflict-free
+__host__ __device__ constexpr int back_srs(int rp) { return rp % 32 == 16 ? rp : rp + 16; }
+
+template <typename T, typename Tin, typename Tps, int MT, int NBT, int NCG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_back_l(const T *__restrict__ S1, const Tps *__restrict__ psi, Dims D,
+                                                PairMap pm, BackRange br, Tables<T> tb,
+                                                Tin *__restrict__ vx, const double *__restrict__ out_scale,
+                                                int weighted, const double *__restrict__ q0,
+                                                const double *__restrict__ q1, const double *__restrict__ q2) {
+  using M = MF<T>;
+  using acc = typename M::acc;
+  typedef T V16 __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int RP = 16 * MT;
+  constexpr int SRS = back_srs(RP);
+  constexpr int PE = 16 / (int)sizeof(T);  // values per 16-byte piece
+  constexpr int NPC = RP * RP / PE;        // pieces per slab
+  constexpr int EPT = (NPC + 255) / 256;   // pieces per thread
+  constexpr int KTB = 2;                   // S1 rows (gamma') per batch of LDS reads
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
+  const int tid = threadIdx.x;
+  const int nct = D.nc2 >> 4, nbt = D.nb1 >> 4;
+  const int ncq = (nct + 4 * NCG - 1) / (4 * NCG);
+  const int nkt = (D.r2 + 3) >> 2;  // gamma' rows in use, in fours
+  T *Ss = reinterpret_cast<T *>(smem_raw);  // [RP][SRS]: the source's S1 slab, S1[gamma'][beta']
+  T *U1c = Ss + RP * SRS;                   // chained U1 fragments [nbt][MT][4][64]
+  for (int idx = tid; idx < nbt * MT * 256; idx += 256) U1c[idx] = tb.U1chain[idx];
+  // (visible after the first source's barriers)
+  const size_t plane = (size_t)D.n1 * D.n2;
+  const size_t S1pair = (size_t)D.n0 * RP * RP;
+  const long long total = (long long)br.nt * D.n0 * ncq;
+  const unsigned soff = (unsigned)(lg * SRS + lr);  // S1 fragment element of this lane
+  for (long long item = blockIdx.x; item < total; item += gridDim.x) {  // uniform per workgroup
+    const int cq = (int)(item % ncq);
+    const long long rest = item / ncq;
+    const int a = (int)(rest % D.n0);
+    const int tglob = br.t0 + (int)(rest / D.n0);
+    Tin *out = vx + (size_t)(tglob - br.out0) * D.n0 * plane + (size_t)a * plane;
+    const int c0 = (4 * cq + wave) * NCG;  // first c tile of this wavefront
+    // c tiles past the last one repeat it and are never stored
+    int ct[NCG];
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) ct[cg] = min(c0 + cg, nct - 1);
+    T bu[4 * MT][NCG];
+#pragma unroll
+    for (int kt = 0; kt < 4 * MT; ++kt)
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) bu[kt][cg] = tb.U2T[(unsigned)((4 * kt + lg) * D.nc2 + 16 * ct[cg] + lr)];
+    unsigned poff0[4];  // within one plane (n1 n2 < 2^31); b tile mbb adds 16 mbb rows, clamped to the last row
+#pragma unroll
+    for (int v = 0; v < 4; ++v) poff0[v] = (unsigned)(drow<T>(lg, v) * D.n2);
+    const unsigned plast = (unsigned)((D.n1 - 1) * D.n2), prow16 = (unsigned)(16 * D.n2);
+    unsigned pc[NCG];
+#pragma unroll
+    for (int cg = 0; cg < NCG; ++cg) pc[cg] = (unsigned)min(16 * ct[cg] + lr, D.n2 - 1);
+
+    acc Acc[NBT][NCG];
+#pragma unroll
+    for (int mb = 0; mb < NBT; ++mb)
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) Acc[mb][cg] = zero4<acc>();
+    if (br.acc_in) {
+#pragma unroll
+      for (int mbb = 0; mbb < NBT; ++mbb) {
+        if (mbb >= nbt) break;  // uniform
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg) {
+          const int c = 16 * (c0 + cg) + lr;
+          if (c0 + cg < nct && c < D.n2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int b = 16 * mbb + drow<T>(lg, v);
+              if (b < D.n1) Acc[mbb][cg][v] = (T)out[(size_t)b * D.n2 + c];
+            }
+          }
+        }
+      }
+    }
+    // the next source's slab, in flight during this source's MFMAs
+    V16 pre[EPT];
+    auto fetch = [&](int s_) {
+      const V16 *src = reinterpret_cast<const V16 *>(S1 + (size_t)local_pair(pm, br, tglob, s_) * S1pair +
+                                                     (size_t)a * RP * RP);
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) pre[j] = src[min(j * 256 + tid, NPC - 1)];
+    };
+    fetch(br.s0);
+    for (int s = br.s0; s < br.s0 + br.ns; ++s) {
+      __syncthreads();  // every wavefront is done with the previous slab
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int e = j * 256 + tid;
+        if (e < NPC) *reinterpret_cast<V16 *>(Ss + (PE * e / RP) * SRS + PE * e % RP) = pre[j];
+      }
+      __syncthreads();
+      if (s + 1 < br.s0 + br.ns) fetch(s + 1);
+      const auto *ps = wave_uniform(psi + (size_t)s * D.n0 * plane + (size_t)a * plane);
+      // the psi row bases, made opaque per source so the per-tile offsets are
+      // formed next to their loads instead of held across the source loop
+      unsigned pb[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        pb[v] = poff0[v];
+        asm volatile("" : "+v"(pb[v]));
+      }
+      // X[beta'][c] = sum_gamma' S1[gamma'][beta'] U2[c][gamma']
+      acc X[MT][NCG];
+#pragma unroll
+      for (int mb = 0; mb < MT; ++mb)
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg) X[mb][cg] = zero4<acc>();
+#pragma unroll
+      for (int kb = 0; kb < 4 * MT; kb += KTB) {
+        if (kb >= nkt) break;  // uniform: padded gamma' rows only
+        T sf[KTB][MT];
+#pragma unroll
+        for (int k = 0; k < KTB; ++k) {
+          const int gam = 4 * (kb + k) + lg;
+#pragma unroll
+          for (int mb = 0; mb < MT; ++mb) {
+            const T x = Ss[soff + (unsigned)(4 * (kb + k) * SRS + 16 * mb)];
+            sf[k][mb] = gam < D.r2 ? x : (T)0;  // rows past r2 are not written by the core kernel
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < KTB; ++k)
+#pragma unroll
+          for (int mb = 0; mb < MT; ++mb)
+#pragma unroll
+            for (int cg = 0; cg < NCG; ++cg) X[mb][cg] = M::mma(sf[k][mb], bu[kb + k][cg], X[mb][cg]);
+      }
+      // phi[b][c] = sum_beta' U1[b][beta'] X[beta'][c] (chained), then Acc += psi_j phi
+#pragma unroll
+      for (int mbb = 0; mbb < NBT; ++mbb) {
+        if (mbb >= nbt) break;  // uniform
+        __builtin_amdgcn_sched_barrier(0);
+        Tps pv[NCG][4];
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) pv[cg][v] = ps[min(pb[v] + (unsigned)mbb * prow16, plast) + pc[cg]];
+        acc ph[NCG];
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg) ph[cg] = zero4<acc>();
+#pragma unroll
+        for (int mbe = 0; mbe < MT; ++mbe)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T af = U1c[lane + ((mbb * MT + mbe) * 4 + v) * 64];
+#pragma unroll
+            for (int cg = 0; cg < NCG; ++cg) ph[cg] = M::mma(af, X[mbe][cg][v], ph[cg]);
+          }
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Acc[mbb][cg][v] += (T)pv[cg][v] * ph[cg][v];
+      }
+    }
+    const double scale = out_scale ? *out_scale : 1.0;
+    // lane indices rebuilt from an opaque copy: the output addresses are then
+    // formed here, not shared with the initial read and held across the loop
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const int lre = ln & 15, lge = ln >> 4;
+#pragma unroll
+    for (int mbb = 0; mbb < NBT; ++mbb) {
+      if (mbb >= nbt) break;
+#pragma unroll
+      for (int cg = 0; cg < NCG; ++cg) {
+        const int c = 16 * (c0 + cg) + lre;
+        if (c0 + cg < nct && c < D.n2) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int b = 16 * mbb + drow<T>(lge, v);
+            if (b < D.n1) {
+              if (br.finish) {
+                double val = -scale * (double)Acc[mbb][cg][v];
+                if (weighted) val *= q0[a] * q1[b] * q2[c];
+                out[(size_t)b * D.n2 + c] = (Tin)val;
+              } else {
+                out[(size_t)b * D.n2 + c] = (Tin)Acc[mbb][cg][v];  // raw sum, exact in Tin
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// LDS bytes of k_back_l: the staged slab and the chained U1 fragments
+inline size_t back_l_lds(int mt, int nbt, size_t elt) {
+  return ((size_t)16 * mt * back_srs(16 * mt) + (size_t)nbt * mt * 256) * elt;
+}
+
+template <typename T, typename Tin, typename Tps, int MT, int NCG>
+hipError_t launch_back_l_mt(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
+  const int nct = a.D.nc2 >> 4, nbt = a.D.nb1 >> 4;
+  const long long items = (long long)br.nt * a.D.n0 * ((nct + 4 * NCG - 1) / (4 * NCG));
+  const unsigned nb = (unsigned)std::min<long long>(items, a.grid_cap);
+  const Tps *psi = std::is_same<Tps, Tin>::value ? (const Tps *)a.psi : (const Tps *)a.psi32;
+  Tin *vx = (Tin *)a.vx;
+  const size_t lds = back_l_lds(MT, nbt, sizeof(T));
+  if constexpr (NCG == 2)  // two c tiles per wavefront only up to four b tiles (registers)
+    if (nbt > 4) return launch_back_l_mt<T, Tin, Tps, MT, 1>(tb, a, br, s);
+  auto go = [&](auto nbt_c) -> hipError_t {
+    constexpr int NB = decltype(nbt_c)::value;
+    if constexpr (NCG == 2 && NB > 4) return hipErrorInvalidValue;  // not reached
+    const void *fn = (const void *)k_back_l<T, Tin, Tps, MT, NB, NCG>;
+    if (lds > 64 * 1024) {
+      const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_back_l<T, Tin, Tps, MT, NB, NCG>), dim3(nb), dim3(256), lds, s, a.S1, psi, a.D, a.pm, br,
+                       tb, vx, a.out_scale, a.weighted, a.qdev[0], a.qdev[1], a.qdev[2]);
+    return hipGetLastError();
+  };
+  if (nbt <= 2) return go(std::integral_constant<int, 2>{});
+  if (nbt <= 4) return go(std::integral_constant<int, 4>{});
+  if (nbt <= 6) return go(std::integral_constant<int, 6>{});
+  if (nbt <= 8) return go(std::integral_constant<int, 8>{});
+  return hipErrorInvalidValue;
+}
+
+template <typename T, typename Tin, typename Tps, int NCG>
+hipError_t launch_back_l_tps(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
+  switch (a.D.MT1) {
+    case 1: return launch_back_l_mt<T, Tin, Tps, 1, NCG>(tb, a, br, s);
+    case 2: return launch_back_l_mt<T, Tin, Tps, 2, NCG>(tb, a, br, s);
+    case 3: return launch_back_l_mt<T, Tin, Tps, 3, NCG>(tb, a, br, s);
+    case 4: return launch_back_l_mt<T, Tin, Tps, 4, NCG>(tb, a, br, s);
+    case 5: return launch_back_l_mt<T, Tin, Tps, 5, NCG>(tb, a, br, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, typename Tin, int NCG>
+hipError_t launch_back_l_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
+  if constexpr (sizeof(Tin) == 8)
+    if (a.psi32) return launch_back_l_tps<T, Tin, float, NCG>(tb, a, br, s);
+  return launch_back_l_tps<T, Tin, Tin, NCG>(tb, a, br, s);
+}
+
 template <typename T, typename Tin, int NCG>
 hipError_t launch_back_s_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
   const int nct = a.D.nc2 >> 4, nbt = a.D.nb1 >> 4;
@@ -431,14 +684,25 @@ hipError_t launch_back_b_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, const B
 
 template <typename T, typename Tin>
 hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
-  // form: streaming (k_back_s, runtime rank loops, high occupancy) or
-  // batched (k_back_b, compile-time rank tiles, loads issued per source in
-  // batches).  Default: batched, which measured fastest on the 64^3 and
-  // 80^3 workloads in both precisions
-  const bool batched = a.back_form ? a.back_form == 2 : true;
+  // form: streaming (k_back_s, runtime rank loops, high occupancy), batched
+  // (k_back_b, compile-time rank tiles, loads issued per source in batches)
+  // or LDS-staged (k_back_l, FP32, while its LDS leaves room for two
+  // workgroups per CU).  Default: LDS-staged where it applies, else batched
+  const int nbt = a.D.nb1 >> 4;
+  // (FP64 orbitals read as they are, without an FP32 copy, only up to six b tiles: registers)
+  const bool psi64_direct = sizeof(Tin) == 8 && !a.psi32;
+  const bool lds_ok = sizeof(T) == 4 && nbt <= (psi64_direct ? 6 : 8) &&
+                      back_l_lds(a.D.MT1, nbt, sizeof(T)) <= 80 * 1024;
+  const int form = a.back_form == 3 && !lds_ok ? 2 : a.back_form ? a.back_form : (lds_ok ? 3 : 2);
+  if (form == 3) {
+    if constexpr (sizeof(T) == 4) {
+      const int ncg = a.back_ncg ? a.back_ncg : 1;
+      return ncg == 2 ? launch_back_l_ncg<T, Tin, 2>(tb, a, br, s) : launch_back_l_ncg<T, Tin, 1>(tb, a, br, s);
+    }
+  }
   // two c-tiles per wavefront while the b-tile accumulators are few
-  const int ncg = a.back_ncg ? a.back_ncg : ((a.D.nb1 >> 4) <= 4 ? 2 : 1);
-  if (batched) return ncg == 2 ? launch_back_b_ncg<T, Tin, 2>(tb, a, br, s) : launch_back_b_ncg<T, Tin, 1>(tb, a, br, s);
+  const int ncg = a.back_ncg ? a.back_ncg : (nbt <= 4 ? 2 : 1);
+  if (form != 1) return ncg == 2 ? launch_back_b_ncg<T, Tin, 2>(tb, a, br, s) : launch_back_b_ncg<T, Tin, 1>(tb, a, br, s);
   return ncg == 2 ? launch_back_s_ncg<T, Tin, 2>(tb, a, br, s) : launch_back_s_ncg<T, Tin, 1>(tb, a, br, s);
 }
 

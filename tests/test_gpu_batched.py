@@ -128,7 +128,7 @@ def test_tuner_cache_roundtrip_and_shapes(env, tmp_path):
     assert ms > 0
     assert knobs["ngs_mul"] in (1, 2, 4) and knobs["proj_gt"] in (1, 2, 3, 4)
     assert knobs["back_ncg"] in (0, 1, 2) and knobs["grid_cap"] in (1024, 2048, 4096)
-    assert knobs["back_form"] in (0, 1, 2)
+    assert knobs["back_form"] in (0, 1, 2, 3)
     assert txe.plan(ctx, sysm, psi, "f64") == (knobs, True)
     v1, e1, _ = txe.apply(ctx, sysm, psi, compute="f64")
     assert abs(float(e1) - float(e0)) <= 1e-13 * abs(float(e0))
