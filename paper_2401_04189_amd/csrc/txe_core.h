@@ -397,6 +397,31 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
         acc W[MT];
 #pragma unroll
         for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
+        if constexpr (F32) {
+          // the slab fragments of K step kt + 2 are read while the MFMAs of kt
+          // run (a ring of three), so the LDS latency stays off the MFMA pipe
+          constexpr int NQ = (MT + PE - 1) / PE;
+          const V16 *src0 = reinterpret_cast<const V16 *>(Gs + (step & 1) * SLAB + lg * SROW + lr * LPL);
+          V16 ring[3][NQ];
+          auto rd = [&](int kt_, V16 (&o)[NQ]) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) o[q] = src0[(4 * kt_ * SROW) / PE + q];
+          };
+          rd(0, ring[0]);
+          if (NKT > 1) rd(1, ring[1]);
+          __builtin_amdgcn_sched_group_barrier(0x100, NKT > 1 ? 2 * NQ : NQ, 0);  // the first two reads
+#pragma unroll
+          for (int kt = 0; kt < 4 * MT; ++kt) {
+            if (kt >= NKT) break;
+            if (kt + 2 < NKT) rd(kt + 2, ring[(kt + 2) % 3]);
+            const T *x = reinterpret_cast<const T *>(&ring[kt % 3][0]);
+#pragma unroll
+            for (int mg = 0; mg < MT; ++mg) W[mg] = M::mma(x[mg], tcb[kt], W[mg]);
+            // issue order: the reads of kt + 2, then the MFMAs of kt
+            if (kt + 2 < NKT) __builtin_amdgcn_sched_group_barrier(0x100, NQ, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, MT, 0);
+          }
+        } else {
 #pragma unroll
         for (int kt = 0; kt < 4 * MT; ++kt) {
           if (kt >= NKT) break;
@@ -411,6 +436,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
           }
 #pragma unroll
           for (int mg = 0; mg < MT; ++mg) W[mg] = M::mma(gl[mg], tcb[kt], W[mg]);
+        }
         }
         if constexpr (SPLIT) {  // first half stored, second half issued
           if (more) kslab_store_part((step + 1) & 1, 0, gnext);
