@@ -850,6 +850,7 @@ struct Plan {
   size_t off_T2, off_G, off_S1, off_epart, off_epair, off_psi32, total;
   std::vector<Chunk> chunks;
   // per-pair bases: per-pair element counts and offsets of its regions
+  size_t gbf_per = 0, off_Gbf = 0;  // split-bf16 slab images per pair (values), their region
   bool colloc = false;  // collocation form: Y0, Y1 and phi per pair (FP64)
   size_t off_Y0 = 0, off_Ys = 0, off_phi = 0;
   bool pair_bases = false;
@@ -903,6 +904,7 @@ static void plan_sizes(const Dims &D, Plan &pl) {
   }
   pl.off_T2 = off; off = align256(off + P * perT2 * pl.elt);
   pl.off_G = off; off = align256(off + P * perG * pl.elt);
+  pl.off_Gbf = off; off = align256(off + P * pl.gbf_per * sizeof(unsigned short));
   pl.off_S1 = off; off = align256(off + P * perS1 * pl.elt);
   pl.off_epart = off; off = align256(off + P * D.MT1 * pl.NGS * sizeof(double));
   pl.off_epair = off; off = align256(off + (size_t)pl.npairs * sizeof(double));
@@ -918,7 +920,7 @@ static long long max_pairs(const Dims &D, Plan &pl, size_t limit) {
   const size_t fixed = pl.total;
   pl.Pmax = 1;
   plan_sizes(D, pl);
-  const size_t per = pl.total - fixed + 256 * 24;  // + alignment slack of the per-pair regions (21 of them)
+  const size_t per = pl.total - fixed + 256 * 24;  // + alignment slack of the per-pair regions (22 of them)
   if (pl.total > limit) return 0;
   return (long long)((limit - fixed) / per);
 }
@@ -1031,6 +1033,7 @@ static txe_status make_plan(const txe_system *sys, const txe_apply_args *a, cons
   pl.npairs = pl.symmetric ? (long long)a->N * (a->N + 1) / 2 : (long long)a->Ni * a->N;
   const int mt = std::max(D.MT0, std::max(D.MT1, D.MT2));
   const int nsplit = a->compute == TXE_COMPUTE_BF16X3 ? 2 : a->compute == TXE_COMPUTE_BF16X6 ? 3 : 0;
+  pl.gbf_per = (size_t)D.rp0 * bf_frag_elems(mt, nsplit);
   const int rows = core_rows(pl.f64, nsplit, mt);
   // fewest gamma' splits whose rows fit the accumulator registers, times the
   // tuned multiplier; then trimmed so that no split is empty
@@ -1154,6 +1157,7 @@ static ChunkArgs<T> chunk_args(const txe_system *sys, const txe_apply_args *a, c
   for (int d = 0; d < 3; ++d) c.qdev[d] = sys->qdev[d];
   c.T2 = (T *)(ws + pl.off_T2);
   c.G = (T *)(ws + pl.off_G);
+  c.Gbf = pl.gbf_per ? (unsigned short *)(ws + pl.off_Gbf) : nullptr;
   c.S1 = (T *)(ws + pl.off_S1);
   c.epart = (double *)(ws + pl.off_epart);
   c.epair = (double *)(ws + pl.off_epair);

@@ -46,6 +46,44 @@ __device__ __forceinline__ bf8 ld_bf8(const unsigned short *p) {
 
 
 // -------------------------------------------------------------------------------------
+// G split into its bf16 parts once per pair, each slab alpha written as the
+// term-major core's LDS image: value i of lane ln of (part sp, gamma tile mg,
+// beta chunk c) is part sp of G[alpha][32 c + 8 (ln >> 4) + i][16 mg + (ln & 15)]
+// (zero for beta past the padded rank).  One thread per (pair, alpha, mg, c, ln).
+// -------------------------------------------------------------------------------------
+template <int MT, int NS>
+__global__ __launch_bounds__(256) void k_split_g(const float *__restrict__ G, int P, unsigned short *__restrict__ Gbf) {
+  constexpr int RP = 16 * MT, NC = (RP + 31) / 32;
+  constexpr int FRAG = NS * MT * NC * 512;
+  const long long total = (long long)P * RP * MT * NC * 64;
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+    const int ln = (int)(t & 63);
+    long long r = t >> 6;
+    const int c = (int)(r % NC);
+    r /= NC;
+    const int mg = (int)(r % MT);
+    r /= MT;
+    const int alpha = (int)(r % RP);
+    const long long p = r / RP;
+    const int gamma = 16 * mg + (ln & 15), b0 = 32 * c + 8 * (ln >> 4);
+    const float *src = G + ((size_t)p * RP + alpha) * RP * RP + gamma;
+    float x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = b0 + i < RP ? src[(size_t)(b0 + i) * RP] : 0.f;
+    bf8 o[NS];
+    split8<NS>(x, o);
+    unsigned short *dst = Gbf + ((size_t)p * RP + alpha) * FRAG + ((size_t)mg * NC + c) * 512 + ln * 8;
+#pragma unroll
+    for (int sp = 0; sp < NS; ++sp) {
+      typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+      u4 v;
+      __builtin_memcpy(&v, &o[sp], 16);
+      *reinterpret_cast<u4 *>(dst + (size_t)sp * MT * NC * 512) = v;
+    }
+  }
+}
+
+// -------------------------------------------------------------------------------------
 // core, split-bf16 form with the slab in LDS: the same loop as k_core<float>
 // (NW wavefronts, one term each per step, Z double-buffered in LDS, phase B
 // in FP32 MFMA), with the two chained contractions of phase A on bf16 MFMA
@@ -56,9 +94,10 @@ __device__ __forceinline__ bf8 ld_bf8(const unsigned short *p) {
 // Ahat columns of the next step are prefetched.
 // -------------------------------------------------------------------------------------
 template <int MT, int NGW, int NS, int NW, bool WRITE_S1, int TZ>
-__global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict__ G, Dims D, int P, int NGS,
-                                                         Tables<float> tb, BfTables bft, float *__restrict__ S1,
-                                                         double *__restrict__ epart) {
+__global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict__ G,
+                                                         const unsigned short *__restrict__ Gbf, Dims D, int P,
+                                                         int NGS, Tables<float> tb, BfTables bft,
+                                                         float *__restrict__ S1, double *__restrict__ epart) {
   using M = MF<float>;
   using acc = f4;
   constexpr int RP = 16 * MT;
@@ -127,17 +166,28 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
       }
     }
   };
-  // zero both buffers (beta rows past RP inside the last chunk stay zero),
-  // then slab 0
-  for (int idx = tid; idx < FRAG; idx += CHT) {
-    Gs[idx] = 0;
-    Gs[FRAG + idx] = 0;
-  }
-  __syncthreads();
-  for (int c = 0; c < NCH; ++c) {
-    float v[EPT];
-    slab_load(c, 0, v);
-    slab_store(c, 0, v);
+  constexpr bool KM = NW == 8 || MT == 4 || (MT == 5 && NS == 2);
+  // term-major: slabs arrive as their split images (k_split_g), copied as they are
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  constexpr int NPC = FRAG / 8;  // 16-byte pieces of a slab image
+  const unsigned short *Gbp = KM ? Gbf + (size_t)p * RP * FRAG : nullptr;
+  if constexpr (KM) {
+    const u4 *src = reinterpret_cast<const u4 *>(Gbp);
+    u4 *dst = reinterpret_cast<u4 *>(Gs);
+    for (int e = tid; e < NPC; e += CHT) dst[e] = src[e];
+  } else {
+    // zero both buffers (beta rows past RP inside the last chunk stay zero),
+    // then slab 0
+    for (int idx = tid; idx < FRAG; idx += CHT) {
+      Gs[idx] = 0;
+      Gs[FRAG + idx] = 0;
+    }
+    __syncthreads();
+    for (int c = 0; c < NCH; ++c) {
+      float v[EPT];
+      slab_load(c, 0, v);
+      slab_store(c, 0, v);
+    }
   }
   __syncthreads();
 
@@ -168,14 +218,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
   // slabs; the next slab arrives in 16-byte pieces, EPS per thread and step
   // (the three-part form at five tiles keeps slab-major order: its held
   // fragments would not fit beside the Phi accumulators)
-  constexpr bool KM = NW == 8 || MT == 4 || (MT == 5 && NS == 2);
   if constexpr (KM) {
-    // pieces of PW consecutive gamma values: 16 bytes with four wavefronts,
-    // single values with eight (fewer registers in flight)
-    constexpr int PW = NW == 8 ? 1 : 4;
-    typedef typename std::conditional<PW == 4, float4, float>::type VP;
-    constexpr int FP = (int)(F / PW);
-    constexpr int EPS = (FP + CHT - 1) / CHT;
+    constexpr int EPS = (NPC + CHT - 1) / CHT;
     typedef float AF[NTG][MT];
     auto load_af = [&](int alpha_, int kq_, AF &af) {
 #pragma unroll
@@ -185,33 +229,17 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
         for (int mt = 0; mt < MT; ++mt) af[tg][mt] = ah[16 * mt];
       }
     };
-    auto kslab_load = [&](int a_, VP (&v)[EPS]) {
-      const VP *src = reinterpret_cast<const VP *>(Gp + (size_t)a_ * F);
+    // the next slab image, 16-byte pieces (threads past the last piece take
+    // the last one again and store the same value)
+    auto kslab_load = [&](int a_, u4 (&v)[EPS]) {
+      const u4 *src = reinterpret_cast<const u4 *>(Gbp + (size_t)a_ * FRAG);
 #pragma unroll
-      for (int j = 0; j < EPS; ++j) v[j] = src[min(j * CHT + tid, FP - 1)];
+      for (int j = 0; j < EPS; ++j) v[j] = src[min(j * CHT + tid, NPC - 1)];
     };
-    auto kslab_store = [&](int buf, const VP (&v)[EPS]) {
+    auto kslab_store = [&](int buf, const u4 (&v)[EPS]) {
+      u4 *dst = reinterpret_cast<u4 *>(Gs + buf * FRAG);
 #pragma unroll
-      for (int j = 0; j < EPS; ++j) {
-        const int e4 = j * CHT + tid;
-        if (e4 < FP) {
-          const int beta = (PW * e4) / RP, g0 = (PW * e4) % RP;
-          const float *x4 = reinterpret_cast<const float *>(&v[j]);
-#pragma unroll
-          for (int q = 0; q < PW; ++q) {
-            const int gamma = g0 + q;
-            const int ln = ((beta >> 3) & 3) * 16 + (gamma & 15);
-            const int base = ((((gamma >> 4) * NC + (beta >> 5)) * 64 + ln) * 8) + (beta & 7);
-            float r = x4[q];
-#pragma unroll
-            for (int sp = 0; sp < NS; ++sp) {
-              const __bf16 h = (__bf16)r;
-              Gs[buf * FRAG + sp * (MT * NC * 512) + base] = __builtin_bit_cast(unsigned short, h);
-              if (sp + 1 < NS) r -= (float)h;
-            }
-          }
-        }
-      }
+      for (int j = 0; j < EPS; ++j) dst[min(j * CHT + tid, NPC - 1)] = v[j];
     };
     // the gamma' tiles this workgroup's split meets: mtb .. mtb + nz - 1 (<= TZ);
     // holding all MT tiles, the tile index is compile-time and the tiles
@@ -227,7 +255,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
       const int k = NW * kq + wave;
       const bool last_a = alpha + 1 == D.r0;
       const bool more = !last_a || kq + 1 < nkq;  // uniform
-      VP gnext[EPS];
+      u4 gnext[EPS];
       kslab_load(last_a ? 0 : alpha + 1, gnext);
       if (more) load_af(last_a ? 0 : alpha + 1, last_a ? kq + 1 : kq, nxt);
       float *Zw = Zs + (size_t)(step & 1) * zsz + (size_t)wave * ZSS;
@@ -236,15 +264,24 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
         acc W[MT];
 #pragma unroll
         for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
+        // the (chunk, tile) pairs in order, their fragments read two pairs
+        // ahead of their MFMAs (a ring of three; issue order pinned)
+        constexpr int NPR = NC * MT;
+        bf8 ring[3][NS];
+        auto rdp = [&](int q, bf8 (&o)[NS]) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
+          for (int sp = 0; sp < NS; ++sp) o[sp] = ld_bf8(gl + ((sp * MT + q % MT) * NC + q / MT) * 512);
+        };
+        rdp(0, ring[0]);
+        if (NPR > 1) rdp(1, ring[1]);
+        __builtin_amdgcn_sched_group_barrier(0x100, (NPR > 1 ? 2 : 1) * NS, 0);
 #pragma unroll
-          for (int mg = 0; mg < MT; ++mg) {
-            bf8 g[NS];
-#pragma unroll
-            for (int sp = 0; sp < NS; ++sp) g[sp] = ld_bf8(gl + ((sp * MT + mg) * NC + c) * 512);
-            W[mg] = mma_split<NS>(g, hcb[c], W[mg]);
-          }
+        for (int q = 0; q < NPR; ++q) {
+          if (q + 2 < NPR) rdp(q + 2, ring[(q + 2) % 3]);
+          W[q % MT] = mma_split<NS>(ring[q % 3], hcb[q / MT], W[q % MT]);
+          if (q + 2 < NPR) __builtin_amdgcn_sched_group_barrier(0x100, NS, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, NS * (NS + 1) / 2, 0);
+        }
         bf8 wsp[NC][NS];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -269,6 +306,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
       } else {
         for (int idx = lane; idx < (g_hi - g_lo) * 16; idx += 64) Zw[(g_lo + (idx >> 4)) * ZRS + (idx & 15)] = 0.f;
       }
+      // the copy stays after this step's chains (it writes the other buffer,
+      // so nothing else orders it; next to its loads it would wait for them)
+      __builtin_amdgcn_sched_barrier(0);
       if (more) kslab_store((step + 1) & 1, gnext);
       __syncthreads();
       const float *zb = Zs + (size_t)(step & 1) * zsz + lr;
@@ -435,11 +475,11 @@ hipError_t launch_core_bf2_tz(const Tables<float> &tb, const BfTables &bft, cons
     if (ea != hipSuccess) return ea;
   }
   if (want_vx)
-    hipLaunchKernelGGL((k_core_bf2<MT, NGW, NS, NW, true, TZ>), dim3(nb), dim3(64 * NW), lds, s, (const float *)a.G, a.D,
-                       a.P, a.NGS, tb, bft, a.S1, a.epart);
+    hipLaunchKernelGGL((k_core_bf2<MT, NGW, NS, NW, true, TZ>), dim3(nb), dim3(64 * NW), lds, s, (const float *)a.G,
+                       (const unsigned short *)a.Gbf, a.D, a.P, a.NGS, tb, bft, a.S1, a.epart);
   else
     hipLaunchKernelGGL((k_core_bf2<MT, NGW, NS, NW, false, TZ>), dim3(nb), dim3(64 * NW), lds, s, (const float *)a.G,
-                       a.D, a.P, a.NGS, tb, bft, a.S1, a.epart);
+                       (const unsigned short *)a.Gbf, a.D, a.P, a.NGS, tb, bft, a.S1, a.epart);
   return hipGetLastError();
 }
 
@@ -456,6 +496,21 @@ hipError_t launch_core_bf2_mt(const Tables<float> &tb, const BfTables &bft, cons
 template <int NS>
 hipError_t launch_core_bf(const Tables<float> &tb, const BfTables &bft, const ChunkArgs<float> &a, bool want_vx,
                           hipStream_t s) {
+  if (bf_frag_elems(a.D.MT0, NS)) {
+    // the term-major cores read every slab as its split image
+    if (!a.Gbf) return hipErrorInvalidValue;
+    const long long threads = (long long)a.P * a.D.rp0 * a.D.MT0 * ((a.D.rp0 + 31) / 32) * 64;
+    const dim3 grid((unsigned)std::min<long long>((threads + 255) / 256, 65536));
+    switch (a.D.MT0) {
+      case 1: hipLaunchKernelGGL((k_split_g<1, NS>), grid, dim3(256), 0, s, (const float *)a.G, a.P, a.Gbf); break;
+      case 2: hipLaunchKernelGGL((k_split_g<2, NS>), grid, dim3(256), 0, s, (const float *)a.G, a.P, a.Gbf); break;
+      case 3: hipLaunchKernelGGL((k_split_g<3, NS>), grid, dim3(256), 0, s, (const float *)a.G, a.P, a.Gbf); break;
+      case 4: hipLaunchKernelGGL((k_split_g<4, NS>), grid, dim3(256), 0, s, (const float *)a.G, a.P, a.Gbf); break;
+      default: hipLaunchKernelGGL((k_split_g<5, NS>), grid, dim3(256), 0, s, (const float *)a.G, a.P, a.Gbf); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   switch (a.D.MT0) {
     // two-part splits at small ranks: eight wavefronts; otherwise four
     case 1:

@@ -105,6 +105,15 @@ struct PairBasesArgs {
   long long ps_c1, ps_c2, ps_ah, ps_u0;
 };
 
+// Values of one slab of G in the split-bf16 core's LDS image (parts x rank
+// tiles x K = 32 chunks x 64 lanes x 8), for the rank-tile counts and splits
+// whose core runs in term-major order (two-part splits, or four tiles); 0
+// otherwise (those cores split the slab as it arrives).
+inline int bf_frag_elems(int mt, int nsplit) {
+  if (nsplit == 0 || !(nsplit == 2 || mt == 4)) return 0;
+  return nsplit * mt * ((16 * mt + 31) / 32) * 512;
+}
+
 // Workspace and per-system data of a chunk in the collocation form (FP64).
 // Terms are taken in groups of COLLOC_GROUP: modes 2 and 1 per term into a
 // stack, then one mode-0 product over the whole group (weights folded into
@@ -158,6 +167,9 @@ struct ChunkArgs {
   int weighted;
   const double *qdev[3];
   T *T2, *G, *S1;
+  // split-bf16 cores in term-major order: G split into its bf16 parts once
+  // per pair, each slab as the core's LDS image (bf_frag_elems values)
+  unsigned short *Gbf;
   double *epart;              // [P][MT1][NGS]
   double *epair;              // all pairs of the apply, in the apply's numbering
 };
