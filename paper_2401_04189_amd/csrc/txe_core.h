@@ -324,6 +324,22 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
       for (int j = 0; j < EPS; ++j) v[j] = src[min(j * CHT + tid, FP - 1)];
     };
     auto kslab_store = [&](int buf, const V16 (&v)[EPS]) {
+      if constexpr (F32) {
+        // without a branch: threads past the slab's last piece loaded that
+        // piece (clamped) and store it again, the same values
+#pragma unroll
+        for (int j = 0; j < EPS; ++j) {
+          const int e4 = min(j * CHT + tid, FP - 1);
+          const int beta = (PE * e4) / RP, g0 = (PE * e4) % RP;
+          const T *x = reinterpret_cast<const T *>(&v[j]);
+#pragma unroll
+          for (int q = 0; q < PE; ++q) {
+            const int gamma = g0 + q;
+            Gs[buf * SLAB + beta * SROW + lane_of(gamma & 15) * LPL + (gamma >> 4)] = x[q];
+          }
+        }
+        return;
+      }
 #pragma unroll
       for (int j = 0; j < EPS; ++j) {
         const int e4 = j * CHT + tid;
@@ -442,6 +458,12 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
           if (more) kslab_store_part((step + 1) & 1, 0, gnext);
           kslab_load_part(a_next, EPS1, gnext);
         }
+        // FP32: the next slab goes into the other buffer during the Z chain
+        // (that buffer's last reads were before the previous barrier, and its
+        // loads had the W chain's time to arrive); its LDS writes are spread
+        // between the Z chain's MFMAs.  Written on the last step too, where
+        // nothing reads it.
+        if constexpr (F32) kslab_store((step + 1) & 1, gnext);
         acc Z[TZ];
 #pragma unroll
         for (int z = 0; z < TZ; ++z) Z[z] = zero4<acc>();
@@ -452,15 +474,21 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
             if (mg == MT - 1 && v >= TL) break;
 #pragma unroll
             for (int z = 0; z < TZ; ++z) Z[z] = M::mma(c2s[z][mg][v], W[mg][v], Z[z]);
+            if constexpr (F32) {
+              __builtin_amdgcn_sched_group_barrier(0x008, TZ, 0);
+              __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
+            }
           }
 #pragma unroll
         for (int z = 0; z < TZ; ++z)
           if (z < nz) store_z(Zw, mtb + z, Z[z]);
       } else {
-        if constexpr (F32)
+        if constexpr (F32) {
+          kslab_store((step + 1) & 1, gnext);
           for (int idx = lane; idx < (g_hi - g_lo) * 16; idx += 64) Zw[(g_lo + (idx >> 4)) * ZRS + (idx & 15)] = (T)0;
-        else
+        } else {
           for (int idx = lane; idx < gper * 16; idx += 64) Zw[idx] = (T)0;
+        }
         if constexpr (SPLIT) {
           if (more) kslab_store_part((step + 1) & 1, 0, gnext);
           kslab_load_part(a_next, EPS1, gnext);
@@ -469,7 +497,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core(const T *__restrict__ G, Di
       if constexpr (SPLIT) {
         if (more) kslab_store_part((step + 1) & 1, EPS1, gnext);
         load_af(alpha, kq, cur);  // this step's phase-B columns, waited for after the barrier
-      } else {
+      } else if constexpr (!F32) {
         if (more) kslab_store((step + 1) & 1, gnext);
       }
       __syncthreads();
