@@ -264,22 +264,25 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
         acc W[MT];
 #pragma unroll
         for (int mg = 0; mg < MT; ++mg) W[mg] = zero4<acc>();
-        // the (chunk, tile) pairs in order, their fragments read two pairs
-        // ahead of their MFMAs (a ring of three; issue order pinned)
+        // the (chunk, tile) pairs in order, their fragments read RA pairs
+        // ahead of their MFMAs (a ring of RA + 1; issue order pinned): a
+        // pair's MFMAs take about 50 cycles, so the reads need several pairs
         constexpr int NPR = NC * MT;
-        bf8 ring[3][NS];
+        constexpr int RA = NS == 2 && NW == 4 ? 4 : 2, RN = RA + 1;  // (eight wavefronts: another hides it)
+        bf8 ring[RN][NS];
         auto rdp = [&](int q, bf8 (&o)[NS]) {
 #pragma unroll
           for (int sp = 0; sp < NS; ++sp) o[sp] = ld_bf8(gl + ((sp * MT + q % MT) * NC + q / MT) * 512);
         };
-        rdp(0, ring[0]);
-        if (NPR > 1) rdp(1, ring[1]);
-        __builtin_amdgcn_sched_group_barrier(0x100, (NPR > 1 ? 2 : 1) * NS, 0);
+#pragma unroll
+        for (int q = 0; q < RA; ++q)
+          if (q < NPR) rdp(q, ring[q]);
+        __builtin_amdgcn_sched_group_barrier(0x100, (NPR < RA ? NPR : RA) * NS, 0);
 #pragma unroll
         for (int q = 0; q < NPR; ++q) {
-          if (q + 2 < NPR) rdp(q + 2, ring[(q + 2) % 3]);
-          W[q % MT] = mma_split<NS>(ring[q % 3], hcb[q / MT], W[q % MT]);
-          if (q + 2 < NPR) __builtin_amdgcn_sched_group_barrier(0x100, NS, 0);
+          if (q + RA < NPR) rdp(q + RA, ring[(q + RA) % RN]);
+          W[q % MT] = mma_split<NS>(ring[q % RN], hcb[q / MT], W[q % MT]);
+          if (q + RA < NPR) __builtin_amdgcn_sched_group_barrier(0x100, NS, 0);
           __builtin_amdgcn_sched_group_barrier(0x008, NS * (NS + 1) / 2, 0);
         }
         bf8 wsp[NC][NS];
@@ -293,6 +296,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
           }
           split8<NS>(x, wsp[c]);
         }
+        // the next slab image into the other buffer (last read before the
+        // previous barrier) beside the Z chain; on the last step too, where
+        // nothing reads it
+        kslab_store((step + 1) & 1, gnext);
 #pragma unroll
         for (int z = 0; z < TZ; ++z) {
           if (z >= nz) break;  // uniform
@@ -304,12 +311,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_core_bf2(const float *__restrict
           for (int v = 0; v < 4; ++v) Zw[(16 * (mtb + z) + 4 * lg + v) * ZRS + lr] = Z[v];
         }
       } else {
+        kslab_store((step + 1) & 1, gnext);
         for (int idx = lane; idx < (g_hi - g_lo) * 16; idx += 64) Zw[(g_lo + (idx >> 4)) * ZRS + (idx & 15)] = 0.f;
       }
-      // the copy stays after this step's chains (it writes the other buffer,
-      // so nothing else orders it; next to its loads it would wait for them)
-      __builtin_amdgcn_sched_barrier(0);
-      if (more) kslab_store((step + 1) & 1, gnext);
       __syncthreads();
       const float *zb = Zs + (size_t)(step & 1) * zsz + lr;
       float bz[NTG][NGW];
