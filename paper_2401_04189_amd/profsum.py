@@ -3,6 +3,8 @@
     python -m paper_2401_04189_amd.profsum ktrace  <run_kernel_stats.csv> <out.md> "<title>" "<command>"
     python -m paper_2401_04189_amd.profsum traffic <fetch.csv> <write.csv> <out.md> "<title>" <key> \
         "<fetch cmd>" "<write cmd>" [<algorithmic core bytes per launch>]
+    python -m paper_2401_04189_amd.profsum sq <counter_collection.csv> <out.md> "<title>" "<command>" \
+        [<FP32 core flops per launch> [<FP64 core flops per launch>]]
 
 `traffic` scales the per-dispatch FETCH_SIZE / WRITE_SIZE counters (KiB) by
 what the same counters read for bench.py's calibration kernel (torch.mul of
@@ -11,6 +13,12 @@ AUnaryFunctor dispatch of the run), and records the per-launch HBM bytes of
 the core kernel in profiles/traffic_core.json under <key> (e.g. "cfg4/f32")
 together with the hash of the kernel source they were taken from (bench.py
 reports them only while that source is unchanged).
+
+`sq` summarises one pass of SQ / GRBM counters per kernel: cycles =
+GRBM_GUI_ACTIVE / 8 (the counter sums the eight XCDs), MFMA busy =
+SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x cycles), executed MFMA flops =
+SQ_INSTS_VALU_MFMA_MOPS_* x 512, waits = SQ_WAIT_ANY / SQ_WAVE_CYCLES, LDS
+conflict share = SQ_LDS_BANK_CONFLICT / (256 CUs x cycles).
 """
 from __future__ import annotations
 
@@ -108,10 +116,46 @@ def traffic(fetch_csv, write_csv, out_md, title, key, cmd_f, cmd_w, alg_bytes=No
     json.dump(old, open(TRAFFIC_JSON, "w"), indent=1)
 
 
+def sq(csv_path, out_md, title, cmd, f32_core_flops=None, f64_core_flops=None, clock_ghz=2.4):
+    per = collections.defaultdict(lambda: collections.defaultdict(dict))
+    for r in csv.DictReader(open(csv_path)):
+        per[r["Kernel_Name"]][int(r["Dispatch_Id"])][r["Counter_Name"]] = float(r["Counter_Value"])
+    lines = [f"# Core-kernel counters: {title}", "", "Command (from the repository root, on the machine with the GPU):",
+             "", "```", cmd, "```", "",
+             "Derived per dispatch (averages over the dispatches of each kernel): cycles = GRBM_GUI_ACTIVE / 8;",
+             "MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x cycles); executed MFMA flops =",
+             "SQ_INSTS_VALU_MFMA_MOPS_* x 512 (a 16x16x4 MFMA counts 4); executed / algorithmic is the work the",
+             "tiling adds; waits = SQ_WAIT_ANY / SQ_WAVE_CYCLES; LDS conflict share = SQ_LDS_BANK_CONFLICT /",
+             "(256 CUs x cycles).", "",
+             "| Kernel | Dispatches | ms (cycles / clock) | MFMA busy | Executed TFLOP/s | Executed / algorithmic | Waits | LDS conflict share |",
+             "|---|---|---|---|---|---|---|---|"]
+    for k, ds in per.items():
+        if "txe::" not in k:
+            continue
+        def avg(name):
+            v = [d.get(name, 0.0) for d in ds.values()]
+            return sum(v) / len(v)
+        cyc = avg("GRBM_GUI_ACTIVE") / 8.0
+        if cyc <= 0:
+            continue
+        ms = cyc / (clock_ghz * 1e6)
+        busy = avg("SQ_VALU_MFMA_BUSY_CYCLES") / (1024.0 * cyc)
+        flops = (avg("SQ_INSTS_VALU_MFMA_MOPS_F32") + avg("SQ_INSTS_VALU_MFMA_MOPS_F64")) * 512.0
+        tf = flops / (ms * 1e-3) / 1e12
+        alg = f32_core_flops if re.search(r"k_core<float", k) else f64_core_flops if re.search(r"k_core<double", k) else None
+        ratio = f"{flops / float(alg):.2f}" if alg else "—"
+        waits = avg("SQ_WAIT_ANY") / max(avg("SQ_WAVE_CYCLES"), 1.0)
+        lds = avg("SQ_LDS_BANK_CONFLICT") / (256.0 * cyc)
+        lines.append(f"| `{short(k)}` | {len(ds)} | {ms:.1f} | {busy:.2f} | {tf:.1f} | {ratio} | {waits:.2f} | {lds:.2f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "ktrace":
         ktrace(*sys.argv[2:6])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:10])
+    elif sys.argv[1] == "sq":
+        sq(*sys.argv[2:6], *[float(x) for x in sys.argv[6:8]])
     else:
         raise SystemExit(__doc__)
