@@ -17,16 +17,35 @@ namespace {
 // contiguous along o, X is the A operand so that the lanes of an accumulator
 // row run along o.
 constexpr int LT = 64;      // output tile edge
-constexpr int KC = 64;      // contraction chunk
-constexpr int MS = KC + 2;  // padded row of the M block (doubles)
+constexpr int KC = 64;      // contraction chunk (at most)
 constexpr int XS = LT + 2;  // padded row of the X block
+// the chunk a product uses (nin rounded up to 4, at most KC) and the padded M
+// row: the LDS is sized by them, so short contractions fit three blocks per CU
+__host__ __device__ inline int kc_of(int nin) { return nin < KC ? (nin + 3) & ~3 : KC; }
+// Element (row i, column j) of the mode-d unfolding of an (A, B, C) tensor
+// sits at col_off(j) + i * row_stride: the column part is formed once per
+// thread and block (a thread keeps its column across the K chunks), so no
+// division runs per element.
+__device__ __forceinline__ long long col_off(int d, int B, int C, long long j) {
+  if (d == 0) return j;
+  if (d == 1) {
+    const unsigned long long q = (unsigned long long)j / (unsigned)C;  // once per thread and block
+    return (long long)q * B * C + (long long)(j - (long long)q * C);
+  }
+  return j * C;
+}
+__device__ __forceinline__ long long row_stride(int d, int B, int C) {
+  return d == 0 ? (long long)B * C : d == 1 ? (long long)C : 1;
+}
+
 __global__ __launch_bounds__(256) void k_mode_lds(const double *__restrict__ X, long long xs, int A, int B, int C,
                                                   int d, int nin, const double *__restrict__ Mm, long long ms, int ldm,
                                                   int Mt, int nout, const double *__restrict__ qout, double yscale,
                                                   int accum, double *__restrict__ Y, long long ys) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int kc = kc_of(nin), MS = kc + 2;
   double *Ms = reinterpret_cast<double *>(smem_raw);  // [LT][MS]: M(i, o) at [o][i - c0]
-  double *Xs = Ms + LT * MS;                          // [KC][XS]: X(i, j) at [i - c0][j - j0]
+  double *Xs = Ms + LT * MS;                          // [kc][XS]: X(i, j) at [i - c0][j - j0]
   const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int ext = d == 0 ? A : d == 1 ? B : C;
@@ -43,14 +62,19 @@ __global__ __launch_bounds__(256) void k_mode_lds(const double *__restrict__ X, 
   const int o0 = LT * to;
   const long long j0 = LT * tj;
   const int ob = 32 * (wave >> 1), jb = 32 * (wave & 1);
+  const long long xr = row_stride(d, B, C);
+  // modes 0 and 1: X is staged along j, and thread tid keeps column tid mod LT
+  // in every pass of the staging loop (256 is a multiple of LT)
+  const long long jt = j0 + (tid % LT);
+  const long long xcol = d != 2 && jt < J ? col_off(d, B, C, jt) : 0;
   typedef double d4 __attribute__((ext_vector_type(4)));
   d4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (d4){0.0, 0.0, 0.0, 0.0};
-  for (int c0 = 0; c0 < nin; c0 += KC) {
-    const int nc = min(KC, nin - c0), NI = (nc + 3) & ~3;
+  for (int c0 = 0; c0 < nin; c0 += kc) {
+    const int nc = min(kc, nin - c0), NI = (nc + 3) & ~3;
     // M block, read along its contiguous index
     for (int e = tid; e < LT * NI; e += 256) {
       int o, i;
@@ -59,11 +83,17 @@ __global__ __launch_bounds__(256) void k_mode_lds(const double *__restrict__ X, 
       Ms[o * MS + i] = (og < nout && i < nc) ? (Mt ? Mp[(size_t)og * ldm + ig] : Mp[(size_t)ig * ldm + og]) : 0.0;
     }
     // X block, read along its contiguous index (j for modes 0 and 1, i for mode 2)
-    for (int e = tid; e < LT * NI; e += 256) {
-      int i, jl;
-      if (d == 2) { jl = e / NI; i = e % NI; } else { i = e / LT; jl = e % LT; }
-      const long long j = j0 + jl;
-      Xs[i * XS + jl] = (j < J && i < nc) ? Xp[unfold_at(d, B, C, c0 + i, j)] : 0.0;
+    if (d == 2) {
+      for (int e = tid; e < LT * NI; e += 256) {
+        const int jl = e / NI, i = e % NI;
+        const long long j = j0 + jl;
+        Xs[i * XS + jl] = (j < J && i < nc) ? Xp[j * C + c0 + i] : 0.0;
+      }
+    } else {
+      for (int e = tid; e < LT * NI; e += 256) {
+        const int i = e / LT, jl = e % LT;  // jl == tid % LT
+        Xs[i * XS + jl] = (jt < J && i < nc) ? Xp[xcol + (long long)(c0 + i) * xr] : 0.0;
+      }
     }
     __syncthreads();
     if (d == 2) {
@@ -98,29 +128,40 @@ __global__ __launch_bounds__(256) void k_mode_lds(const double *__restrict__ X, 
     __syncthreads();  // the next chunk overwrites the blocks
   }
   double *Yp = Y + (size_t)p * ys;
+  const long long yr = row_stride(d, Bo, Co);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int t = 0; t < 2; ++t) {
+    // the lane's fixed index of tile t: column j (modes 0, 1) or row o (mode 2)
+    const int fo = o0 + ob + 16 * t + lr;
+    const long long fj = j0 + jb + 16 * t + lr;
+    const long long ycol = d != 2 && fj < J ? col_off(d, Bo, Co, fj) : 0;
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         // FP64 accumulator row 4v + lg, column lr of tile (a, b)
         int o;
-        long long j;
-        if (d == 2) {
-          o = o0 + ob + 16 * b + lr;
-          j = j0 + jb + 16 * a + 4 * v + lg;
-        } else {
-          o = o0 + ob + 16 * a + 4 * v + lg;
-          j = j0 + jb + 16 * b + lr;
+        long long j, at;
+        double r;
+        if (d == 2) {  // tile (a = u, b = t): lanes along o
+          o = fo;
+          j = j0 + jb + 16 * u + 4 * v + lg;
+          at = j * Co + o;
+          r = acc[u][t][v];
+        } else {  // tile (a = u, b = t): lanes along j
+          o = o0 + ob + 16 * u + 4 * v + lg;
+          j = fj;
+          at = ycol + (long long)o * yr;
+          r = acc[u][t][v];
         }
         if (o < nout && j < J) {
-          double val = yscale * (qout ? acc[a][b][v] / sqrt(qout[o]) : acc[a][b][v]);
-          double *y = Yp + unfold_at(d, Bo, Co, o, j);
+          double val = yscale * (qout ? r / sqrt(qout[o]) : r);
+          double *y = Yp + at;
           if (accum) val += *y;
           *y = val;
         }
       }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_accum(const double *__restrict__ phi, int phi_acb,
@@ -163,9 +204,12 @@ hipError_t launch_mode_f64(const double *X, long long xs, int A, int B, int C, i
   const int ext = d == 0 ? A : d == 1 ? B : C;
   const long long J = (long long)A * B * C / ext;
   const long long blocks = (long long)P * ((nout + LT - 1) / LT) * ((J + LT - 1) / LT);
-  constexpr size_t lds = ((size_t)LT * MS + (size_t)KC * XS) * sizeof(double);  // 67.6 KB
+  const int kc = kc_of(nin);
+  // the launch takes what its chunk needs (42.6 KB at nin = 40); the opt-in is the largest
+  const size_t lds = ((size_t)LT * (kc + 2) + (size_t)kc * XS) * sizeof(double);
+  constexpr size_t lds_max = ((size_t)LT * (KC + 2) + (size_t)KC * XS) * sizeof(double);  // 67.6 KB
   const hipError_t ea = hipFuncSetAttribute((const void *)k_mode_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)lds);
+                                            (int)lds_max);
   if (ea != hipSuccess) return ea;
   hipLaunchKernelGGL(k_mode_lds, dim3((unsigned)blocks), dim3(256), lds, s, X, xs, A, B, C, d, nin, M, ms, ldm, Mt,
                      nout, qout, yscale, accum, Y, ys);
