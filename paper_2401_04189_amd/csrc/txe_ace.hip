@@ -5,8 +5,9 @@
 //
 // Three kernels, all FP64 arithmetic (inputs may be FP32):
 //   k_gram     G[i][j] = sum_g w(g) X_i(g) Y_j(g): FP64 MFMA 16x16x4 per
-//              (i tile, j tile, grid chunk), chunk partials summed in order
-//              by k_gram_reduce (no atomics, bitwise repeatable)
+//              (64 x 64 output tile, grid chunk), operands staged in LDS,
+//              chunk partials summed in order by k_gram_reduce (no atomics,
+//              bitwise repeatable)
 //   k_chol_inv one workgroup: Cholesky of -M (left-looking, a column at a
 //              time) and the inverse of the triangular factor, column per
 //              thread
@@ -27,51 +28,81 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// One wavefront per (chunk, i tile, j tile).  Lane (lr, lg) reads four
-// consecutive grid points base + 4 lg + q (q = 0..3) of row 16 ti + lr of X
-// and of row 16 tj + lr of Y; step q is one MFMA whose K index is lg.  The
-// four points share (a, b) because n2 is a multiple of 4.
+// One workgroup per (grid chunk, 64-row i tile, 64-column j tile); each
+// wavefront holds a 32 x 32 corner (2 x 2 MFMA tiles).  The chunk is walked
+// in slices of GS grid points: rows of X and of w Y are staged in LDS (thread
+// t takes point t mod GS of the slice and eight rows of each, so a point's
+// weight is formed once per slice), then each wavefront runs GS / 4 MFMA K
+// steps from LDS.  Every staged value serves four MFMA tiles.
+constexpr int GT = 64;       // output tile edge
+constexpr int GS = 32;       // grid points per slice
+constexpr int GP = GS + 2;   // padded LDS row (doubles): a fragment read hits 64 distinct banks
 template <typename TX, typename TY>
 __global__ __launch_bounds__(256) void k_gram(const TX *__restrict__ X, int NX, const TY *__restrict__ Y, int NY,
                                               int n0, int n1, int n2, const double *__restrict__ q0,
                                               const double *__restrict__ q1, const double *__restrict__ q2,
                                               long long chunk, int nchunks, double *__restrict__ part) {
-  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int nti = (NX + 15) >> 4, ntj = (NY + 15) >> 4;
-  const long long item = (long long)blockIdx.x * 4 + wave;
-  const long long total = (long long)nchunks * nti * ntj;
-  if (item >= total) return;  // whole wavefront (item is uniform)
-  const int tj = (int)(item % ntj);
-  const int ti = (int)((item / ntj) % nti);
-  const int ch = (int)(item / ((long long)ntj * nti));
+  __shared__ double Xs[GT * GP], Ys[GT * GP];
+  const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
+  const int nti = (NX + GT - 1) / GT, ntj = (NY + GT - 1) / GT;
+  const long long blk = blockIdx.x;
+  const int tj = (int)(blk % ntj);
+  const int ti = (int)((blk / ntj) % nti);
+  const int ch = (int)(blk / ((long long)ntj * nti));
   const long long ng = (long long)n0 * n1 * n2;
   const long long g_begin = ch * chunk;
   const long long g_end = g_begin + chunk < ng ? g_begin + chunk : ng;
-  const int ix = min(16 * ti + lr, NX - 1), iy = min(16 * tj + lr, NY - 1);
-  const bool vx = 16 * ti + lr < NX, vy = 16 * tj + lr < NY;
-  const TX *xr = X + (size_t)ix * ng;
-  const TY *yr = Y + (size_t)iy * ng;
-  d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (long long base = g_begin; base < g_end; base += 16) {
-    const long long p = base + 4 * lg;  // multiple of 4: same (a, b) for the four points
-    const int c = (int)(p % n2);
-    const long long ab = p / n2;
-    const int b = (int)(ab % n1), a = (int)(ab / n1);
-    const double wab = q0[a] * q1[b];
+  const int ib = 32 * (wave >> 1), jb = 32 * (wave & 1);
+  // staging: point sp = tid mod GS of the slice, rows r0 + 8 k (k < 8)
+  const int sp = tid % GS, r0 = tid / GS;
+  typedef double d4v __attribute__((ext_vector_type(4)));
+  d4v acc[2][2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double xv = vx ? (double)xr[p + q] : 0.0;
-      const double yv = vy ? (double)yr[p + q] * (wab * q2[c + q]) : 0.0;
-      acc = mfma64(xv, yv, acc);
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
+  for (long long base = g_begin; base < g_end; base += GS) {
+    const long long g = base + sp;
+    const bool live = g < g_end;
+    double w = 0.0;
+    if (live) {
+      const int c = (int)(g % n2);
+      const long long ab = g / n2;
+      w = q0[ab / n1] * q1[ab % n1] * q2[c];
     }
-  }
-  // f64 MFMA result: row 4 v + lg, column lr
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int i = 16 * ti + 4 * v + lg, j = 16 * tj + lr;
-    if (i < NX && j < NY) part[((size_t)ch * NX + i) * NY + j] = acc[v];
+    for (int k = 0; k < 8; ++k) {
+      const int r = r0 + 8 * k;
+      const int ix = GT * ti + r, iy = GT * tj + r;
+      Xs[r * GP + sp] = live && ix < NX ? (double)X[(size_t)ix * ng + g] : 0.0;
+      Ys[r * GP + sp] = live && iy < NY ? w * (double)Y[(size_t)iy * ng + g] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k0 = 0; k0 < GS; k0 += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = Xs[(ib + 16 * a + lr) * GP + k0 + lg];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Ys[(jb + 16 * b + lr) * GP + k0 + lg];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();  // the next slice overwrites the staged rows
   }
+  // f64 MFMA result: row 4 v + lg, column lr of each tile
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = GT * ti + ib + 16 * a + 4 * v + lg, j = GT * tj + jb + 16 * b + lr;
+        if (i < NX && j < NY) part[((size_t)ch * NX + i) * NY + j] = acc[a][b][v];
+      }
 }
 
 __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ part, int nchunks, long long nxy,
@@ -194,16 +225,16 @@ constexpr int COMB_MG = 4;
 // ------------------------------------------------------------------------------------
 // host-side launchers (argument checks are done by the caller)
 // ------------------------------------------------------------------------------------
-// Grid points per chunk of the Gram kernel: about 8192 wavefronts in all,
-// chunks of at least 64 points, a multiple of 16.
+// Grid points per chunk of the Gram kernel: about 2048 workgroups in all,
+// chunks of at least 256 points, a multiple of the slice.
 static long long gram_chunk_len(int NX, int NY, long long ng) {
-  const long long tiles = (long long)((NX + 15) / 16) * ((NY + 15) / 16);
-  long long nch = (8192 + tiles - 1) / tiles;
-  const long long maxch = ng / 64;
+  const long long tiles = (long long)((NX + GT - 1) / GT) * ((NY + GT - 1) / GT);
+  long long nch = (2048 + tiles - 1) / tiles;
+  const long long maxch = ng / 256;
   if (nch > maxch) nch = maxch;
   if (nch < 1) nch = 1;
   const long long chunk = (ng + nch - 1) / nch;
-  return (chunk + 15) / 16 * 16;
+  return (chunk + GS - 1) / GS * GS;
 }
 
 int gram_nchunks(int NX, int NY, long long ng) {
@@ -217,9 +248,9 @@ static hipError_t gram_t(const TX *X, int NX, const TY *Y, int NY, const Dims &D
   const long long ng = (long long)D.n0 * D.n1 * D.n2;
   const long long chunk = gram_chunk_len(NX, NY, ng);
   const int nchunks = gram_nchunks(NX, NY, ng);
-  const long long waves = (long long)nchunks * ((NX + 15) / 16) * ((NY + 15) / 16);
-  hipLaunchKernelGGL((k_gram<TX, TY>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, X, NX, Y, NY, D.n0, D.n1,
-                     D.n2, qdev[0], qdev[1], qdev[2], chunk, nchunks, part);
+  const long long blocks = (long long)nchunks * ((NX + GT - 1) / GT) * ((NY + GT - 1) / GT);
+  hipLaunchKernelGGL((k_gram<TX, TY>), dim3((unsigned)blocks), dim3(256), 0, s, X, NX, Y, NY, D.n0, D.n1, D.n2,
+                     qdev[0], qdev[1], qdev[2], chunk, nchunks, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long nxy = (long long)NX * NY;
