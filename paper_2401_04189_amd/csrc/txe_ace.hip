@@ -8,9 +8,10 @@
 //              (64 x 64 output tile, grid chunk), operands staged in LDS,
 //              chunk partials summed in order by k_gram_reduce (no atomics,
 //              bitwise repeatable)
-//   k_chol_inv one workgroup: Cholesky of -M (left-looking, a column at a
-//              time) and the inverse of the triangular factor, column per
-//              thread
+//   k_chol     one workgroup: Cholesky of -M (left-looking, a column at a
+//              time, the pivot row's prefix in LDS)
+//   k_tri_inv  the inverse of the triangular factor, a column per thread
+//              over as many workgroups as it takes
 //   k_comb     out[m][g] = s * sum_i A[m][i] X_i(g): FP64 MFMA with the
 //              grid point as the output column
 #include <hip/hip_runtime.h>
@@ -114,28 +115,30 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ 
   G[e] = s;
 }
 
-// Cholesky of -M and the inverse of its factor, in one workgroup of 256.
-// info: 0 on success, j + 1 when the pivot of column j is not positive
-// (M not negative definite); L and T are then undefined.
-__global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ M, int N, double *__restrict__ L,
-                                                  double *__restrict__ T, int *__restrict__ info) {
+// Cholesky of -M in one workgroup of 256 (left-looking, a column at a time):
+// the pivot row's finished prefix L[j][0..j) is staged in LDS, and each
+// thread forms its rows' dot products with four partial sums (a fixed order
+// per thread).  info: 0 on success, j + 1 when the pivot of column j is not
+// positive (M not negative definite); L is then undefined.
+constexpr int CHOL_MAX = 2048;
+__global__ __launch_bounds__(256) void k_chol(const double *__restrict__ M, int N, double *__restrict__ L,
+                                              int *__restrict__ info) {
   __shared__ double red[256];
-  __shared__ int bad;
+  __shared__ double lj[CHOL_MAX];
   const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
   for (long long e = tid; e < (long long)N * N; e += 256) {
     const int i = (int)(e / N), j = (int)(e % N);
-    if (j > i) {
-      L[e] = 0.0;
-      T[e] = 0.0;
-    }
+    if (j > i) L[e] = 0.0;
   }
-  __syncthreads();
   for (int j = 0; j < N; ++j) {
-    // pivot: -M[j][j] - sum_{k<j} L[j][k]^2, each thread a strided part in
-    // order, then a fixed-shape tree
+    // the pivot row's prefix, and its squares summed: each thread a strided
+    // part in order, then a fixed-shape tree
     double s = 0.0;
-    for (int k = tid; k < j; k += 256) s += L[(size_t)j * N + k] * L[(size_t)j * N + k];
+    for (int k = tid; k < j; k += 256) {
+      const double v = L[(size_t)j * N + k];
+      lj[k] = v;
+      s += v * v;
+    }
     red[tid] = s;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -145,32 +148,51 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double *__restrict__ M, 
     const double d = -M[(size_t)j * N + j] - red[0];
     __syncthreads();  // red[0] read by everyone before it is overwritten
     if (!(d > 0.0) || !isfinite(d)) {
-      if (tid == 0) {
-        bad = j + 1;
-        *info = j + 1;
-      }
-      break;  // uniform: every thread computed the same d
+      if (tid == 0) *info = j + 1;
+      return;  // uniform: every thread computed the same d
     }
     const double ljj = sqrt(d);
     if (tid == 0) L[(size_t)j * N + j] = ljj;
     for (int i = j + 1 + tid; i < N; i += 256) {
-      double t = -M[(size_t)i * N + j];
-      for (int k = 0; k < j; ++k) t -= L[(size_t)i * N + k] * L[(size_t)j * N + k];
-      L[(size_t)i * N + j] = t / ljj;
+      const double *li = L + (size_t)i * N;
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+      int k = 0;
+      for (; k + 3 < j; k += 4) {
+        t0 += li[k] * lj[k];
+        t1 += li[k + 1] * lj[k + 1];
+        t2 += li[k + 2] * lj[k + 2];
+        t3 += li[k + 3] * lj[k + 3];
+      }
+      for (; k < j; ++k) t0 += li[k] * lj[k];
+      L[(size_t)i * N + j] = (-M[(size_t)i * N + j] - ((t0 + t1) + (t2 + t3))) / ljj;
     }
-    __syncthreads();
+    __syncthreads();  // column j is complete before row j + 1 is staged
   }
-  __syncthreads();
-  if (bad) return;
   if (tid == 0) *info = 0;
-  // T = L^-1 (lower): column c by one thread, rows in order
-  for (int c = tid; c < N; c += 256) {
-    T[(size_t)c * N + c] = 1.0 / L[(size_t)c * N + c];
-    for (int i = c + 1; i < N; ++i) {
-      double t = 0.0;
-      for (int k = c; k < i; ++k) t += L[(size_t)i * N + k] * T[(size_t)k * N + c];
-      T[(size_t)i * N + c] = -t / L[(size_t)i * N + i];
+}
+
+// T = L^-1 (lower triangular), one column per thread (the columns are
+// independent: column c solves L t = e_c by forward substitution, rows in
+// order, four partial sums per row); skipped unless the factorisation
+// succeeded.
+__global__ __launch_bounds__(256) void k_tri_inv(const double *__restrict__ L, int N, const int *__restrict__ info,
+                                                 double *__restrict__ T) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= N || *info != 0) return;
+  for (int i = 0; i < c; ++i) T[(size_t)i * N + c] = 0.0;
+  T[(size_t)c * N + c] = 1.0 / L[(size_t)c * N + c];
+  for (int i = c + 1; i < N; ++i) {
+    const double *li = L + (size_t)i * N;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    int k = c;
+    for (; k + 3 < i; k += 4) {
+      t0 += li[k] * T[(size_t)k * N + c];
+      t1 += li[k + 1] * T[(size_t)(k + 1) * N + c];
+      t2 += li[k + 2] * T[(size_t)(k + 2) * N + c];
+      t3 += li[k + 3] * T[(size_t)(k + 3) * N + c];
     }
+    for (; k < i; ++k) t0 += li[k] * T[(size_t)k * N + c];
+    T[(size_t)i * N + c] = -((t0 + t1) + (t2 + t3)) / L[(size_t)i * N + i];
   }
 }
 
@@ -267,7 +289,11 @@ hipError_t ace_gram(bool x64, bool y64, const void *X, int NX, const void *Y, in
 }
 
 hipError_t ace_chol_inv(const double *M, int N, double *L, double *T, int *info, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, M, N, L, T, info);
+  if (N > CHOL_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), 0, s, M, N, L, info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tri_inv, dim3((N + 255) / 256), dim3(256), 0, s, L, N, (const int *)info, T);
   return hipGetLastError();
 }
 

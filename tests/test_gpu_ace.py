@@ -5,7 +5,11 @@ against the CPU oracle, each side from its own exchange action.
     on random trial functions against the oracle's operator;
   * exactness on the orbitals (V_ACE psi = Vx psi) on the GPU, FP64 and
     FP32, at 16^3 and on the 64^3 / 64-orbital workload;
-  * a W that is not negative definite sets info to the failing column.
+  * a W that is not negative definite sets info to the failing column;
+  * many orbitals (several 64 x 64 Gram tiles with a ragged last one, and
+    several grid chunks): the build and a non-square apply against the
+    oracle, with synthetic orbitals and W = -psi (M = -Gram(psi) is negative
+    definite).
 """
 import numpy as np
 import pytest
@@ -104,3 +108,28 @@ def test_ace_reports_non_definite_matrix(ctx, small):
     xi, info = txe.ace_build(ctx, sysm, psi, psi.clone())
     torch.cuda.synchronize()
     assert int(info) == 1
+
+
+def test_ace_many_orbitals_against_oracle(ctx, small):
+    """N = 150 (three Gram tiles, the last with 22 rows) on the 16^3 grid
+    (16 grid chunks per tile); 70 trial functions for the apply (a 70 x 150
+    Gram).  Inputs are synthetic: the build only needs W with <psi, W> < 0."""
+    s, sysm, st = small[0], small[1], small[2]
+    rng = np.random.default_rng(150)
+    p = rng.standard_normal((150,) + tuple(sysm.n))
+    w = -p
+    M_ref, L_ref, xi_ref = O.ace_build(p, w, st.q)
+    psi = torch.as_tensor(p, device="cuda")
+    xi, info, M, L = txe.ace_build(ctx, sysm, psi, torch.as_tensor(w, device="cuda"), want_factors=True)
+    phi = rng.standard_normal((70,) + tuple(sysm.n))
+    out = txe.ace_apply(ctx, sysm, xi, torch.as_tensor(phi, device="cuda")).cpu().numpy()
+    torch.cuda.synchronize()
+    M, L, xi = M.cpu().numpy(), L.cpu().numpy(), xi.cpu().numpy()
+    em = np.abs(M - M_ref).max() / np.abs(M_ref).max()
+    el = np.abs(L - L_ref).max() / np.abs(L_ref).max()
+    ex = np.abs(xi - xi_ref).max() / np.abs(xi_ref).max()
+    ref = O.ace_apply(xi_ref, st.q, phi)
+    ea = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"N=150: M rel {em:.2e}  L rel {el:.2e}  xi rel {ex:.2e}  V_ACE phi rel {ea:.2e}", flush=True)
+    assert int(info) == 0
+    assert em <= 1e-10 and el <= 1e-10 and ex <= 1e-9 and ea <= 1e-9
