@@ -2,8 +2,9 @@
 // actually sustains, the measured denominators next to the published peaks
 // in a roofline.  Each MFMA kernel keeps eight independent accumulator
 // chains per wavefront (enough to cover the pipeline latency of every shape
-// used here) and runs a fixed trip count; the stream kernel reads and writes
-// float4 with a grid-stride loop.
+// used here) and runs a fixed trip count on operands that differ from lane
+// to lane and element to element (hashed values in [0.5, 1.5), as in real
+// tiles); the stream kernel reads and writes float4 with a grid-stride loop.
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -20,9 +21,19 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 constexpr int CHAINS = 8;
 constexpr int ITERS = 2048;
 
+// an integer hash of x mapped to [0.5, 1.5)
+__device__ __forceinline__ float hashed(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return 0.5f + (float)(x >> 8) * (1.0f / 16777216.0f);
+}
+
 __global__ __launch_bounds__(256) void k_peak_f64(double seed, double *out) {
   d4 c[CHAINS];
-  const double a = seed + threadIdx.x * 1e-9, b = seed - threadIdx.x * 1e-9;
+  const double a = seed * hashed(2 * threadIdx.x), b = seed * hashed(2 * threadIdx.x + 1);
 #pragma unroll
   for (int i = 0; i < CHAINS; ++i) c[i] = d4{0.0, 0.0, 0.0, 0.0};
   for (int it = 0; it < ITERS; ++it)
@@ -36,7 +47,7 @@ __global__ __launch_bounds__(256) void k_peak_f64(double seed, double *out) {
 
 __global__ __launch_bounds__(256) void k_peak_f32(float seed, float *out) {
   f4v c[CHAINS];
-  const float a = seed + threadIdx.x * 1e-6f, b = seed - threadIdx.x * 1e-6f;
+  const float a = seed * hashed(2 * threadIdx.x), b = seed * hashed(2 * threadIdx.x + 1);
 #pragma unroll
   for (int i = 0; i < CHAINS; ++i) c[i] = f4v{0.f, 0.f, 0.f, 0.f};
   for (int it = 0; it < ITERS; ++it)
@@ -53,8 +64,8 @@ __global__ __launch_bounds__(256) void k_peak_bf16(float seed, float *out) {
   bf8v a, b;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    a[i] = (__bf16)(seed + i * 1e-3f);
-    b[i] = (__bf16)(seed - i * 1e-3f + threadIdx.x * 1e-6f);
+    a[i] = (__bf16)(seed * hashed(16 * threadIdx.x + i));
+    b[i] = (__bf16)(seed * hashed(16 * threadIdx.x + 8 + i));
   }
 #pragma unroll
   for (int i = 0; i < CHAINS; ++i) c[i] = f4v{0.f, 0.f, 0.f, 0.f};
