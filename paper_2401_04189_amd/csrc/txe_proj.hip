@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_proj12(const Tin *__restrict__ psi, Dim
 // the grid are zeroed by a select.  TABS: the shared operands in LDS,
 // 2 = V2 and the chained V1 fragments, 1 = V2 only, 0 = neither.
 template <typename T, typename Tin, int MT, int TABS, int PD>
-__global__ __launch_bounds__(256) void k_proj12m(const Tin *__restrict__ psi, Dims D, PairMap pm, int P,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_proj12m(const Tin *__restrict__ psi, Dims D, PairMap pm, int P,
                                                  Tables<T> tb, T *__restrict__ T2) {
   using M = MF<T>;
   using acc = typename M::acc;
