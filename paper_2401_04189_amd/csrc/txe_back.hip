@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void k_back_b(const T *__restrict__ S1, const 
 __host__ __device__ constexpr int back_srs(int rp) { return rp % 32 == 16 ? rp : rp + 16; }
 
 template <typename T, typename Tin, typename Tps, int MT, int NBT, int NCG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_back_l(const T *__restrict__ S1, const Tps *__restrict__ psi, Dims D,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_back_l(const T *__restrict__ S1, const Tps *__restrict__ psi, Dims D,
                                                 PairMap pm, BackRange br, Tables<T> tb,
                                                 Tin *__restrict__ vx, const double *__restrict__ out_scale,
                                                 int weighted, const double *__restrict__ q0,
@@ -460,7 +460,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int cg = 0; cg < NCG; ++cg) X[mb][cg] = zero4<acc>();
 #pragma unroll
       for (int kb = 0; kb < 4 * MT; kb += KTB) {
-        if (kb >= nkt) break;  // uniform: padded gamma' rows only
+        // uniform: padded gamma' rows only (FP64 skips them instead of leaving
+        // the loop: with the exit the compiler left it rolled and moved bu to
+        // scratch)
+        if constexpr (sizeof(T) == 4) {
+          if (kb >= nkt) break;
+        } else if (kb >= nkt) {
+          continue;
+        }
         T sf[KTB][MT];
 #pragma unroll
         for (int k = 0; k < KTB; ++k) {
@@ -585,7 +592,7 @@ hipError_t launch_back_l_tps(const Tables<T> &tb, const ChunkArgs<T> &a, const B
 
 template <typename T, typename Tin, int NCG>
 hipError_t launch_back_l_ncg(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
-  if constexpr (sizeof(Tin) == 8)
+  if constexpr (sizeof(T) == 4 && sizeof(Tin) == 8)
     if (a.psi32) return launch_back_l_tps<T, Tin, float, NCG>(tb, a, br, s);
   return launch_back_l_tps<T, Tin, Tin, NCG>(tb, a, br, s);
 }
@@ -686,19 +693,19 @@ template <typename T, typename Tin>
 hipError_t launch_back(const Tables<T> &tb, const ChunkArgs<T> &a, const BackRange &br, hipStream_t s) {
   // form: streaming (k_back_s, runtime rank loops, high occupancy), batched
   // (k_back_b, compile-time rank tiles, loads issued per source in batches)
-  // or LDS-staged (k_back_l, FP32, while its LDS leaves room for two
-  // workgroups per CU).  Default: LDS-staged where it applies, else batched
+  // or LDS-staged (k_back_l: FP32 while its LDS leaves room for two
+  // workgroups per CU, FP64 while it fits one).  Default: LDS-staged where
+  // it applies, else batched
   const int nbt = a.D.nb1 >> 4;
-  // (FP64 orbitals read as they are, without an FP32 copy, only up to six b tiles: registers)
-  const bool psi64_direct = sizeof(Tin) == 8 && !a.psi32;
-  const bool lds_ok = sizeof(T) == 4 && nbt <= (psi64_direct ? 6 : 8) &&
-                      back_l_lds(a.D.MT1, nbt, sizeof(T)) <= 80 * 1024;
+  // (FP32 compute reads FP64 orbitals as they are, without an FP32 copy, only
+  // up to six b tiles: registers)
+  const bool psi64_direct = sizeof(T) == 4 && sizeof(Tin) == 8 && !a.psi32;
+  const bool lds_ok = nbt <= (psi64_direct ? 6 : 8) &&
+                      back_l_lds(a.D.MT1, nbt, sizeof(T)) <= (sizeof(T) == 4 ? 80 : 160) * 1024;
   const int form = a.back_form == 3 && !lds_ok ? 2 : a.back_form ? a.back_form : (lds_ok ? 3 : 2);
   if (form == 3) {
-    if constexpr (sizeof(T) == 4) {
-      const int ncg = a.back_ncg ? a.back_ncg : 1;
-      return ncg == 2 ? launch_back_l_ncg<T, Tin, 2>(tb, a, br, s) : launch_back_l_ncg<T, Tin, 1>(tb, a, br, s);
-    }
+    const int ncg = a.back_ncg ? a.back_ncg : 1;
+    return ncg == 2 ? launch_back_l_ncg<T, Tin, 2>(tb, a, br, s) : launch_back_l_ncg<T, Tin, 1>(tb, a, br, s);
   }
   // two c-tiles per wavefront while the b-tile accumulators are few
   const int ncg = a.back_ncg ? a.back_ncg : (nbt <= 4 ? 2 : 1);

@@ -3,7 +3,9 @@ the same products in the same order, so in FP32 compute every form and
 c-tile count must give bitwise the same Vx psi and E_x as the default, at
 two to eight b tiles, one to three rank tiles, FP32 and FP64 orbitals (with
 and without the FP32 copy of the orbitals), symmetric and block mode.  The
-default itself is checked against the FP64 path."""
+default itself is checked against the FP64 path.  FP64 compute: the same
+bitwise agreement of the three forms (its default is the LDS-staged form
+where its LDS fits one workgroup per CU)."""
 import json
 
 import pytest
@@ -31,13 +33,13 @@ def ctx():
     c.close()
 
 
-def forced(ctx, sysm, psi, form, ncg, key_path, **kw):
+def forced(ctx, sysm, psi, form, ncg, key_path, compute="f32", **kw):
     """Apply with the back form forced through the launch-shape cache."""
     key = next(iter(json.loads(key_path.read_text())))
     ent = dict(ngs_mul=1, proj_gt=4, back_ncg=ncg, grid_cap=2048, back_form=form)
     key_path.write_text(json.dumps({key: ent}))
     assert txe.tune_load(ctx, key_path) == 1
-    out = txe.apply(ctx, sysm, psi, compute="f32", **kw)
+    out = txe.apply(ctx, sysm, psi, compute=compute, **kw)
     torch.cuda.synchronize()
     return out
 
@@ -77,6 +79,31 @@ def test_back_forms_bitwise(ctx, case, psi_dtype, tmp_path, monkeypatch):
                         vd, ed = v, e
                     assert torch.equal(v, vd) and float(e) == float(ed)
                 monkeypatch.delenv("TXE_TEST_MAX_WORKSPACE")
+            sysm.close()
+        finally:
+            c2.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"n{c[0]}r{c[3]}")
+def test_back_forms_bitwise_f64(case, tmp_path):
+    n, L, N, r, K = case
+    s = W.make_system(f"bf{n}", n, L, N, 3, (0.4, 2.5), r, K, seed=900 + n, box=0.4 * L)
+    psi = s.psi.cuda()
+    for mode in ("symmetric", "block"):
+        kw = dict(symmetric=True) if mode == "symmetric" else dict(symmetric=False, i0=1, Ni=N - 1)
+        c2 = txe.Context(0)
+        try:
+            sysm = txe.System.from_workload(c2, s)
+            v0, e0, _ = txe.apply(c2, sysm, psi, compute="f64", **kw)
+            torch.cuda.synchronize()
+            print(f"[n{n} r{r} f64 {mode}] E_x {float(e0):.15e}", flush=True)
+            txe.tune(c2, sysm, psi, "f64", reps=1, **kw)
+            path = tmp_path / f"k64_{mode}.json"
+            txe.tune_save(c2, path)
+            for form, ncg in FORMS:
+                v, e, _ = forced(c2, sysm, psi, form, ncg, path, compute="f64", **kw)
+                assert torch.equal(v, v0), f"form {form} ncg {ncg}: Vx psi differs"
+                assert float(e) == float(e0), f"form {form} ncg {ncg}: E_x differs"
             sysm.close()
         finally:
             c2.close()
