@@ -329,8 +329,9 @@ txe_status txe_graph_destroy(txe_graph *graph);
  * 0 = chosen by size); knobs[3] workgroups of the persistent projection and
  * back-projection kernels; knobs[4] form of the back-projection kernel (1
  * streaming, 2 batched loads, 3 each source's slab staged in LDS per
- * workgroup, FP32 compute only; 0 = default: 3 where its LDS leaves room for
- * two workgroups per CU, else 2).  Results do not depend on
+ * workgroup; 0 = default: 3 where its LDS leaves room for two workgroups per
+ * CU in FP32 compute, or fits one (160 KiB) in FP64, else 2; 3 falls back
+ * to 2 where it does not fit).  Results do not depend on
  * knobs[1..4]; knobs[0] changes the summation order of the pair energies
  * only.
  *
