@@ -17,13 +17,14 @@ namespace txe {
 //             fragments hoisted out of the source loop, each source's S1
 //             rows loaded in batches ahead of their MFMAs (clamped addresses
 //             and selects instead of branches); fewer, busier wavefronts
-//   k_back_l  LDS-staged (FP32): the four wavefronts of a workgroup share the
+//   k_back_l  LDS-staged: the four wavefronts of a workgroup share the
 //             target and slab a and take four c-tile groups; each source's
 //             S1 slab is loaded once per workgroup in 16-byte pieces one
 //             source ahead and read from LDS, the chained U1 fragments are
 //             staged in LDS once per workgroup, and every b tile is done in
-//             one pass, so X is computed once per source.  Same products in
-//             the same order as k_back_b.
+//             one pass, so X is computed once per source (FP32: two
+//             workgroups per CU; FP64: one, its LDS up to 160 KiB).  Same
+//             products in the same order as k_back_b.
 // -------------------------------------------------------------------------------------
 template <typename T, typename Tin, int NBT, int NCG, bool LDS_TAB>
 __global__ __launch_bounds__(256) void k_back_s(const T *__restrict__ S1, const Tin *__restrict__ psi, Dims D,
