@@ -62,9 +62,11 @@ q-orthonormal; the kernel sum evaluated in the Tucker core and then
 back-projected (phi = P C P rho).  Per-pair bases (O8): the truncation runs
 modes 0, 1, 2 in that order, in the W inner product (on uniform meshes the
 nodal Frobenius norm the paper measures its error in, up to a constant
-factor); O8 is pinned by its own identities (tests/test_oracle_sthosvd.py).  Parity of the Tucker-truncated
-(r < n) result against anything but this oracle is unpinned (no closed form
-exists for it); the full-rank case is pinned to a dense 3-D kernel apply.
+factor); O8 is pinned by its own identities (tests/test_oracle_sthosvd.py).  The Tucker-truncated
+(r < n) result is pinned by brute force: on tiny graded grids it equals the
+dense operator P C P (P the W-orthogonal projector onto the span of the
+tensor-product bases, C the separable kernel) applied to rho; the full-rank
+case is pinned to a dense 3-D kernel apply.
 """
 from __future__ import annotations
 

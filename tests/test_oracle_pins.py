@@ -126,6 +126,57 @@ def test_non_cubic_full_rank_equals_dense_kernel():
     assert np.abs(phi - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+def _dense_projected_operator(st):
+    """P C P as dense (n0 n1 n2)^2 matrices, from Kronecker products: P_d =
+    U_d U_d^T diag(q_d) is the W-orthogonal projector onto span(U_d) (the
+    Tucker space of the shared bases), C = sum_k w_k C_k^0 (x) C_k^1 (x) C_k^2
+    the separable kernel on the grid, C-ordered (a, b, c) -> (a n1 + b) n2 + c."""
+    P = [st.U[d] @ st.U[d].T @ np.diag(st.q[d]) for d in range(3)]
+    Pd = np.kron(P[0], np.kron(P[1], P[2]))
+    n = Pd.shape[0]
+    Cd = np.zeros((n, n))
+    for k in range(len(st.w)):
+        Cd += st.w[k] * np.kron(st.C[0][k], np.kron(st.C[1][k], st.C[2][k]))
+    return Pd @ Cd @ Pd
+
+
+def test_truncated_rank_equals_dense_projected_kernel():
+    """O2/O3 at r < n: the core-space evaluation equals the projected
+    operator P C P applied to rho as a dense matrix (brute force on a tiny
+    non-cubic graded grid with anisotropic ranks: non-uniform weights make
+    C_k^d and Chat_k^d unsymmetric, so a transposed operand shows); e_ij =
+    <rho, P C P rho>_W; Vx psi and E_x of apply() follow from the same dense
+    operator pair by pair."""
+    g = W.graded_grid((5, 6, 7), (3.0, 3.5, 4.0), stretch=1.2)
+    psi, _ = W.make_orbitals(g, 3, 3, (0.5, 2.0), seed=11, box=1.0)
+    Ufull = W.full_rank_bases(g, seed=13)
+    U = [Ufull[0][:, :3], Ufull[1][:, :4], Ufull[2][:, :5]]  # still q-orthonormal
+    w, a = W.exp_sum(5)
+    st = O.Setup(g.x, g.q, U, w, a)
+    A = _dense_projected_operator(st)
+    wv = np.kron(g.q[0], np.kron(g.q[1], g.q[2]))
+    p = psi.numpy()
+    N = p.shape[0]
+    vx_ref = np.zeros_like(p)
+    ex_ref = 0.0
+    for i in range(N):
+        for j in range(N):
+            rho = (p[i] * p[j]).ravel()
+            phi_ref = A @ rho
+            e_ref = float(np.sum(wv * rho * phi_ref))
+            phi, e, _, _ = O.pair(p[i], p[j], st)
+            assert np.abs(phi.ravel() - phi_ref).max() <= 1e-12 * np.abs(phi_ref).max()
+            assert abs(e - e_ref) <= 1e-12 * abs(e_ref)
+            vx_ref[i] -= p[j] * phi_ref.reshape(p[i].shape)
+            ex_ref -= 0.5 * e_ref
+    # the projection changes the result (so the test sees the truncation)
+    full = O.dense_kernel_apply(p[0] * p[1], st.w, st.C).ravel()
+    assert np.abs(A @ (p[0] * p[1]).ravel() - full).max() > 1e-3 * np.abs(full).max()
+    vx, ex = O.apply(p, st)
+    assert abs(ex - ex_ref) <= 1e-12 * abs(ex_ref)
+    assert np.abs(vx - vx_ref).max() <= 1e-12 * np.abs(vx_ref).max()
+
+
 # ---------------------------------------------------------------------------------------
 # whole discretisation: a single s-Gaussian density has a closed-form
 # exp-sum Coulomb energy; the grid result converges to it at O(h^2)
