@@ -62,7 +62,7 @@ typedef enum {
   TXE_ERR_SHAPE = 2,        /* inconsistent sizes                                           */
   TXE_ERR_NOMEM = 3,        /* device allocation failed or the workspace limit is exceeded  */
   TXE_ERR_DEVICE = 4,       /* a HIP call failed (sticky on the context)                    */
-  TXE_ERR_UNSUPPORTED = 5,  /* valid request that this build does not implement             */
+  TXE_ERR_UNSUPPORTED = 5,  /* valid request that the library does not implement            */
   TXE_ERR_STATE = 6         /* call not allowed in the current state (e.g. would allocate   */
                             /* while the stream is being captured)                          */
 } txe_status;
